@@ -1,0 +1,212 @@
+"""ctypes front end of the plain FP64 CPU oracle (``nlte_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke entry point and the benchmark's
+CPU-baseline leg are its only users.  The HIP library never imports or links it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nlte_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_up = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE order, no contraction, OpenMP over points)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        L.or_create.restype = C.c_void_p
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_set_species.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_double, C.c_int, _ip, _ip,
+                                     _dp, C.c_int, _ip, _ip, C.c_int, _dp, _dp]
+        L.or_set_model.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int, _ip,
+                                   C.c_void_p]
+        L.or_set_rays.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.or_set_quadrature.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.or_set_params.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_int]
+        L.or_n_pairs.argtypes = [C.c_void_p]
+        L.or_line_width_speed.argtypes = [C.c_void_p, _dp]
+        L.or_planck.argtypes = [C.c_double, C.c_double]
+        L.or_planck.restype = C.c_double
+        L.or_coll_rates.argtypes = [C.c_void_p, C.c_int64, _dp, _dp]
+        L.or_lte.argtypes = [C.c_void_p, _dp]
+        L.or_walk.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+        L.or_pair_nodes.argtypes = [C.c_void_p, _dp, C.c_int64, C.c_int, C.c_int, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(C.c_int)]
+        L.or_solve_ray.argtypes = [C.c_int, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int,
+                                   C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.c_void_p]
+        L.or_formal_solve.argtypes = [C.c_void_p, _dp, C.c_int64, C.c_void_p, _dp, _dp, _dp]
+        L.or_stateq.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_void_p]
+        L.or_rel_change.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(C.c_double)]
+        L.or_rel_change.restype = C.c_double
+        L.or_run_ali.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int, C.c_double, _dp]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def planck(nu: float, T: float) -> float:
+    return lib().or_planck(nu, T)
+
+
+def solve_ray(z, chi, S, I_lo, I_hi, o, tau_floor=1e-30, want_all=False):
+    """One Feautrier solve on explicit nodes: returns (u_o, Lambda_oo, ueff_o[, u_all])."""
+    z, chi, S = _f64(z), _f64(chi), _f64(S)
+    N = z.shape[0]
+    u, lam, ue = C.c_double(), C.c_double(), C.c_double()
+    ua = np.zeros(N) if want_all else None
+    lib().or_solve_ray(N, z, chi, S, I_lo, I_hi, int(o), tau_floor, C.byref(u), C.byref(lam),
+                       C.byref(ue), ua.ctypes.data if want_all else None)
+    if want_all:
+        return u.value, lam.value, ue.value, ua
+    return u.value, lam.value, ue.value
+
+
+class Oracle:
+    """One model + species + rays + quadrature, as the oracle sees it."""
+
+    def __init__(self, model, species, rays, quad_x, quad_w, t_cmb=2.725, f_sub=0.25,
+                 tau_floor=1e-30, use_alo=True):
+        L = lib()
+        self._L = L
+        self.c = L.or_create()
+        sp = species
+        self.species = sp
+        self.n_lev = sp.n_lev
+        self.n_lines = sp.n_lines
+        self._keep = []
+        L.or_set_species(self.c, sp.n_lev, _f64(sp.energy), _f64(sp.weight), float(sp.mass),
+                         sp.n_lines, _i32(sp.line_up), _i32(sp.line_lo), _f64(sp.line_A),
+                         int(sp.coll_up.shape[0]), _i32(sp.coll_up), _i32(sp.coll_lo),
+                         int(sp.coll_T.shape[0]), _f64(sp.coll_T), _f64(sp.coll_K))
+        m = model
+        self.P = m.n_points
+        bnd = None
+        if m.boundary is not None:
+            bnd = np.ascontiguousarray(m.boundary, dtype=np.uint8)
+            self._keep.append(bnd)
+        L.or_set_model(self.c, self.P, _f64(m.pos), _f64(m.vel), _f64(m.n_h2), _f64(m.temperature),
+                       _f64(m.v_turb), _f64(m.abundance), int(m.nbr.shape[1]), _i32(m.nbr),
+                       bnd.ctypes.data if bnd is not None else None)
+        npairs = L.or_set_rays(self.c, int(rays.shape[0]), _f64(rays))
+        if npairs < 0:
+            raise ValueError("ray set is not point-symmetric")
+        self.n_rays = int(rays.shape[0])
+        self.n_pairs = npairs
+        L.or_set_quadrature(self.c, int(quad_x.shape[0]), _f64(quad_x), _f64(quad_w))
+        L.or_set_params(self.c, t_cmb, f_sub, tau_floor, 1 if use_alo else 0)
+
+    def __del__(self):
+        try:
+            self._L.or_destroy(self.c)
+        except Exception:
+            pass
+
+    def line_width_speed(self):
+        out = np.zeros(self.P)
+        self._L.or_line_width_speed(self.c, out)
+        return out
+
+    def coll_rates(self, p):
+        n = int(self.species.coll_up.shape[0])
+        a, b = np.zeros(n), np.zeros(n)
+        self._L.or_coll_rates(self.c, int(p), a, b)
+        return a, b
+
+    def lte(self):
+        out = np.zeros((self.P, self.n_lev))
+        self._L.or_lte(self.c, out)
+        return out
+
+    def walk(self, O, ray):
+        n = self._L.or_walk(self.c, int(O), int(ray), None, None, 0)
+        cells = np.zeros(max(n, 1), dtype=np.int32)
+        Z = np.zeros(max(n, 1))
+        self._L.or_walk(self.c, int(O), int(ray), cells.ctypes.data, Z.ctypes.data, n)
+        return cells[:n].copy(), Z[:n].copy()
+
+    def pair_nodes(self, pops, O, pair):
+        pops = _f64(pops)
+        io = C.c_int()
+        N = self._L.or_pair_nodes(self.c, pops, int(O), int(pair), 0, None, None, None, None, None,
+                                  C.byref(io))
+        z, a, b = np.zeros(N), np.zeros(N), np.zeros(N)
+        kap, S = np.zeros((N, self.n_lines)), np.zeros((N, self.n_lines))
+        self._L.or_pair_nodes(self.c, pops, int(O), int(pair), N, z.ctypes.data, a.ctypes.data,
+                              b.ctypes.data, kap.ctypes.data, S.ctypes.data, C.byref(io))
+        return dict(z=z, a=a, b=b, kappa=kap, S=S, o=io.value)
+
+    def formal_solve(self, pops, sel=None):
+        pops = _f64(pops)
+        if sel is None:
+            n = self.P
+            selp = None
+            sel_arr = None
+        else:
+            sel_arr = np.ascontiguousarray(sel, dtype=np.int64)
+            n = sel_arr.shape[0]
+            selp = sel_arr.ctypes.data
+        J = np.zeros((n, self.n_lines))
+        Je = np.zeros((n, self.n_lines))
+        Ls = np.zeros((n, self.n_lines))
+        self._L.or_formal_solve(self.c, pops, n, selp, J, Je, Ls)
+        return J, Je, Ls
+
+    def stateq(self, pops_old, J, Jeff, L):
+        out = np.zeros((self.P, self.n_lev))
+        flags = np.zeros(self.P, dtype=np.uint8)
+        self._L.or_stateq(self.c, _f64(pops_old), _f64(J), _f64(Jeff), _f64(L), out,
+                          flags.ctypes.data)
+        return out, flags
+
+    def rel_change(self, old, new):
+        mean = C.c_double()
+        mx = self._L.or_rel_change(self.c, _f64(old), _f64(new), C.byref(mean))
+        return mx, mean.value
+
+    def run_ali(self, pops_init=None, max_iter=50, tol=1e-4):
+        out = np.zeros((self.P, self.n_lev))
+        ch = np.zeros(max_iter)
+        pi = None
+        if pops_init is not None:
+            pi = _f64(pops_init)
+        it = self._L.or_run_ali(self.c, pi.ctypes.data if pi is not None else None, out, max_iter, tol, ch)
+        return out, ch[:it].copy()
+
+
+def from_workload(w, **kw) -> Oracle:
+    return Oracle(w.model, w.species, w.rays, w.quad_x, w.quad_w, t_cmb=w.t_cmb, f_sub=w.f_sub, **kw)
