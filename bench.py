@@ -1,0 +1,221 @@
+"""Benchmark of the ALI hot path on one MI355X.
+
+A step is one accelerated-Lambda-iteration sweep over the whole model with inputs
+resident in HBM: line coefficients, the ray-pair formal solve with J / L* / Jeff
+accumulation, and the statistical-equilibrium update.  The ray walks are traced once
+before timing (they depend only on the geometry).
+
+Workload (default): outflow5 -- 50,000 points in a sphere, 48 HEALPix rays, 5-level
+linear rotor (4 lines x 31 frequencies), radial outflow of 15 km/s.
+
+Prints one JSON line.  `value` is formal-solve throughput in point*ray*frequency per
+second of step time; `roofline` covers the formal-solve kernel (VALU bound, FP64 flops
+per node-frequency step; see the design doc for the count); `cpu_baseline` is the FP64 CPU
+oracle timed on a bounded sample of origin points on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 flops of one elimination step at one frequency (profile, optical depth,
+# Rybicki-Hummer step; exp and the reciprocal count one each); velocity sub-step nodes
+# add 6 for the linear interpolation of x, kappa and S.
+FLOPS_PER_STEP = 17
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    p = os.path.join(ROOT, "paper_1912_08445_amd", "csrc", "formal_solve.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(workload_name, precision, launch_steps):
+    """HBM bytes per formal-solve launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"formal_solve_{workload_name}_{precision}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_sha") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, target_s=15.0):
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    o = oracle.from_workload(w)
+    pops = o.lte()
+    rng = np.random.default_rng(12345)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    probe = rng.choice(w.n_points, max(threads, 8), replace=False)
+    t0 = time.perf_counter()
+    o.formal_solve(pops, probe)
+    dt = time.perf_counter() - t0
+    n = int(min(w.n_points, max(len(probe), len(probe) * target_s / max(dt, 1e-3))))
+    sel = rng.choice(w.n_points, n, replace=False)
+    t0 = time.perf_counter()
+    o.formal_solve(pops, sel)
+    dt = time.perf_counter() - t0
+    units = n * w.rays.shape[0] * w.species.n_lines * w.quad_x.shape[0]
+    return {"value": units / dt, "unit": "point*ray*freq/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} random origin points of {w.n_points} (all {w.rays.shape[0]} rays, "
+                      f"{w.species.n_lines} lines x {w.quad_x.shape[0]} frequencies), LTE "
+                      f"populations, formal solve only, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="outflow5", choices=["outflow5", "sphere2", "disc10"])
+    ap.add_argument("--points", type=int, default=None, help="override the point count")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ali", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method shards by "
+              "origin point across GPUs but this build measures a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_08445_amd.binding import Solver
+    from synth import configs
+
+    make = {"outflow5": configs.outflow5, "sphere2": configs.sphere2, "disc10": configs.disc10}[args.workload]
+    t0 = time.perf_counter()
+    w = make() if args.points is None else make(n_points=args.points)
+    log(f"workload {w.name}: {w.n_points} points, {w.rays.shape[0]} rays, {w.species.n_lines} lines x "
+        f"{w.quad_x.shape[0]} freqs ({time.perf_counter() - t0:.1f} s to generate)")
+
+    s = Solver(0)
+    t0 = time.perf_counter()
+    s.setup(w, precision=args.precision)
+    total_cells, max_len, steps_per_freq = s.trace_stats()
+    log(f"traced in {time.perf_counter() - t0:.2f} s: {total_cells} cells, longest ray {max_len}, "
+        f"{steps_per_freq} elimination steps per frequency")
+
+    dev = torch.device("cuda:0")
+    P, nlev, nl = w.n_points, w.species.n_lev, w.species.n_lines
+    pops = torch.empty((P, nlev), dtype=torch.float64, device=dev)
+    new = torch.empty_like(pops)
+    J, Je, L = [torch.empty((P, nl), dtype=torch.float64, device=dev) for _ in range(3)]
+    s.lte_dev(pops)
+    torch.cuda.synchronize()
+
+    bufs = [pops, new]
+
+    def step():
+        # one ALI iteration: populations bufs[0] -> bufs[1], then swap
+        s.formal_solve_dev(bufs[0], J, Je, L)
+        s.stateq_dev(bufs[0], J, Je, L, bufs[1])
+        bufs.reverse()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    # timed region: HIP events on torch's current stream, which is the stream every
+    # library call above is launched on; per-kernel HIP events inside the library
+    s.set_params(profile=1)
+    s.reset_kernel_stats()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    s.set_params(profile=0)
+    ms_step = ms_total / args.steps
+    k_ms, k_n = s.kernel_stats("formal_solve")
+    k_avg = k_ms / max(k_n, 1)
+    lc_ms, _ = s.kernel_stats("line_coef")
+    se_ms, _ = s.kernel_stats("stateq")
+    log(f"step {ms_step:.3f} ms; formal_solve kernel {k_avg:.3f} ms avg over {k_n} launches; "
+        f"line_coef {lc_ms / max(k_n, 1):.3f} ms; stateq {se_ms / max(k_n, 1):.3f} ms")
+
+    units = P * w.rays.shape[0] * nl * w.quad_x.shape[0]
+    value = units / (ms_step * 1e-3)
+    node_freq = steps_per_freq * nl * w.quad_x.shape[0]
+    flops = node_freq * FLOPS_PER_STEP
+    achieved = flops / (k_avg * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": traffic_from_profile(w.name, args.precision, node_freq),
+            "kernel": "k_formal_solve", "kernel_ms": k_avg, "node_freq_per_launch": node_freq,
+            "flops_per_node_freq": FLOPS_PER_STEP}
+
+    ali = None
+    if not args.no_ali:
+        s.set_params(tol=1e-4, max_iter=200)
+        out = torch.empty_like(pops)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = s.run_ali_dev(None, out)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ali = {"iterations": rep["iterations"], "converged": rep["converged"], "wall_s": wall,
+               "final_max_change": rep["max_change"][-1] if rep["max_change"] else None,
+               "tol": 1e-4, "start": "LTE"}
+        log(f"ALI to 1e-4: {rep['iterations']} iterations, {wall:.2f} s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(w)
+        log(f"cpu baseline {cpu['value']:.3e} {cpu['unit']} on {cpu['cores']} threads")
+
+    desc = (f"{w.name}: {P} points, {w.rays.shape[0]} HEALPix rays, {nl} lines x "
+            f"{w.quad_x.shape[0]} frequencies, {nlev} levels")
+    line = {
+        "metric": "formal-solve (point*ray*freq)/s; ALI wall time to 1e-4 convergence vs FP64",
+        "value": value,
+        "unit": "point*ray*freq/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "points": P, "rays": int(w.rays.shape[0]), "lines": nl,
+                   "frequencies": int(w.quad_x.shape[0]), "levels": nlev,
+                   "precision": args.precision, "cells_cached": total_cells,
+                   "node_freq_per_sweep": node_freq},
+        "node_freq_per_s": node_freq / (ms_step * 1e-3),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "ali": ali,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

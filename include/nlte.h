@@ -1,0 +1,225 @@
+/*
+ * nlte.h -- C ABI of the MI355X (gfx950) non-LTE line radiative-transfer library.
+ *
+ * The library implements the hot path of the accelerated Lambda iteration (ALI) of
+ * De Ceuster et al., "Magritte I: non-LTE atomic and molecular line modelling":
+ * rays traced over a point cloud with nearest-neighbour lists (Sec. 3.2), the
+ * second-order (Feautrier) transfer equation solved on every antipodal ray pair at
+ * every Doppler-shifted line frequency (Sec. 3.3), accumulation of the mean intensity
+ * J and of the diagonal approximate Lambda operator (Sec. 2.2.1, 3.4), and the
+ * per-point statistical-equilibrium update that consumes them (Eq. ourALI).
+ *
+ * Conventions
+ *   - CGS units; arrays are dense and row-major; indices are 0-based.
+ *   - The caller owns every buffer.  The library copies what it keeps and never
+ *     retains or frees a caller pointer.  Host-pointer calls copy in and out and return
+ *     when the results are in the caller's buffers.  *_dev calls take device pointers
+ *     and a hipStream_t (passed as void*, NULL = the context's own stream); they only
+ *     enqueue work, so the caller synchronises that stream before reading results.
+ *   - Return codes: NLTE_OK (0); errors are negative, warnings positive.  After any
+ *     non-zero code nlte_last_error() describes it.  No C++ exception crosses the ABI.
+ *   - A context is bound to one HIP device and is not thread-safe: use one context per
+ *     host thread.  Calls must follow the order create -> set_species -> set_model(s)
+ *     -> set_rays -> set_quadrature -> [set_params] -> trace -> compute calls;
+ *     NLTE_E_STATE reports a call made before its prerequisites.
+ */
+#ifndef NLTE_H
+#define NLTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nlte_ctx nlte_ctx;
+typedef int nlte_status;
+
+#define NLTE_OK 0
+#define NLTE_E_INVALID_ARG (-1) /* an argument is out of range, non-finite or inconsistent */
+#define NLTE_E_STATE (-2)       /* a prerequisite call is missing */
+#define NLTE_E_OOM (-3)         /* device or host allocation failed */
+#define NLTE_E_HIP (-4)         /* a HIP runtime call failed */
+#define NLTE_W_NOT_CONVERGED 1  /* ALI stopped at max_iter above tol */
+#define NLTE_W_NONPHYSICAL 2    /* some points fell back or kept their old populations */
+
+/* Arithmetic used by the formal solve. */
+#define NLTE_PREC_FP64 0      /* every step in FP64 */
+#define NLTE_PREC_FP32_BULK 1 /* FP32 profile, opacity, optical depth, source function and
+                                 J accumulation; FP64 Feautrier elimination and stat-eq */
+
+typedef struct {
+    double t_cmb;     /* boundary (CMB) temperature [K]; incoming intensity B_nu(t_cmb) at the
+                         line-centre frequency on both ends of every ray pair (Sec. 4.1). 2.725 */
+    double f_sub;     /* velocity sub-step fraction: a segment whose projected velocity
+                         changes by more than f_sub times the smaller line-width speed of its
+                         two ends is split into equal parts (Sec. 3.1.1, 3.2).  0.25 */
+    double tol;       /* ALI stops when the maximum relative population change is below tol */
+    int max_iter;     /* ALI iteration cap */
+    int use_alo;      /* 1: diagonal ALO (Sec. 3.4); 0: plain Lambda iteration */
+    int precision;    /* NLTE_PREC_* */
+    int profile;      /* 1: time every kernel with HIP events (nlte_kernel_stats) */
+    double tau_floor; /* lower bound on every optical-depth step (zero-opacity segments in
+                         the far line wings).  1e-30 */
+} nlte_params;
+
+/* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0. */
+void nlte_default_params(nlte_params *p);
+
+typedef struct {
+    int iterations;          /* ALI iterations performed */
+    int converged;           /* 1 if the last change was below tol */
+    double max_change[1024]; /* per-iteration max relative change (first min(iters,1024)) */
+    double mean_change[1024];/* per-iteration mean relative change over the same entries */
+    int64_t n_fallback;      /* stat-eq solves that fell back to plain Lambda (last iteration) */
+    int64_t n_kept;          /* points that kept their previous populations (last iteration) */
+    int64_t n_maser;         /* (point, line) pairs with non-positive opacity (last iteration) */
+    double ms_total;         /* wall time of the iteration loop [ms] */
+} nlte_ali_report;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+nlte_status nlte_create(nlte_ctx **out, int hip_device);
+/* Free the context and every device buffer it owns.  NULL is allowed. */
+void nlte_destroy(nlte_ctx *ctx);
+/* Text of the last error or warning on this context (valid until the next call). */
+const char *nlte_last_error(const nlte_ctx *ctx);
+
+/* ---------------------------------------------------------------- inputs */
+
+/*
+ * Species (Sec. 2.2.1).  n_lev levels with energies E [erg] and statistical weights g;
+ * species mass [g] for the thermal speed sqrt(2kT/m).  n_lines radiative lines
+ * up[l] -> lo[l] (E[up] > E[lo]) with Einstein A_ul [s^-1]; line frequency
+ * nu = (E_up - E_lo)/h, B_ul = A_ul c^2/(2 h nu^3), B_lu = (g_up/g_lo) B_ul.
+ * n_coll collisional pairs c_up[c] -> c_lo[c] with H2 de-excitation coefficients
+ * K_ul[c][t] [cm^3 s^-1] tabulated at n_T strictly increasing temperatures T_K[t],
+ * interpolated linearly in T and clamped at the ends; excitation follows from
+ * detailed balance C_lu = C_ul (g_u/g_l) exp(-(E_u - E_l)/kT).
+ * Limits: 2 <= n_lev <= 16, 1 <= n_lines <= 32, 0 <= n_coll <= 256, 1 <= n_T <= 256.
+ */
+nlte_status nlte_set_species(nlte_ctx *ctx, int n_lev, const double *E, const double *g,
+                             double mass, int n_lines, const int32_t *up, const int32_t *lo,
+                             const double *A_ul, int n_coll, const int32_t *c_up,
+                             const int32_t *c_lo, int n_T, const double *T_K,
+                             const double *K_ul);
+
+/*
+ * Model(s): the point cloud with nearest-neighbour lists (Sec. 3.1.1).  n_models models
+ * are stored back to back; model m owns points offsets[m] .. offsets[m+1]-1, with
+ * offsets [n_models+1] required, offsets[0] = 0 and P = offsets[n_models] (one model:
+ * {0, P}).  Must follow nlte_set_species (which invalidates a previous model, since the
+ * line widths depend on the species mass).  Per point: pos [P][3] cm, vel [P][3] cm/s,
+ * n_h2 [P] cm^-3, T [P] K, v_turb [P] cm/s, abundance [P] (species per H2);
+ * nbr [P][k] neighbour indices local to the point's model, -1 = unused slot (no self
+ * references).  boundary (nullable) [P]: 1 marks points where rays end (Sec. 3.1.1).
+ * Invalidates a previous trace.
+ */
+nlte_status nlte_set_models(nlte_ctx *ctx, int n_models, const int64_t *offsets,
+                            const double *pos, const double *vel, const double *n_h2,
+                            const double *T, const double *v_turb, const double *abundance,
+                            int k, const int32_t *nbr, const uint8_t *boundary);
+
+/*
+ * Ray directions (Sec. 3.1.3): n_rays unit vectors [n][3] forming antipodal pairs
+ * (every direction's negative is in the set within 1e-12).  The pair representative is
+ * the lower index; n_rays <= 1024.  Invalidates a previous trace.
+ */
+nlte_status nlte_set_rays(nlte_ctx *ctx, int n_rays, const double *dir);
+
+/*
+ * Frequency quadrature (Sec. 3.1.2): offsets x[n] in units of the local line width and
+ * weights w[n] against the normalised profile, symmetric (x[n] = -x[N-1-n],
+ * w[n] = w[N-1-n] within 1e-12) with sum w = 1 within 1e-12.  1 <= n_q <= 256.
+ */
+nlte_status nlte_set_quadrature(nlte_ctx *ctx, int n_q, const double *x, const double *w);
+
+nlte_status nlte_set_params(nlte_ctx *ctx, const nlte_params *p);
+
+/* ---------------------------------------------------------------- ray walk */
+
+/*
+ * Trace every (point, ray) once (Sec. 3.2): from the current cell step to the neighbour
+ * whose projection on the ray lies farther than the current one and which is closest
+ * to the line through the origin point; stop when no such neighbour exists or at a
+ * flagged boundary point.  Exact distance ties go to the lower point index.  The cell
+ * lists are cached on the device for all later sweeps.
+ */
+nlte_status nlte_trace(nlte_ctx *ctx);
+
+/* Cells met by ray `ray` from global point `point`, nearest first.  Copies up to cap
+ * indices (model-local, like nbr) into cells; *len receives the full length. */
+nlte_status nlte_get_ray(nlte_ctx *ctx, int64_t point, int ray, int32_t *cells, int cap,
+                         int *len);
+
+/* Total cached cells over all (point, ray), the longest ray, and the number of
+ * elimination steps one frequency of one line takes over all half rays (cells plus
+ * velocity sub-steps); any output pointer may be NULL. */
+nlte_status nlte_trace_stats(nlte_ctx *ctx, int64_t *total_cells, int *max_len,
+                             int64_t *total_steps);
+
+/* Per-point line-width speed sqrt(2kT/m + v_turb^2) [cm/s] as the kernels use it. */
+nlte_status nlte_get_line_width_speed(nlte_ctx *ctx, double *vw);
+
+/* ---------------------------------------------------------------- one ALI step */
+
+/* Boltzmann populations at the local temperature, scaled to abundance * n_h2.
+ * pops [P][n_lev]. */
+nlte_status nlte_lte(nlte_ctx *ctx, double *pops);
+nlte_status nlte_lte_dev(nlte_ctx *ctx, double *d_pops, void *stream);
+
+/*
+ * One formal-solve sweep with populations pops [P][n_lev]:
+ *   J    [P][n_lines]  mean intensity in the line (Eq. meanIntensity, ray average of
+ *                      Sec. 3.1.3, u pairs I(n, x) with I(-n, -x)),
+ *   Jeff [P][n_lines]  J - L*[S], the part of J not produced by the point's own source
+ *                      function (Eq. ourJeff),
+ *   Lstar[P][n_lines]  diagonal of the line-averaged Lambda operator (Eq. ALO).
+ */
+nlte_status nlte_formal_solve(nlte_ctx *ctx, const double *pops, double *J, double *Jeff,
+                              double *Lstar);
+nlte_status nlte_formal_solve_dev(nlte_ctx *ctx, const double *d_pops, double *d_J,
+                                  double *d_Jeff, double *d_Lstar, void *stream);
+
+/*
+ * Statistical equilibrium (Eq. ourALI with the diagonal ALO): per point the rates
+ * u->l = A(1 - L*) + B_ul Jeff + C_ul and l->u = B_lu Jeff + C_lu, the first level's
+ * equation replaced by sum_i n_i = abundance * n_h2, solved by Gaussian elimination
+ * with partial pivoting.  A solution with a non-positive or non-finite population is
+ * redone without the ALO (L* = 0, Jeff = J); if that also fails the point keeps
+ * pops_old (Sec. 6.1).  flags [P] (nullable): 0 ok, 1 fell back, 2 kept old.
+ * With use_alo = 0 the plain Lambda-iteration rates are used directly.
+ */
+nlte_status nlte_stateq(nlte_ctx *ctx, const double *pops_old, const double *J,
+                        const double *Jeff, const double *Lstar, double *pops_new,
+                        uint8_t *flags);
+nlte_status nlte_stateq_dev(nlte_ctx *ctx, const double *d_pops_old, const double *d_J,
+                            const double *d_Jeff, const double *d_Lstar, double *d_pops_new,
+                            uint8_t *d_flags, void *stream);
+
+/* ---------------------------------------------------------------- ALI */
+
+/*
+ * Accelerated Lambda iteration (Sec. 2.2.1, 3.4) from pops_init (NULL = LTE): repeat
+ * formal solve + statistical equilibrium until the maximum relative change
+ * |n_new - n_old| / n_new over levels with n_i / (abundance n_h2) > 1e-10 drops below
+ * tol, or max_iter iterations ran.  pops_out [P][n_lev]; rep (nullable) gets the report.
+ * Returns NLTE_W_NOT_CONVERGED if tol was not reached.
+ */
+nlte_status nlte_run_ali(nlte_ctx *ctx, const double *pops_init, double *pops_out,
+                         nlte_ali_report *rep);
+nlte_status nlte_run_ali_dev(nlte_ctx *ctx, const double *d_pops_init, double *d_pops_out,
+                             nlte_ali_report *rep, void *stream);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* With params.profile = 1: accumulated HIP-event time [ms] and launch count of kernel
+ * `name` ("line_coef", "formal_solve", "stateq", "lte", "trace") since the last reset. */
+nlte_status nlte_kernel_stats(nlte_ctx *ctx, const char *name, double *ms, int64_t *launches);
+nlte_status nlte_reset_kernel_stats(nlte_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLTE_H */

@@ -67,6 +67,8 @@ def lib():
         L.or_rel_change.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(C.c_double)]
         L.or_rel_change.restype = C.c_double
         L.or_run_ali.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int, C.c_double, _dp]
+        L.or_walk_all.argtypes = [C.c_void_p, _lp, C.c_void_p]
+        L.or_walk_all.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -158,6 +160,14 @@ class Oracle:
         Z = np.zeros(max(n, 1))
         self._L.or_walk(self.c, int(O), int(ray), cells.ctypes.data, Z.ctypes.data, n)
         return cells[:n].copy(), Z[:n].copy()
+
+    def walk_all(self):
+        """CSR of every (point, ray) walk: (offsets [P*n_rays+1], cells)."""
+        off = np.zeros(self.P * self.n_rays + 1, dtype=np.int64)
+        tot = self._L.or_walk_all(self.c, off, None)
+        cells = np.zeros(max(tot, 1), dtype=np.int32)
+        self._L.or_walk_all(self.c, off, cells.ctypes.data)
+        return off, cells[:tot]
 
     def pair_nodes(self, pops, O, pair):
         pops = _f64(pops)

@@ -213,7 +213,7 @@ static double coll_K(const or_ctx *c, int ic, double T)
     if (T <= Tt[0]) return K[0];
     if (T >= Tt[c->n_T - 1]) return K[c->n_T - 1];
     int j = 0;
-    while (!(T < Tt[j + 1])) ++j;
+    while (j + 2 < c->n_T && !(T < Tt[j + 1])) ++j;
     return K[j] + (K[j + 1] - K[j]) * (T - Tt[j]) / (Tt[j + 1] - Tt[j]);
 }
 
@@ -332,7 +332,8 @@ static int n_sub(double f, double s0, double s1, double w0, double w1)
     double ds = fabs(s1 - s0);
     double thr = f * fmin(w0, w1);
     if (!(ds > thr)) return 1;
-    return (int)ceil(ds / thr);
+    double m = ceil(ds / thr);
+    return m < 1048576.0 ? (int)m : 1048576; /* cap of 2^20 sub-intervals per segment */
 }
 
 /*
@@ -716,4 +717,21 @@ int or_run_ali(const or_ctx *c, const double *pops_init, double *pops_out, int m
     }
     free(J); free(Je); free(L); free(nw);
     return it;
+}
+
+/* Every (point, ray) walk in CSR form, rays of a point consecutive: off [P*n_rays+1],
+ * cells [off[P*n_rays]] (pass cells = NULL to get the offsets and the total only). */
+int64_t or_walk_all(const or_ctx *c, int64_t *off, int32_t *cells)
+{
+    int64_t n = c->P * c->n_rays;
+    off[0] = 0;
+    for (int64_t q = 0; q < n; ++q)
+        off[q + 1] = off[q] + or_walk(c, q / c->n_rays, (int)(q % c->n_rays), NULL, NULL, 0);
+    if (cells) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t q = 0; q < n; ++q)
+            or_walk(c, q / c->n_rays, (int)(q % c->n_rays), cells + off[q], NULL,
+                    (int)(off[q + 1] - off[q]));
+    }
+    return off[n];
 }

@@ -1,0 +1,797 @@
+// C ABI of the library (declared in include/nlte.h): input validation, device buffers,
+// the trace pipeline, one ALI step and the ALI loop.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+
+#include "nlte_internal.h"
+
+using namespace nlte;
+
+namespace {
+
+nlte_status fail(nlte_ctx *c, nlte_status code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, NLTE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+template <typename T>
+nlte_status dalloc(nlte_ctx *c, T **p, size_t count)
+{
+    if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, NLTE_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    return NLTE_OK;
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+bool finite_all(const double *a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+hipStream_t pick(nlte_ctx *c, void *stream) { return stream ? (hipStream_t)stream : c->stream; }
+
+// Time a launch with HIP events on its stream when profiling is on.
+template <typename F>
+hipError_t timed(nlte_ctx *c, KernelStat &st, hipStream_t s, F &&launch)
+{
+    if (!c->params.profile) return launch();
+    hipError_t e = hipEventRecord(c->ev0, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(c->ev1, s);
+    if (e != hipSuccess) return e;
+    e = hipEventSynchronize(c->ev1);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    st.ms += ms;
+    st.launches += 1;
+    return e;
+}
+
+nlte_status need(nlte_ctx *c, bool traced)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!c->have_species) return fail(c, NLTE_E_STATE, "nlte_set_species has not been called");
+    if (!c->have_model) return fail(c, NLTE_E_STATE, "nlte_set_models has not been called");
+    if (!c->have_rays) return fail(c, NLTE_E_STATE, "nlte_set_rays has not been called");
+    if (!c->have_quad) return fail(c, NLTE_E_STATE, "nlte_set_quadrature has not been called");
+    if (traced && !c->traced) return fail(c, NLTE_E_STATE, "nlte_trace has not been called");
+    return NLTE_OK;
+}
+
+// Boundary intensity B_nu(t_cmb) at every line-centre frequency.
+nlte_status upload_ibdy(nlte_ctx *c)
+{
+    if (!c->have_species) return NLTE_OK;
+    std::vector<double> ib(c->n_lines);
+    for (int l = 0; l < c->n_lines; ++l) {
+        double nu = c->nu[l];
+        ib[l] = 2.0 * kH * nu * nu * nu / (kC * kC) / expm1(kH * nu / (kKB * c->params.t_cmb));
+    }
+    nlte_status st = dalloc(c, &c->d_ibdy, c->n_lines);
+    if (st) return st;
+    HIPCHK(c, hipMemcpy(c->d_ibdy, ib.data(), sizeof(double) * c->n_lines, hipMemcpyHostToDevice));
+    return NLTE_OK;
+}
+
+// Work buffers sized for the current model and species.
+nlte_status ensure_work(nlte_ctx *c)
+{
+    const int64_t P = c->P;
+    const size_t lcbytes = (size_t)P * c->n_lines * sizeof(double2);
+    nlte_status st;
+    if ((st = dalloc(c, (char **)&c->d_lc, lcbytes))) return st;
+    if ((st = dalloc(c, &c->d_pops_a, (size_t)P * c->n_lev))) return st;
+    if ((st = dalloc(c, &c->d_pops_b, (size_t)P * c->n_lev))) return st;
+    if ((st = dalloc(c, &c->d_J, (size_t)P * c->n_lines))) return st;
+    if ((st = dalloc(c, &c->d_Jeff, (size_t)P * c->n_lines))) return st;
+    if ((st = dalloc(c, &c->d_L, (size_t)P * c->n_lines))) return st;
+    if ((st = dalloc(c, &c->d_flags, (size_t)P))) return st;
+    c->n_partials_cap = stateq_blocks(P);
+    if ((st = dalloc(c, &c->d_partials, (size_t)c->n_partials_cap))) return st;
+    return NLTE_OK;
+}
+
+SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
+{
+    SolveArgs a{};
+    a.cell = c->d_cell;
+    a.lc = c->d_lc;
+    a.roff = c->d_roff;
+    a.rcells = c->d_rcells;
+    a.dir = c->d_dir;
+    a.pair_r = c->d_pair_r;
+    a.anti = c->d_anti;
+    a.qx = c->d_qx;
+    a.qw = c->d_qw;
+    a.ibdy = c->d_ibdy;
+    a.f_sub = c->params.f_sub;
+    a.tau_floor = c->params.tau_floor;
+    a.norm = 2.0 / (double)c->n_rays;
+    a.P = c->P;
+    a.n_rays = c->n_rays;
+    a.n_pairs = c->n_pairs;
+    a.n_q = c->n_q;
+    a.n_lines = c->n_lines;
+    if (c->n_q <= kWave) {
+        a.lines_per_wave = std::min(2, kWave / c->n_q);
+        a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
+        a.fchunks = 1;
+    } else {
+        a.lines_per_wave = 0;
+        a.groups = c->n_lines;
+        a.fchunks = (c->n_q + kWave - 1) / kWave;
+    }
+    a.n_blocks = c->P * a.groups;
+    a.J = J;
+    a.Jeff = Jeff;
+    a.L = L;
+    return a;
+}
+
+nlte_status formal_solve_impl(nlte_ctx *c, const double *d_pops, double *d_J, double *d_Jeff,
+                              double *d_L, hipStream_t s)
+{
+    const int fp32 = c->params.precision == NLTE_PREC_FP32_BULK;
+    HIPCHK(c, timed(c, c->st_line_coef, s, [&] {
+               return launch_line_coef(c->sp, c->d_cell, d_pops, c->P, fp32, c->d_lc, c->d_maser, s);
+           }));
+    SolveArgs a = solve_args(c, d_J, d_Jeff, d_L);
+    HIPCHK(c, timed(c, c->st_formal, s, [&] { return launch_formal_solve(a, fp32, s); }));
+    return NLTE_OK;
+}
+
+nlte_status stateq_impl(nlte_ctx *c, const double *d_old, const double *d_J, const double *d_Jeff,
+                        const double *d_L, double *d_new, uint8_t *d_flags, ConvResult *d_conv,
+                        hipStream_t s)
+{
+    const int64_t nb = stateq_blocks(c->P);
+    HIPCHK(c, timed(c, c->st_stateq, s, [&] {
+               return launch_stateq(c->sp, c->d_cell, c->d_nh2, c->d_T, c->P, c->params.use_alo,
+                                    d_old, d_J, d_Jeff, d_L, d_new, d_flags, c->d_partials, nb, s);
+           }));
+    if (d_conv) HIPCHK(c, launch_conv_final(c->d_partials, nb, d_conv, s));
+    return NLTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nlte_default_params(nlte_params *p)
+{
+    if (!p) return;
+    p->t_cmb = 2.725;
+    p->f_sub = 0.25;
+    p->tol = 1e-4;
+    p->max_iter = 50;
+    p->use_alo = 1;
+    p->precision = NLTE_PREC_FP64;
+    p->profile = 0;
+    p->tau_floor = 1e-30;
+}
+
+nlte_status nlte_create(nlte_ctx **out, int hip_device)
+{
+    if (!out) return NLTE_E_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return NLTE_E_HIP;
+    nlte_ctx *c = new (std::nothrow) nlte_ctx();
+    if (!c) return NLTE_E_OOM;
+    c->device = hip_device;
+    nlte_default_params(&c->params);
+    if (hipSetDevice(hip_device) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipMalloc((void **)&c->d_maser, sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void **)&c->d_conv, sizeof(ConvResult) * 1025) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_conv, sizeof(ConvResult) * 1025, 0) != hipSuccess) {
+        nlte_destroy(c);
+        return NLTE_E_HIP;
+    }
+    *out = c;
+    return NLTE_OK;
+}
+
+void nlte_destroy(nlte_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    dfree(c->d_species_mem);
+    dfree(c->d_cell);
+    dfree(c->d_nh2);
+    dfree(c->d_T);
+    dfree(c->d_nbr);
+    dfree(c->d_bnd);
+    dfree(c->d_dir);
+    dfree(c->d_pair_r);
+    dfree(c->d_anti);
+    dfree(c->d_qx);
+    dfree(c->d_qw);
+    dfree(c->d_ibdy);
+    dfree(c->d_roff);
+    dfree(c->d_rcells);
+    dfree(c->d_lc);
+    dfree(c->d_pops_a);
+    dfree(c->d_pops_b);
+    dfree(c->d_J);
+    dfree(c->d_Jeff);
+    dfree(c->d_L);
+    dfree(c->d_flags);
+    dfree(c->d_partials);
+    dfree(c->d_conv);
+    dfree(c->d_maser);
+    if (c->h_conv) (void)hipHostFree(c->h_conv);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *nlte_last_error(const nlte_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+nlte_status nlte_set_species(nlte_ctx *c, int n_lev, const double *E, const double *g, double mass,
+                             int n_lines, const int32_t *up, const int32_t *lo, const double *A_ul,
+                             int n_coll, const int32_t *c_up, const int32_t *c_lo, int n_T,
+                             const double *T_K, const double *K_ul)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    (void)hipSetDevice(c->device);
+    if (n_lev < 2 || n_lev > kMaxLev) return fail(c, NLTE_E_INVALID_ARG, "n_lev out of [2, 16]");
+    if (n_lines < 1 || n_lines > kMaxLines) return fail(c, NLTE_E_INVALID_ARG, "n_lines out of [1, 32]");
+    if (n_coll < 0 || n_coll > 256) return fail(c, NLTE_E_INVALID_ARG, "n_coll out of [0, 256]");
+    if (n_T < 1 || n_T > 256) return fail(c, NLTE_E_INVALID_ARG, "n_T out of [1, 256]");
+    if (!E || !g || !up || !lo || !A_ul || !T_K || (n_coll > 0 && (!c_up || !c_lo || !K_ul)))
+        return fail(c, NLTE_E_INVALID_ARG, "null species array");
+    if (!(mass > 0.0) || !std::isfinite(mass)) return fail(c, NLTE_E_INVALID_ARG, "mass must be > 0");
+    if (!finite_all(E, n_lev) || !finite_all(g, n_lev) || !finite_all(A_ul, n_lines) ||
+        !finite_all(T_K, n_T) || !finite_all(K_ul, (int64_t)n_coll * n_T))
+        return fail(c, NLTE_E_INVALID_ARG, "non-finite species data");
+    for (int i = 0; i < n_lev; ++i)
+        if (!(g[i] > 0.0)) return fail(c, NLTE_E_INVALID_ARG, "statistical weights must be > 0");
+    for (int l = 0; l < n_lines; ++l) {
+        if (up[l] < 0 || up[l] >= n_lev || lo[l] < 0 || lo[l] >= n_lev || !(E[up[l]] > E[lo[l]]))
+            return fail(c, NLTE_E_INVALID_ARG, "line levels out of range or E_up <= E_lo");
+        if (!(A_ul[l] >= 0.0)) return fail(c, NLTE_E_INVALID_ARG, "negative Einstein A");
+    }
+    for (int i = 0; i < n_coll; ++i)
+        if (c_up[i] < 0 || c_up[i] >= n_lev || c_lo[i] < 0 || c_lo[i] >= n_lev || c_up[i] == c_lo[i])
+            return fail(c, NLTE_E_INVALID_ARG, "collision levels out of range");
+    for (int t = 0; t + 1 < n_T; ++t)
+        if (!(T_K[t + 1] > T_K[t])) return fail(c, NLTE_E_INVALID_ARG, "T table not increasing");
+
+    // packed device layout: ints first, then doubles
+    const int ni = 2 * n_lines + 2 * n_coll;
+    const int nd = 5 * n_lines + 2 * n_lev + n_T + n_coll * n_T;
+    std::vector<int32_t> hi(ni);
+    std::vector<double> hd(nd);
+    c->nu.assign(n_lines, 0.0);
+    for (int l = 0; l < n_lines; ++l) {
+        hi[l] = up[l];
+        hi[n_lines + l] = lo[l];
+        double nu = (E[up[l]] - E[lo[l]]) / kH;
+        c->nu[l] = nu;
+        double Bul = A_ul[l] * kC * kC / (2.0 * kH * nu * nu * nu);
+        hd[l] = A_ul[l];
+        hd[n_lines + l] = nu;
+        hd[2 * n_lines + l] = Bul;
+        hd[3 * n_lines + l] = (g[up[l]] / g[lo[l]]) * Bul;
+        hd[4 * n_lines + l] = kH * nu / (4.0 * kPi);
+    }
+    for (int i = 0; i < n_coll; ++i) {
+        hi[2 * n_lines + i] = c_up[i];
+        hi[2 * n_lines + n_coll + i] = c_lo[i];
+    }
+    double *dd = hd.data() + 5 * n_lines;
+    memcpy(dd, E, sizeof(double) * n_lev);
+    memcpy(dd + n_lev, g, sizeof(double) * n_lev);
+    memcpy(dd + 2 * n_lev, T_K, sizeof(double) * n_T);
+    if (n_coll) memcpy(dd + 2 * n_lev + n_T, K_ul, sizeof(double) * n_coll * n_T);
+    const size_t ibytes = ((sizeof(int32_t) * ni + 255) / 256) * 256;
+    char *mem = nullptr;
+    nlte_status st = dalloc(c, &mem, ibytes + sizeof(double) * nd);
+    if (st) return st;
+    dfree(c->d_species_mem);
+    c->d_species_mem = mem;
+    HIPCHK(c, hipMemcpy(mem, hi.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(mem + ibytes, hd.data(), sizeof(double) * nd, hipMemcpyHostToDevice));
+    const int32_t *di = (const int32_t *)mem;
+    const double *ddv = (const double *)(mem + ibytes);
+    SpeciesDev &sp = c->sp;
+    sp.n_lev = n_lev;
+    sp.n_lines = n_lines;
+    sp.n_coll = n_coll;
+    sp.n_T = n_T;
+    sp.mass = mass;
+    sp.lu = di;
+    sp.ll = di + n_lines;
+    sp.cu = di + 2 * n_lines;
+    sp.cl = di + 2 * n_lines + n_coll;
+    sp.A = ddv;
+    sp.nu = ddv + n_lines;
+    sp.Bul = ddv + 2 * n_lines;
+    sp.Blu = ddv + 3 * n_lines;
+    sp.pre = ddv + 4 * n_lines;
+    sp.E = ddv + 5 * n_lines;
+    sp.g = sp.E + n_lev;
+    sp.Ttab = sp.g + n_lev;
+    sp.Ktab = sp.Ttab + n_T;
+    c->n_lev = n_lev;
+    c->n_lines = n_lines;
+    c->n_coll = n_coll;
+    c->n_T = n_T;
+    c->mass = mass;
+    c->have_species = true;
+    // line widths and work buffers depend on the species: the model must be set again
+    c->have_model = false;
+    c->traced = false;
+    return upload_ibdy(c);
+}
+
+nlte_status nlte_set_models(nlte_ctx *c, int n_models, const int64_t *offsets, const double *pos,
+                            const double *vel, const double *n_h2, const double *T,
+                            const double *v_turb, const double *abundance, int k,
+                            const int32_t *nbr, const uint8_t *boundary)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    (void)hipSetDevice(c->device);
+    if (!c->have_species) return fail(c, NLTE_E_STATE, "call nlte_set_species first");
+    if (n_models < 1) return fail(c, NLTE_E_INVALID_ARG, "n_models must be >= 1");
+    if (!pos || !vel || !n_h2 || !T || !v_turb || !abundance || !nbr)
+        return fail(c, NLTE_E_INVALID_ARG, "null model array");
+    if (k < 1 || k > 64) return fail(c, NLTE_E_INVALID_ARG, "k out of [1, 64]");
+    if (!offsets) return fail(c, NLTE_E_INVALID_ARG, "offsets required ({0, P} for one model)");
+    std::vector<int64_t> off(offsets, offsets + n_models + 1);
+    if (off[0] != 0) return fail(c, NLTE_E_INVALID_ARG, "offsets[0] must be 0");
+    for (int m = 0; m < n_models; ++m)
+        if (off[m + 1] <= off[m]) return fail(c, NLTE_E_INVALID_ARG, "empty or decreasing model");
+    const int64_t P = off[n_models];
+    if (P < 1 || P > ((int64_t)1 << 31) - 1) return fail(c, NLTE_E_INVALID_ARG, "point count out of range");
+    if (!finite_all(pos, 3 * P) || !finite_all(vel, 3 * P) || !finite_all(n_h2, P) ||
+        !finite_all(T, P) || !finite_all(v_turb, P) || !finite_all(abundance, P))
+        return fail(c, NLTE_E_INVALID_ARG, "non-finite model data");
+    for (int64_t p = 0; p < P; ++p)
+        if (!(T[p] > 0.0) || n_h2[p] < 0.0 || abundance[p] < 0.0 || v_turb[p] < 0.0)
+            return fail(c, NLTE_E_INVALID_ARG, "T must be > 0 and densities, abundances, v_turb >= 0");
+    std::vector<int32_t> g(P * (size_t)k);
+    for (int m = 0; m < n_models; ++m) {
+        const int64_t o = off[m], n = off[m + 1] - off[m];
+        for (int64_t p = o; p < o + n; ++p)
+            for (int s = 0; s < k; ++s) {
+                int32_t v = nbr[p * k + s];
+                if (v == -1) {
+                    g[p * k + s] = -1;
+                    continue;
+                }
+                if (v < 0 || v >= n) return fail(c, NLTE_E_INVALID_ARG, "neighbour index out of range");
+                if (o + v == p) return fail(c, NLTE_E_INVALID_ARG, "point lists itself as neighbour");
+                g[p * k + s] = (int32_t)(o + v);
+            }
+    }
+    // device copies
+    double *d_pos = nullptr, *d_vel = nullptr, *d_vt = nullptr, *d_X = nullptr;
+    nlte_status st;
+    if ((st = dalloc(c, &c->d_cell, P)) || (st = dalloc(c, &c->d_nh2, P)) || (st = dalloc(c, &c->d_T, P)) ||
+        (st = dalloc(c, &c->d_nbr, P * (size_t)k)) || (st = dalloc(c, &d_pos, 3 * P)) ||
+        (st = dalloc(c, &d_vel, 3 * P)) || (st = dalloc(c, &d_vt, P)) || (st = dalloc(c, &d_X, P))) {
+        dfree(d_pos);
+        dfree(d_vel);
+        dfree(d_vt);
+        dfree(d_X);
+        return st;
+    }
+    dfree(c->d_bnd);
+    hipError_t e = hipSuccess;
+    auto cp = [&](void *d, const void *h, size_t b) {
+        if (e == hipSuccess) e = hipMemcpy(d, h, b, hipMemcpyHostToDevice);
+    };
+    cp(d_pos, pos, sizeof(double) * 3 * P);
+    cp(d_vel, vel, sizeof(double) * 3 * P);
+    cp(c->d_nh2, n_h2, sizeof(double) * P);
+    cp(c->d_T, T, sizeof(double) * P);
+    cp(d_vt, v_turb, sizeof(double) * P);
+    cp(d_X, abundance, sizeof(double) * P);
+    cp(c->d_nbr, g.data(), sizeof(int32_t) * P * k);
+    if (boundary && e == hipSuccess) {
+        if (hipMalloc((void **)&c->d_bnd, P) != hipSuccess) e = hipErrorOutOfMemory;
+        cp(c->d_bnd, boundary, P);
+    }
+    if (e == hipSuccess)
+        e = launch_setup_points(d_pos, d_vel, c->d_nh2, c->d_T, d_vt, d_X, c->mass, P, c->d_cell, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(d_pos);
+    dfree(d_vel);
+    dfree(d_vt);
+    dfree(d_X);
+    if (e != hipSuccess) return fail(c, NLTE_E_HIP, std::string("model upload: ") + hipGetErrorString(e));
+    c->P = P;
+    c->k = k;
+    c->n_models = n_models;
+    c->offsets = off;
+    c->have_model = true;
+    c->traced = false;
+    return ensure_work(c);
+}
+
+nlte_status nlte_set_rays(nlte_ctx *c, int n_rays, const double *dir)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    (void)hipSetDevice(c->device);
+    if (n_rays < 2 || n_rays > 1024 || (n_rays & 1)) return fail(c, NLTE_E_INVALID_ARG, "n_rays must be even in [2, 1024]");
+    if (!dir || !finite_all(dir, 3 * (int64_t)n_rays)) return fail(c, NLTE_E_INVALID_ARG, "bad directions");
+    std::vector<int32_t> anti(n_rays, -1), pr;
+    for (int r = 0; r < n_rays; ++r) {
+        double nn = dir[3 * r] * dir[3 * r] + dir[3 * r + 1] * dir[3 * r + 1] + dir[3 * r + 2] * dir[3 * r + 2];
+        if (fabs(nn - 1.0) > 1e-10) return fail(c, NLTE_E_INVALID_ARG, "directions must be unit vectors");
+        for (int s = 0; s < n_rays; ++s) {
+            double e = fabs(dir[3 * r] + dir[3 * s]) + fabs(dir[3 * r + 1] + dir[3 * s + 1]) +
+                       fabs(dir[3 * r + 2] + dir[3 * s + 2]);
+            if (e < 1e-12) {
+                if (anti[r] >= 0) return fail(c, NLTE_E_INVALID_ARG, "duplicate antipodes");
+                anti[r] = s;
+            }
+        }
+        if (anti[r] < 0) return fail(c, NLTE_E_INVALID_ARG, "ray set is not point-symmetric");
+    }
+    for (int r = 0; r < n_rays; ++r)
+        if (r < anti[r]) pr.push_back(r);
+    nlte_status st;
+    if ((st = dalloc(c, &c->d_dir, 3 * (size_t)n_rays)) || (st = dalloc(c, &c->d_anti, n_rays)) ||
+        (st = dalloc(c, &c->d_pair_r, pr.size())))
+        return st;
+    HIPCHK(c, hipMemcpy(c->d_dir, dir, sizeof(double) * 3 * n_rays, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_anti, anti.data(), sizeof(int32_t) * n_rays, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_pair_r, pr.data(), sizeof(int32_t) * pr.size(), hipMemcpyHostToDevice));
+    c->n_rays = n_rays;
+    c->n_pairs = (int)pr.size();
+    c->anti = anti;
+    c->pair_r = pr;
+    c->have_rays = true;
+    c->traced = false;
+    return NLTE_OK;
+}
+
+nlte_status nlte_set_quadrature(nlte_ctx *c, int n_q, const double *x, const double *w)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    (void)hipSetDevice(c->device);
+    if (n_q < 1 || n_q > 256 || !x || !w) return fail(c, NLTE_E_INVALID_ARG, "n_q out of [1, 256]");
+    if (!finite_all(x, n_q) || !finite_all(w, n_q)) return fail(c, NLTE_E_INVALID_ARG, "non-finite quadrature");
+    double sw = 0.0;
+    for (int n = 0; n < n_q; ++n) {
+        if (fabs(x[n] + x[n_q - 1 - n]) > 1e-12 || fabs(w[n] - w[n_q - 1 - n]) > 1e-12 || w[n] < 0.0)
+            return fail(c, NLTE_E_INVALID_ARG, "quadrature must be symmetric with w >= 0");
+        sw += w[n];
+    }
+    if (fabs(sw - 1.0) > 1e-12) return fail(c, NLTE_E_INVALID_ARG, "quadrature weights must sum to 1");
+    nlte_status st;
+    if ((st = dalloc(c, &c->d_qx, n_q)) || (st = dalloc(c, &c->d_qw, n_q))) return st;
+    HIPCHK(c, hipMemcpy(c->d_qx, x, sizeof(double) * n_q, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_qw, w, sizeof(double) * n_q, hipMemcpyHostToDevice));
+    c->n_q = n_q;
+    c->have_quad = true;
+    return NLTE_OK;
+}
+
+nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
+{
+    if (!c || !p) return NLTE_E_INVALID_ARG;
+    if (!(p->t_cmb > 0.0) || !(p->f_sub > 0.0) || !(p->tol >= 0.0) || p->max_iter < 1 ||
+        p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
+        !(p->tau_floor >= 0.0) || !(p->tau_floor < 1e-3))
+        return fail(c, NLTE_E_INVALID_ARG, "parameter out of range");
+    c->params = *p;
+    return upload_ibdy(c);
+}
+
+nlte_status nlte_trace(nlte_ctx *c)
+{
+    nlte_status st = need(c, false);
+    if (st) return st;
+    (void)hipSetDevice(c->device);
+    const int64_t n = c->P * c->n_rays;
+    if ((st = dalloc(c, &c->d_roff, n + 1))) return st;
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemsetAsync(c->d_roff, 0, sizeof(int64_t), s));
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(c, launch_walk_count(c->d_cell, c->d_nbr, c->k, c->d_bnd, c->d_dir, c->n_rays, c->P,
+                                c->d_roff + 1, s));
+    size_t tmp_bytes = 0;
+    HIPCHK(c, scan_lengths(c->d_roff, n, nullptr, &tmp_bytes, s));
+    void *tmp = nullptr;
+    HIPCHK(c, hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 1));
+    hipError_t e = scan_lengths(c->d_roff, n, tmp, &tmp_bytes, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, NLTE_E_HIP, std::string("scan: ") + hipGetErrorString(e));
+    int64_t total = 0;
+    HIPCHK(c, hipMemcpy(&total, c->d_roff + n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if ((st = dalloc(c, &c->d_rcells, (size_t)total))) return st;
+    HIPCHK(c, launch_walk_fill(c->d_cell, c->d_nbr, c->k, c->d_bnd, c->d_dir, c->n_rays, c->P,
+                               c->d_roff, c->d_rcells, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    c->st_trace.ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    c->st_trace.launches += 1;
+    // longest ray
+    std::vector<int64_t> off(n + 1);
+    HIPCHK(c, hipMemcpy(off.data(), c->d_roff, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    int mx = 0;
+    for (int64_t i = 0; i < n; ++i) mx = std::max<int>(mx, (int)(off[i + 1] - off[i]));
+    c->total_cells = total;
+    c->max_len = mx;
+    // elimination steps per frequency (cells + velocity sub-steps)
+    HIPCHK(c, hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s));
+    SolveArgs a = solve_args(c, nullptr, nullptr, nullptr);
+    HIPCHK(c, launch_count_steps(a, c->d_maser, s));
+    HIPCHK(c, hipMemcpyAsync(&c->total_steps, c->d_maser, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->traced = true;
+    return NLTE_OK;
+}
+
+nlte_status nlte_get_ray(nlte_ctx *c, int64_t point, int ray, int32_t *cells, int cap, int *len)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (point < 0 || point >= c->P || ray < 0 || ray >= c->n_rays || cap < 0 || (cap > 0 && !cells))
+        return fail(c, NLTE_E_INVALID_ARG, "point or ray out of range");
+    int64_t q = point * c->n_rays + ray, o[2];
+    HIPCHK(c, hipMemcpy(o, c->d_roff + q, sizeof(int64_t) * 2, hipMemcpyDeviceToHost));
+    int L = (int)(o[1] - o[0]);
+    if (len) *len = L;
+    int ncopy = std::min(L, cap);
+    if (ncopy > 0) {
+        HIPCHK(c, hipMemcpy(cells, c->d_rcells + o[0], sizeof(int32_t) * ncopy, hipMemcpyDeviceToHost));
+        // model-local indices
+        int m = (int)(std::upper_bound(c->offsets.begin(), c->offsets.end(), point) - c->offsets.begin()) - 1;
+        for (int i = 0; i < ncopy; ++i) cells[i] -= (int32_t)c->offsets[m];
+    }
+    return NLTE_OK;
+}
+
+nlte_status nlte_trace_stats(nlte_ctx *c, int64_t *total_cells, int *max_len, int64_t *total_steps)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (total_cells) *total_cells = c->total_cells;
+    if (max_len) *max_len = c->max_len;
+    if (total_steps) *total_steps = c->total_steps;
+    return NLTE_OK;
+}
+
+nlte_status nlte_get_line_width_speed(nlte_ctx *c, double *vw)
+{
+    if (!c || !vw) return NLTE_E_INVALID_ARG;
+    if (!c->have_model) return fail(c, NLTE_E_STATE, "no model");
+    std::vector<CellRec> h(c->P);
+    HIPCHK(c, hipMemcpy(h.data(), c->d_cell, sizeof(CellRec) * c->P, hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < c->P; ++p) vw[p] = h[p].vw;
+    return NLTE_OK;
+}
+
+nlte_status nlte_lte_dev(nlte_ctx *c, double *d_pops, void *stream)
+{
+    nlte_status st = need(c, false);
+    if (st) return st;
+    if (!d_pops) return fail(c, NLTE_E_INVALID_ARG, "null pops");
+    (void)hipSetDevice(c->device);
+    hipStream_t s = pick(c, stream);
+    HIPCHK(c, timed(c, c->st_lte, s, [&] { return launch_lte(c->sp, c->d_cell, c->d_T, c->P, d_pops, s); }));
+    return NLTE_OK;
+}
+
+nlte_status nlte_lte(nlte_ctx *c, double *pops)
+{
+    if (!pops) return fail(c, NLTE_E_INVALID_ARG, "null pops");
+    nlte_status st = nlte_lte_dev(c, c ? c->d_pops_a : nullptr, nullptr);
+    if (st) return st;
+    HIPCHK(c, hipMemcpyAsync(pops, c->d_pops_a, sizeof(double) * c->P * c->n_lev, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NLTE_OK;
+}
+
+nlte_status nlte_formal_solve_dev(nlte_ctx *c, const double *d_pops, double *d_J, double *d_Jeff,
+                                  double *d_L, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!d_pops || !d_J || !d_Jeff || !d_L) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    (void)hipSetDevice(c->device);
+    hipStream_t s = pick(c, stream);
+    HIPCHK(c, hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s));
+    return formal_solve_impl(c, d_pops, d_J, d_Jeff, d_L, s);
+}
+
+nlte_status nlte_formal_solve(nlte_ctx *c, const double *pops, double *J, double *Jeff, double *L)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!pops || !J || !Jeff || !L) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    (void)hipSetDevice(c->device);
+    const size_t np = sizeof(double) * c->P * c->n_lev, nj = sizeof(double) * c->P * c->n_lines;
+    HIPCHK(c, hipMemcpyAsync(c->d_pops_a, pops, np, hipMemcpyHostToDevice, c->stream));
+    if ((st = nlte_formal_solve_dev(c, c->d_pops_a, c->d_J, c->d_Jeff, c->d_L, nullptr))) return st;
+    HIPCHK(c, hipMemcpyAsync(J, c->d_J, nj, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Jeff, c->d_Jeff, nj, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(L, c->d_L, nj, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NLTE_OK;
+}
+
+nlte_status nlte_stateq_dev(nlte_ctx *c, const double *d_old, const double *d_J, const double *d_Jeff,
+                            const double *d_L, double *d_new, uint8_t *d_flags, void *stream)
+{
+    nlte_status st = need(c, false);
+    if (st) return st;
+    if (!d_old || !d_J || !d_Jeff || !d_L || !d_new) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    (void)hipSetDevice(c->device);
+    return stateq_impl(c, d_old, d_J, d_Jeff, d_L, d_new, d_flags, nullptr, pick(c, stream));
+}
+
+nlte_status nlte_stateq(nlte_ctx *c, const double *pops_old, const double *J, const double *Jeff,
+                        const double *L, double *pops_new, uint8_t *flags)
+{
+    nlte_status st = need(c, false);
+    if (st) return st;
+    if (!pops_old || !J || !Jeff || !L || !pops_new) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    (void)hipSetDevice(c->device);
+    const size_t np = sizeof(double) * c->P * c->n_lev, nj = sizeof(double) * c->P * c->n_lines;
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(c->d_pops_a, pops_old, np, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_J, J, nj, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_Jeff, Jeff, nj, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_L, L, nj, hipMemcpyHostToDevice, s));
+    if ((st = stateq_impl(c, c->d_pops_a, c->d_J, c->d_Jeff, c->d_L, c->d_pops_b, c->d_flags, nullptr, s)))
+        return st;
+    HIPCHK(c, hipMemcpyAsync(pops_new, c->d_pops_b, np, hipMemcpyDeviceToHost, s));
+    if (flags) HIPCHK(c, hipMemcpyAsync(flags, c->d_flags, c->P, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return NLTE_OK;
+}
+
+nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, nlte_ali_report *rep,
+                             void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!d_out) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    (void)hipSetDevice(c->device);
+    hipStream_t s = pick(c, stream);
+    const size_t np = sizeof(double) * c->P * c->n_lev;
+    auto t0 = std::chrono::steady_clock::now();
+    if (d_init)
+        HIPCHK(c, hipMemcpyAsync(c->d_pops_a, d_init, np, hipMemcpyDeviceToDevice, s));
+    else
+        HIPCHK(c, launch_lte(c->sp, c->d_cell, c->d_T, c->P, c->d_pops_a, s));
+    double *cur = c->d_pops_a, *nxt = c->d_pops_b;
+    if (rep) memset(rep, 0, sizeof(*rep));
+    int it = 0;
+    bool conv = false;
+    ConvResult last{};
+    while (it < c->params.max_iter) {
+        HIPCHK(c, hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s));
+        if ((st = formal_solve_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, s))) return st;
+        if ((st = stateq_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, nxt, c->d_flags, c->d_conv, s))) return st;
+        HIPCHK(c, hipMemcpyAsync(c->h_conv, c->d_conv, sizeof(ConvResult), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        last = *c->h_conv;
+        if (rep && it < 1024) {
+            rep->max_change[it] = last.max_change;
+            rep->mean_change[it] = last.mean_change;
+        }
+        std::swap(cur, nxt);
+        ++it;
+        if (last.max_change < c->params.tol) {
+            conv = true;
+            break;
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(d_out, cur, np, hipMemcpyDeviceToDevice, s));
+    int64_t maser = 0;
+    HIPCHK(c, hipMemcpyAsync(&maser, c->d_maser, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    if (rep) {
+        rep->iterations = it;
+        rep->converged = conv ? 1 : 0;
+        rep->n_fallback = last.n_fallback;
+        rep->n_kept = last.n_kept;
+        rep->n_maser = maser;
+        rep->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (!conv) {
+        c->err = "ALI stopped at max_iter above tol";
+        return NLTE_W_NOT_CONVERGED;
+    }
+    if (last.n_fallback || last.n_kept) {
+        c->err = "some points fell back or kept their populations";
+        return NLTE_W_NONPHYSICAL;
+    }
+    return NLTE_OK;
+}
+
+nlte_status nlte_run_ali(nlte_ctx *c, const double *pops_init, double *pops_out, nlte_ali_report *rep)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!pops_out) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    (void)hipSetDevice(c->device);
+    const size_t np = sizeof(double) * c->P * c->n_lev;
+    double *d_in = nullptr, *d_out = nullptr;
+    if ((st = dalloc(c, &d_out, (size_t)c->P * c->n_lev))) return st;
+    if (pops_init) {
+        if ((st = dalloc(c, &d_in, (size_t)c->P * c->n_lev))) {
+            dfree(d_out);
+            return st;
+        }
+        if (hipMemcpy(d_in, pops_init, np, hipMemcpyHostToDevice) != hipSuccess) {
+            dfree(d_in);
+            dfree(d_out);
+            return fail(c, NLTE_E_HIP, "copy of pops_init failed");
+        }
+    }
+    nlte_status rs = nlte_run_ali_dev(c, d_in, d_out, rep, nullptr);
+    if (rs >= 0) {
+        if (hipMemcpy(pops_out, d_out, np, hipMemcpyDeviceToHost) != hipSuccess) rs = NLTE_E_HIP;
+    }
+    dfree(d_in);
+    dfree(d_out);
+    return rs;
+}
+
+nlte_status nlte_kernel_stats(nlte_ctx *c, const char *name, double *ms, int64_t *launches)
+{
+    if (!c || !name) return NLTE_E_INVALID_ARG;
+    KernelStat *k = nullptr;
+    if (!strcmp(name, "line_coef")) k = &c->st_line_coef;
+    else if (!strcmp(name, "formal_solve")) k = &c->st_formal;
+    else if (!strcmp(name, "stateq")) k = &c->st_stateq;
+    else if (!strcmp(name, "lte")) k = &c->st_lte;
+    else if (!strcmp(name, "trace")) k = &c->st_trace;
+    if (!k) return fail(c, NLTE_E_INVALID_ARG, "unknown kernel name");
+    if (ms) *ms = k->ms;
+    if (launches) *launches = k->launches;
+    return NLTE_OK;
+}
+
+nlte_status nlte_reset_kernel_stats(nlte_ctx *c)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    c->st_line_coef = c->st_formal = c->st_stateq = c->st_lte = c->st_trace = KernelStat{};
+    return NLTE_OK;
+}
+
+}  // extern "C"

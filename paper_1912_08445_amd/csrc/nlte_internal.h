@@ -1,0 +1,181 @@
+// Internal declarations of the gfx950 library: device data layout, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "nlte.h"
+
+namespace nlte {
+
+// CGS constants (SI-exact values).
+constexpr double kH = 6.62607015e-27;
+constexpr double kKB = 1.380649e-16;
+constexpr double kC = 2.99792458e10;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602730;
+
+constexpr int kMaxLev = 16;
+constexpr int kMaxLines = 32;
+constexpr int kWave = 64;
+// Upper bound on the velocity sub-intervals of one segment (an implementation limit that
+// keeps every sweep finite for any input; realistic models stay far below it).
+constexpr int kMaxSub = 1 << 20;
+
+// One gather-friendly 64-byte record per point: what a ray walk and a ray-pair sweep
+// read from the cells they visit.
+struct __align__(64) CellRec {
+    double px, py, pz;  // position [cm]
+    double vw;          // line-width speed sqrt(2kT/m + v_turb^2) [cm/s]
+    double vx, vy, vz;  // velocity [cm/s]
+    double ntot;        // species density abundance * n_H2 [cm^-3]
+};
+
+// Species tables in device memory (one allocation, pointers into it).
+struct SpeciesDev {
+    int n_lev, n_lines, n_coll, n_T;
+    double mass;
+    const int32_t *lu, *ll, *cu, *cl;
+    const double *A, *nu, *Bul, *Blu, *pre;  // pre = h nu / 4 pi
+    const double *E, *g, *Ttab, *Ktab;
+};
+
+// Per-iteration convergence partials written by the stat-eq kernel.
+struct ConvPartial {
+    double max_change;
+    double sum_change;
+    int64_t count;
+    int64_t n_fallback;
+    int64_t n_kept;
+};
+
+struct ConvResult {
+    double max_change;
+    double mean_change;
+    int64_t n_fallback;
+    int64_t n_kept;
+};
+
+struct SolveArgs {
+    const CellRec *cell;
+    const void *lc;          // [P][n_lines] (kappa, S): double2 (FP64) or float2 (FP32 bulk)
+    const int64_t *roff;     // [P * n_rays + 1]
+    const int32_t *rcells;   // cached walks, global point indices, nearest first
+    const double *dir;       // [n_rays][3]
+    const int32_t *pair_r;   // [n_pairs] representative ray of each pair
+    const int32_t *anti;     // [n_rays]
+    const double *qx, *qw;   // [n_q]
+    const double *ibdy;      // [n_lines] boundary intensity
+    double f_sub;
+    double tau_floor;
+    double norm;             // 2 / n_rays
+    int64_t P;
+    int n_rays, n_pairs, n_q, n_lines;
+    int groups;              // waves per point
+    int lines_per_wave;      // > 0 when n_q <= 64
+    int fchunks;             // frequency chunks per wave when n_q > 64
+    int64_t n_blocks;        // logical blocks (P * groups)
+    double *J, *Jeff, *L;    // [P][n_lines]
+};
+
+struct KernelStat {
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+
+}  // namespace nlte
+
+struct nlte_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    nlte_params params{};
+
+    // species
+    bool have_species = false;
+    int n_lev = 0, n_lines = 0, n_coll = 0, n_T = 0;
+    double mass = 0.0;
+    std::vector<double> nu;  // host copy of line frequencies
+    void *d_species_mem = nullptr;
+    nlte::SpeciesDev sp{};
+
+    // model(s)
+    bool have_model = false;
+    int64_t P = 0;
+    int k = 0;
+    int n_models = 0;
+    std::vector<int64_t> offsets;   // [n_models + 1]
+    nlte::CellRec *d_cell = nullptr;
+    double *d_nh2 = nullptr, *d_T = nullptr;
+    int32_t *d_nbr = nullptr;  // global indices
+    uint8_t *d_bnd = nullptr;
+
+    // rays
+    bool have_rays = false;
+    int n_rays = 0, n_pairs = 0;
+    std::vector<int32_t> pair_r, anti;
+    double *d_dir = nullptr;
+    int32_t *d_pair_r = nullptr, *d_anti = nullptr;
+
+    // quadrature
+    bool have_quad = false;
+    int n_q = 0;
+    double *d_qx = nullptr, *d_qw = nullptr;
+    double *d_ibdy = nullptr;
+
+    // ray cache
+    bool traced = false;
+    int64_t *d_roff = nullptr;
+    int32_t *d_rcells = nullptr;
+    int64_t total_cells = 0;
+    int64_t total_steps = 0;
+    int max_len = 0;
+
+    // work buffers (sized for P)
+    void *d_lc = nullptr;  // line coefficients
+    double *d_pops_a = nullptr, *d_pops_b = nullptr;
+    double *d_J = nullptr, *d_Jeff = nullptr, *d_L = nullptr;
+    uint8_t *d_flags = nullptr;
+    nlte::ConvPartial *d_partials = nullptr;
+    int64_t n_partials_cap = 0;
+    nlte::ConvResult *d_conv = nullptr;
+    nlte::ConvResult *h_conv = nullptr;  // pinned
+    int64_t *d_maser = nullptr;
+
+    // profiling
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    nlte::KernelStat st_line_coef, st_formal, st_stateq, st_lte, st_trace;
+};
+
+namespace nlte {
+
+// Launchers (each enqueues on `stream`; return hipSuccess or the launch error).
+hipError_t launch_setup_points(const double *pos, const double *vel, const double *nh2,
+                               const double *T, const double *vturb, const double *X,
+                               double mass, int64_t P, CellRec *cell, hipStream_t s);
+hipError_t launch_lte(const SpeciesDev &sp, const CellRec *cell, const double *T, int64_t P,
+                      double *pops, hipStream_t s);
+hipError_t launch_walk_count(const CellRec *cell, const int32_t *nbr, int k, const uint8_t *bnd,
+                             const double *dir, int n_rays, int64_t P, int64_t *len,
+                             hipStream_t s);
+hipError_t launch_walk_fill(const CellRec *cell, const int32_t *nbr, int k, const uint8_t *bnd,
+                            const double *dir, int n_rays, int64_t P, const int64_t *off,
+                            int32_t *cells, hipStream_t s);
+hipError_t scan_lengths(int64_t *len_then_off, int64_t n, void *tmp, size_t *tmp_bytes,
+                        hipStream_t s);
+hipError_t launch_line_coef(const SpeciesDev &sp, const CellRec *cell, const double *pops,
+                            int64_t P, int fp32, void *lc, int64_t *maser_count, hipStream_t s);
+hipError_t launch_formal_solve(const SolveArgs &a, int fp32, hipStream_t s);
+hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, hipStream_t s);
+hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double *nh2,
+                         const double *T, int64_t P, int use_alo, const double *pops_old,
+                         const double *J, const double *Jeff, const double *L, double *pops_new,
+                         uint8_t *flags, ConvPartial *partials, int64_t n_blocks, hipStream_t s);
+int64_t stateq_blocks(int64_t P);
+hipError_t launch_conv_final(const ConvPartial *partials, int64_t n, ConvResult *out,
+                             hipStream_t s);
+
+}  // namespace nlte

@@ -1,0 +1,224 @@
+// Statistical equilibrium per point and the convergence reduction.
+#include "nlte_internal.h"
+
+namespace nlte {
+
+// H2 de-excitation coefficient of collision pair ic, linear in T between table points
+// and clamped at the ends; j is the table interval holding T (T inside the table).
+__device__ __forceinline__ double coll_K(const SpeciesDev &sp, int ic, double T, int j, int where)
+{
+    const double *K = sp.Ktab + (int64_t)ic * sp.n_T;
+    if (where < 0) return K[0];
+    if (where > 0) return K[sp.n_T - 1];
+    return K[j] + (K[j + 1] - K[j]) * (T - sp.Ttab[j]) / (sp.Ttab[j + 1] - sp.Ttab[j]);
+}
+
+// Assemble and solve the rate equations of one point (Eq. ourALI, diagonal ALO):
+// u->l = A(1 - L) + B_ul Jeff + C_ul,  l->u = B_lu Jeff + C_lu; row 0 := conservation.
+__device__ int solve_point(const SpeciesDev &sp, double T, double nh2, double ntot,
+                           const double *Jrow, const double *Lrow, bool with_L, double *x)
+{
+    const int n = sp.n_lev;
+    double M[kMaxLev * kMaxLev];
+    double rhs[kMaxLev];
+    for (int i = 0; i < n * n; ++i) M[i] = 0.0;
+    for (int i = 0; i < n; ++i) rhs[i] = 0.0;
+    // transition a -> b with rate R: gain for b, loss for a
+    for (int l = 0; l < sp.n_lines; ++l) {
+        const int u = sp.lu[l], lo = sp.ll[l];
+        const double Lv = with_L ? Lrow[l] : 0.0;
+        const double Rul = sp.A[l] * (1.0 - Lv) + sp.Bul[l] * Jrow[l];
+        const double Rlu = sp.Blu[l] * Jrow[l];
+        M[lo * n + u] += Rul;
+        M[u * n + u] -= Rul;
+        M[u * n + lo] += Rlu;
+        M[lo * n + lo] -= Rlu;
+    }
+    int where = 0, j = 0;
+    if (T <= sp.Ttab[0]) where = -1;
+    else if (T >= sp.Ttab[sp.n_T - 1]) where = 1;
+    else
+        while (j + 2 < sp.n_T && !(T < sp.Ttab[j + 1])) ++j;
+    const double kT = kKB * T;
+    for (int ic = 0; ic < sp.n_coll; ++ic) {
+        const int u = sp.cu[ic], lo = sp.cl[ic];
+        const double Cul = coll_K(sp, ic, T, j, where) * nh2;
+        // detailed balance with the Boltzmann sign
+        const double Clu = Cul * (sp.g[u] / sp.g[lo]) * exp(-(sp.E[u] - sp.E[lo]) / kT);
+        M[lo * n + u] += Cul;
+        M[u * n + u] -= Cul;
+        M[u * n + lo] += Clu;
+        M[lo * n + lo] -= Clu;
+    }
+    for (int c = 0; c < n; ++c) M[c] = 1.0;
+    rhs[0] = ntot;
+    // Gaussian elimination with partial pivoting
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(M[r * n + col]) > fabs(M[piv * n + col])) piv = r;
+        if (M[piv * n + col] == 0.0) return -1;
+        if (piv != col) {
+            for (int c = 0; c < n; ++c) {
+                double t = M[col * n + c];
+                M[col * n + c] = M[piv * n + c];
+                M[piv * n + c] = t;
+            }
+            double t = rhs[col];
+            rhs[col] = rhs[piv];
+            rhs[piv] = t;
+        }
+        for (int r = col + 1; r < n; ++r) {
+            double f = M[r * n + col] / M[col * n + col];
+            for (int c = col; c < n; ++c) M[r * n + c] -= f * M[col * n + c];
+            rhs[r] -= f * rhs[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = rhs[r];
+        for (int c = r + 1; c < n; ++c) s -= M[r * n + c] * x[c];
+        x[r] = s / M[r * n + r];
+    }
+    return 0;
+}
+
+__device__ __forceinline__ bool valid(int n, const double *x)
+{
+    for (int i = 0; i < n; ++i)
+        if (!(x[i] > 0.0) || !isfinite(x[i])) return false;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_stateq(SpeciesDev sp, const CellRec *__restrict__ cell,
+                                                const double *__restrict__ nh2,
+                                                const double *__restrict__ Tg, int64_t P, int use_alo,
+                                                const double *__restrict__ pops_old,
+                                                const double *__restrict__ J,
+                                                const double *__restrict__ Jeff,
+                                                const double *__restrict__ L,
+                                                double *__restrict__ pops_new,
+                                                uint8_t *__restrict__ flags, ConvPartial *partials)
+{
+    __shared__ double s_max[256], s_sum[256];
+    __shared__ int64_t s_cnt[256], s_fb[256], s_kept[256];
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double mx = 0.0, sum = 0.0;
+    int64_t cnt = 0, fb = 0, kept = 0;
+    if (p < P) {
+        const int n = sp.n_lev, nl = sp.n_lines;
+        const double T = Tg[p], nh = nh2[p], nt = cell[p].ntot;
+        double x[kMaxLev];
+        uint8_t f = 0;
+        const double *Jr = J + p * nl;
+        const double *Er = use_alo ? Jeff + p * nl : Jr;
+        if (solve_point(sp, T, nh, nt, Er, L + p * nl, use_alo != 0, x) != 0 || !valid(n, x)) {
+            // Sec. 6.1: redo without the ALO, then keep the old populations
+            f = 1;
+            if (solve_point(sp, T, nh, nt, Jr, L + p * nl, false, x) != 0 || !valid(n, x)) {
+                f = 2;
+                for (int i = 0; i < n; ++i) x[i] = pops_old[p * n + i];
+            }
+        }
+        for (int i = 0; i < n; ++i) {
+            pops_new[p * n + i] = x[i];
+            if (x[i] / nt > 1e-10) {
+                double d = fabs(x[i] - pops_old[p * n + i]) / x[i];
+                mx = fmax(mx, d);
+                sum += d;
+                ++cnt;
+            }
+        }
+        if (flags) flags[p] = f;
+        fb = (f == 1);
+        kept = (f == 2);
+    }
+    const int t = threadIdx.x;
+    s_max[t] = mx;
+    s_sum[t] = sum;
+    s_cnt[t] = cnt;
+    s_fb[t] = fb;
+    s_kept[t] = kept;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            s_max[t] = fmax(s_max[t], s_max[t + w]);
+            s_sum[t] += s_sum[t + w];
+            s_cnt[t] += s_cnt[t + w];
+            s_fb[t] += s_fb[t + w];
+            s_kept[t] += s_kept[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0 && partials) {
+        ConvPartial cp;
+        cp.max_change = s_max[0];
+        cp.sum_change = s_sum[0];
+        cp.count = s_cnt[0];
+        cp.n_fallback = s_fb[0];
+        cp.n_kept = s_kept[0];
+        partials[blockIdx.x] = cp;
+    }
+}
+
+int64_t stateq_blocks(int64_t P) { return (P + 255) / 256; }
+
+hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double *nh2,
+                         const double *T, int64_t P, int use_alo, const double *pops_old,
+                         const double *J, const double *Jeff, const double *L, double *pops_new,
+                         uint8_t *flags, ConvPartial *partials, int64_t n_blocks, hipStream_t s)
+{
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stateq, dim3((unsigned)n_blocks), dim3(256), 0, s, sp, cell, nh2, T, P,
+                       use_alo, pops_old, J, Jeff, L, pops_new, flags, partials);
+    return hipGetLastError();
+}
+
+// Deterministic final reduction of the per-block partials (one workgroup, fixed order).
+__global__ __launch_bounds__(256) void k_conv_final(const ConvPartial *__restrict__ part, int64_t n,
+                                                    ConvResult *out)
+{
+    __shared__ double s_max[256], s_sum[256];
+    __shared__ int64_t s_cnt[256], s_fb[256], s_kept[256];
+    const int t = threadIdx.x;
+    double mx = 0.0, sum = 0.0;
+    int64_t cnt = 0, fb = 0, kept = 0;
+    for (int64_t i = t; i < n; i += 256) {
+        mx = fmax(mx, part[i].max_change);
+        sum += part[i].sum_change;
+        cnt += part[i].count;
+        fb += part[i].n_fallback;
+        kept += part[i].n_kept;
+    }
+    s_max[t] = mx;
+    s_sum[t] = sum;
+    s_cnt[t] = cnt;
+    s_fb[t] = fb;
+    s_kept[t] = kept;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            s_max[t] = fmax(s_max[t], s_max[t + w]);
+            s_sum[t] += s_sum[t + w];
+            s_cnt[t] += s_cnt[t + w];
+            s_fb[t] += s_fb[t + w];
+            s_kept[t] += s_kept[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        ConvResult r;
+        r.max_change = s_max[0];
+        r.mean_change = s_cnt[0] ? s_sum[0] / (double)s_cnt[0] : 0.0;
+        r.n_fallback = s_fb[0];
+        r.n_kept = s_kept[0];
+        *out = r;
+    }
+}
+
+hipError_t launch_conv_final(const ConvPartial *partials, int64_t n, ConvResult *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_conv_final, dim3(1), dim3(256), 0, s, partials, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace nlte
