@@ -59,8 +59,6 @@ typedef struct {
     int use_alo;      /* 1: diagonal ALO (Sec. 3.4); 0: plain Lambda iteration */
     int precision;    /* NLTE_PREC_* */
     int profile;      /* 1: time every kernel with HIP events (nlte_kernel_stats) */
-    double tau_floor; /* lower bound on every optical-depth step (zero-opacity segments in
-                         the far line wings).  1e-30 */
 } nlte_params;
 
 /* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0. */

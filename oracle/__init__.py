@@ -85,7 +85,7 @@ def planck(nu: float, T: float) -> float:
     return lib().or_planck(nu, T)
 
 
-def solve_ray(z, chi, S, I_lo, I_hi, o, tau_floor=1e-30, want_all=False):
+def solve_ray(z, chi, S, I_lo, I_hi, o, tau_floor=1e-100, want_all=False):
     """One Feautrier solve on explicit nodes: returns (u_o, Lambda_oo, ueff_o[, u_all])."""
     z, chi, S = _f64(z), _f64(chi), _f64(S)
     N = z.shape[0]
@@ -102,7 +102,7 @@ class Oracle:
     """One model + species + rays + quadrature, as the oracle sees it."""
 
     def __init__(self, model, species, rays, quad_x, quad_w, t_cmb=2.725, f_sub=0.25,
-                 tau_floor=1e-30, use_alo=True):
+                 tau_floor=1e-100, use_alo=True):
         L = lib()
         self._L = L
         self.c = L.or_create()

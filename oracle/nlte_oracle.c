@@ -79,7 +79,7 @@ or_ctx *or_create(void)
     or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
     c->t_cmb = 2.725;
     c->f_sub = 0.25;
-    c->tau_floor = 1e-30;
+    c->tau_floor = 1e-100; /* guards A_i, C_i against zero optical depth; effect < 1e-90 */
     c->use_alo = 1;
     return c;
 }

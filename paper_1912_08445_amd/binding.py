@@ -38,7 +38,7 @@ EXPORTS = (
 class Params(C.Structure):
     _fields_ = [("t_cmb", C.c_double), ("f_sub", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("use_alo", C.c_int), ("precision", C.c_int),
-                ("profile", C.c_int), ("tau_floor", C.c_double)]
+                ("profile", C.c_int)]
 
 
 class AliReport(C.Structure):

@@ -136,7 +136,7 @@ SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
     a.qw = c->d_qw;
     a.ibdy = c->d_ibdy;
     a.f_sub = c->params.f_sub;
-    a.tau_floor = c->params.tau_floor;
+    a.xq_max = c->xq_max;
     a.norm = 2.0 / (double)c->n_rays;
     a.P = c->P;
     a.n_rays = c->n_rays;
@@ -198,7 +198,6 @@ void nlte_default_params(nlte_params *p)
     p->use_alo = 1;
     p->precision = NLTE_PREC_FP64;
     p->profile = 0;
-    p->tau_floor = 1e-30;
 }
 
 nlte_status nlte_create(nlte_ctx **out, int hip_device)
@@ -501,6 +500,8 @@ nlte_status nlte_set_quadrature(nlte_ctx *c, int n_q, const double *x, const dou
     HIPCHK(c, hipMemcpy(c->d_qx, x, sizeof(double) * n_q, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_qw, w, sizeof(double) * n_q, hipMemcpyHostToDevice));
     c->n_q = n_q;
+    c->xq_max = 0.0;
+    for (int n = 0; n < n_q; ++n) c->xq_max = std::max(c->xq_max, fabs(x[n]));
     c->have_quad = true;
     return NLTE_OK;
 }
@@ -509,8 +510,7 @@ nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
 {
     if (!c || !p) return NLTE_E_INVALID_ARG;
     if (!(p->t_cmb > 0.0) || !(p->f_sub > 0.0) || !(p->tol >= 0.0) || p->max_iter < 1 ||
-        p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
-        !(p->tau_floor >= 0.0) || !(p->tau_floor < 1e-3))
+        p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK))
         return fail(c, NLTE_E_INVALID_ARG, "parameter out of range");
     c->params = *p;
     return upload_ibdy(c);

@@ -14,8 +14,9 @@
 // (z_i the Rybicki-Hummer right-hand side), one elimination step becomes
 //   T = h_i + Q_{i-1};  F_i = D_+ T;  E = 1/(1 + F_i);  Q_i = T E;  y_i = (S_i h_i + y_{i-1}) E
 // with Q = 1, y = I_boundary, D_- = 0 before the first node, which is exactly the Auer
-// boundary row.  No step divides by an optical depth, so zero-opacity segments need no
-// floor.  At O the two halves combine into
+// boundary row.  No step divides by an optical depth.  The sweep carries Q and y as
+// fractions N/D and Y/D, which turns each step into three multiply-adds of non-negative
+// numbers with no division (see elim_step).  At O the two halves combine into
 //   u_O = (h_O S_O + y_f + y_b) / (h_O + Q_f + Q_b),   Lambda_OO = h_O / (h_O + Q_f + Q_b),
 // and u_O - Lambda_OO S_O = (y_f + y_b) / (h_O + Q_f + Q_b) without cancellation.
 //
@@ -92,52 +93,81 @@ struct Bulk<true> {
 };
 
 // One staged node of a half ray.  (a, b) give the Doppler offset of a lane's frequency
-// x_q at this node as x = a x_q - b; (dzh, m) describe the segment to the next node
-// toward O: m sub-intervals of half-length dzh each.
+// x_q at this node as x = a x_q - b.  The segment to the next node toward O has m
+// sub-intervals of half-length dzh; per sub-interval x changes by da x_q - db and kappa,
+// S by dk, dS (per staged line); K is the restart interval of the profile recurrence.
 template <typename T>
 struct NodeRec {
-    T a, b, dzh;
-    T kap[2], S[2];
-    int m;
+    T a, b, dzh, da, db;
+    T kap[2], S[2], dk[2], dS[2];
+    int m, K;
 };
 
+// Elimination state of a half sweep in homogeneous form: the Rybicki-Hummer quantities
+// Q = N / D and y = Y / D (see the file comment), and the previous optical-depth step.
 struct HalfState {
-    double Q, y, Dm;
+    double N, D, Y, Dm;
 };
 
-__device__ __forceinline__ double rcp64(double d)
+// e^y for y <= 700 in FP64: y = n ln2 + r with |r| <= ln2/2 (two-part ln2), e^r by its
+// degree-11 Taylor polynomial (truncation < 7e-15 relative), scaled by 2^n.  Results
+// below the FP64 range come out as 0 through ldexp; no other special cases arise for
+// the arguments used here (finite, at most 700).
+__device__ __forceinline__ double exp_le700(double y)
 {
-    // v_rcp_f64 refined by two Newton steps (d >= 1 here)
-    double r = __builtin_amdgcn_rcp(d);
-    double e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-d, r, 1.0);
-    return fma(r, e, r);
+    const double n = rint(y * 1.44269504088896338700);
+    double r = fma(-n, 6.93147180369123816490e-01, y);
+    r = fma(-n, 1.90821492927058770002e-10, r);
+    double p = 2.50521083854417187751e-08;           // 1/11!
+    p = fma(p, r, 2.75573192239858906526e-07);       // 1/10!
+    p = fma(p, r, 2.75573192239858906526e-06);       // 1/9!
+    p = fma(p, r, 2.48015873015873015873e-05);       // 1/8!
+    p = fma(p, r, 1.98412698412698412698e-04);       // 1/7!
+    p = fma(p, r, 1.38888888888888888889e-03);       // 1/6!
+    p = fma(p, r, 8.33333333333333333333e-03);       // 1/5!
+    p = fma(p, r, 4.16666666666666666667e-02);       // 1/4!
+    p = fma(p, r, 1.66666666666666666667e-01);       // 1/3!
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    const int ni = (int)fmax(n, -2200.0);
+    return ldexp(p, ni);
 }
 
-__device__ __forceinline__ double profile(double x) { return exp(-(x * x)); }
+__device__ __forceinline__ double profile(double x) { return exp_le700(-(x * x)); }
 __device__ __forceinline__ float profile(float x)
 {
     // e^{-x^2} = 2^{-x^2 log2 e} on the hardware exp2
     return __builtin_amdgcn_exp2f(-(x * x) * 1.44269504088896340736f);
 }
 
-template <bool F32>
+// One elimination step: node with source S_e (between optical-depth steps Dm and Dp) is
+// eliminated.  With h = (Dm + Dp)/2 the Rybicki-Hummer update
+//   T = h + Q, E = 1/(1 + Dp T), Q' = T E, y' = (S h + y) E
+// becomes, for Q = N/D and y = Y/D,
+//   N' = N + h D,  Y' = Y + S h D,  D' = D + Dp N'
+// (only products and sums of non-negative numbers).  RENORM rescales N, D, Y by the
+// power of two that brings D into [0.5, 1), which is exact.
+template <bool F32, bool RENORM>
 __device__ __forceinline__ void elim_step(typename Bulk<F32>::T chi_t, typename Bulk<F32>::T S_t,
                                           typename Bulk<F32>::T dzh, typename Bulk<F32>::T &chi_prev,
-                                          typename Bulk<F32>::T &S_e, HalfState &st, double floor)
+                                          typename Bulk<F32>::T &S_e, HalfState &st)
 {
-    // trapezoid optical depth of the step, floored like the zero-opacity far wings
-    double Dp = fmax((double)((chi_prev + chi_t) * dzh), floor);
-    double h = 0.5 * (st.Dm + Dp);
-    double Tt = h + st.Q;
-    double F = Dp * Tt;
-    double E = rcp64(1.0 + F);
-    st.Q = Tt * E;
-    st.y = fma((double)S_e, h, st.y) * E;
+    // trapezoid optical depth of the step; zero is allowed (nothing divides by it)
+    const double Dp = (double)((chi_prev + chi_t) * dzh);
+    const double hD = (0.5 * (st.Dm + Dp)) * st.D;
+    st.N = st.N + hD;
+    st.Y = fma((double)S_e, hD, st.Y);
+    st.D = fma(Dp, st.N, st.D);
     st.Dm = Dp;
     chi_prev = chi_t;
     S_e = S_t;
+    if (RENORM) {
+        const int e = __builtin_amdgcn_frexp_exp(st.D);
+        st.N = ldexp(st.N, -e);
+        st.D = ldexp(st.D, -e);
+        st.Y = ldexp(st.Y, -e);
+    }
 }
 
 // Half-sweep along ray `ray` from its far end to O for Doppler offset xq of this lane.
@@ -151,20 +181,22 @@ __device__ HalfState half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::
     const T2 *lc = reinterpret_cast<const T2 *>(a.lc);
     const int lane = threadIdx.x;
     HalfState st;
-    st.Q = 1.0;
-    st.y = ib;
+    st.N = 1.0;
+    st.D = 1.0;
+    st.Y = ib;
     st.Dm = 0.0;
     const int64_t base = O * a.n_rays + ray;
     const int64_t beg = a.roff[base];
     const int L = (int)(a.roff[base + 1] - beg);
     if (L == 0) return st;
     const double nx = a.dir[3 * ray], ny = a.dir[3 * ray + 1], nz = a.dir[3 * ray + 2];
-    T x_cur = 0, k_cur = 0, S_e = 0, chi_prev = 0;
+    T x_cur = 0, k_cur = 0, S_e = 0, chi_prev = 0, g_cur = 0;
     for (int b0 = 0; b0 < L; b0 += kWave - 1) {
         __syncthreads();
         // ---- stage nodes b0 .. b0+63 in sweep order (far end first, O last)
         const int s = b0 + lane;
-        double Zs = 0.0, sv = 0.0, vw = 1.0;
+        double Zs = 0.0, sv = 0.0, vw = 1.0, an = 0.0, bn = 0.0;
+        T k0 = 0, S0 = 0, k1 = 0, S1 = 0;
         if (s <= L) {
             int64_t cidx = (s < L) ? (int64_t)a.rcells[beg + (L - 1 - s)] : O;
             const CellRec c = a.cell[cidx];
@@ -173,37 +205,59 @@ __device__ HalfState half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::
             double dvx = c.vx - cO.vx, dvy = c.vy - cO.vy, dvz = c.vz - cO.vz;
             sv = (dvx * nx + dvy * ny) + dvz * nz;
             vw = c.vw;
-            NodeRec<T> r;
-            r.a = (T)(cO.vw / vw);
-            r.b = (T)(sv / vw);
+            an = cO.vw / vw;
+            bn = sv / vw;
             T2 c0 = lc[cidx * a.n_lines + line0];
-            r.kap[0] = c0.x;
-            r.S[0] = c0.y;
+            k0 = c0.x;
+            S0 = c0.y;
             if (nlw > 1) {
                 T2 c1 = lc[cidx * a.n_lines + line0 + 1];
-                r.kap[1] = c1.x;
-                r.S[1] = c1.y;
-            } else {
-                r.kap[1] = 0;
-                r.S[1] = 0;
+                k1 = c1.x;
+                S1 = c1.y;
             }
-            r.dzh = 0;
-            r.m = 1;
-            rec[lane] = r;
         }
         const double Zn = __shfl_down(Zs, 1), sn = __shfl_down(sv, 1), vwn = __shfl_down(vw, 1);
-        if (s < L && lane < kWave - 1) {
-            // velocity sub-steps (Sec. 3.2): split when the projected velocity changes by
-            // more than f_sub of the smaller line-width speed
-            double ds = fabs(sn - sv);
-            double thr = a.f_sub * fmin(vw, vwn);
-            int m = 1;
-            if (ds > thr) {
-                const double mr = ceil(ds / thr);
-                m = mr < (double)kMaxSub ? (int)mr : kMaxSub;
+        const double an1 = __shfl_down(an, 1), bn1 = __shfl_down(bn, 1);
+        const T k0n = __shfl_down(k0, 1), S0n = __shfl_down(S0, 1);
+        const T k1n = __shfl_down(k1, 1), S1n = __shfl_down(S1, 1);
+        if (s <= L) {
+            NodeRec<T> r;
+            r.a = (T)an;
+            r.b = (T)bn;
+            r.kap[0] = k0;
+            r.S[0] = S0;
+            r.kap[1] = k1;
+            r.S[1] = S1;
+            r.m = 1;
+            r.K = 64;
+            r.dzh = 0;
+            r.da = r.db = 0;
+            r.dk[0] = r.dk[1] = r.dS[0] = r.dS[1] = 0;
+            if (s < L && lane < kWave - 1) {
+                // velocity sub-steps (Sec. 3.2): split when the projected velocity changes
+                // by more than f_sub of the smaller line-width speed
+                const double ds = fabs(sn - sv);
+                const double thr = a.f_sub * fmin(vw, vwn);
+                int m = 1;
+                if (ds > thr) {
+                    const double mr = ceil(ds / thr);
+                    m = mr < (double)kMaxSub ? (int)mr : kMaxSub;
+                }
+                const double im = 1.0 / (double)m;
+                r.m = m;
+                r.dzh = (T)(0.5 * (Zs - Zn) * im);
+                r.da = (T)((an1 - an) * im);
+                r.db = (T)((bn1 - bn) * im);
+                r.dk[0] = (T)((k0n - k0) * (T)im);
+                r.dS[0] = (T)((S0n - S0) * (T)im);
+                r.dk[1] = (T)((k1n - k1) * (T)im);
+                r.dS[1] = (T)((S1n - S1) * (T)im);
+                // bound on |dx| over every frequency of the quadrature; the recurrence of
+                // the profile restarts after at most 16 widths of travel in x
+                const double maxdx = (fabs(an1 - an) * a.xq_max + fabs(bn1 - bn)) * im;
+                r.K = maxdx > 4.0 ? 0 : (maxdx > 0.25 ? (int)(16.0 / maxdx) : 64);
             }
-            rec[lane].m = m;
-            rec[lane].dzh = (T)(0.5 * (Zs - Zn) / (double)m);
+            rec[lane] = r;
         }
         __syncthreads();
         // ---- sweep the staged segments
@@ -212,29 +266,84 @@ __device__ HalfState half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::
             x_cur = rec[0].a * xq - rec[0].b;
             k_cur = rec[0].kap[slot];
             S_e = rec[0].S[slot];
-            chi_prev = k_cur * profile(x_cur);
+            g_cur = profile(x_cur);
+            chi_prev = k_cur * g_cur;
         }
         for (int i = 0; i < nseg; ++i) {
             const int m = rec[i].m;
             const T dzh = rec[i].dzh;
-            const T an = rec[i + 1].a, bn = rec[i + 1].b;
+            const T xn = rec[i + 1].a * xq - rec[i + 1].b;
             const T kn = rec[i + 1].kap[slot], Sn = rec[i + 1].S[slot];
-            const T xn = an * xq - bn;
-            if (m > 1) {
-                const T inv_m = (T)1 / (T)m;
-                const T dx = (xn - x_cur) * inv_m, dk = (kn - k_cur) * inv_m, dS = (Sn - S_e) * inv_m;
-                const T S0 = S_e;
-                for (int j = 1; j < m; ++j) {
-                    const T tj = (T)j;
-                    const T xt = x_cur + tj * dx;
-                    const T kt = k_cur + tj * dk;
-                    const T St = S0 + tj * dS;
-                    elim_step<F32>(kt * profile(xt), St, dzh, chi_prev, S_e, st, a.tau_floor);
+            T gn;
+            if (m == 1) {
+                gn = profile(xn);
+            } else {
+                const T dx = rec[i].da * xq - rec[i].db;
+                const T dk = rec[i].dk[slot], dS = rec[i].dS[slot];
+                const int K = rec[i].K;
+                if (F32 || K == 0) {
+                    const T S0 = S_e;
+                    for (int j = 1; j < m; ++j) {
+                        const T tj = (T)j;
+                        elim_step<F32, true>((k_cur + tj * dk) * profile(x_cur + tj * dx), S0 + tj * dS, dzh,
+                                             chi_prev, S_e, st);
+                    }
+                } else {
+                    // x is linear in the sub-step index j, so g_j = e^{-x_j^2} obeys
+                    // g_{j+1} = g_j r_j, r_{j+1} = r_j c with r_j = e^{-2 x_j dx - dx^2} and
+                    // c = e^{-2 dx^2}.  It starts from the exact value at the segment's
+                    // first node and restarts from exact values every K sub-steps, K such
+                    // that x moves by at most 16 widths in between: a value that
+                    // underflowed (|x| > 27) cannot hide a profile above e^{-121}.
+                    const double c = exp_le700(-2.0 * dx * dx);
+                    double g = g_cur, r = exp_le700(fmin(-(2.0 * x_cur + dx) * dx, 700.0));
+                    double kt = k_cur, St = S_e;
+                    const double kc = k_cur, Sc = S_e;
+                    for (int j0 = 0; j0 < m - 1; j0 += K) {
+                        if (j0 > 0) {
+                            const double xj = fma((double)j0, dx, x_cur);
+                            g = exp_le700(-(xj * xj));
+                            r = exp_le700(fmin(-(2.0 * xj + dx) * dx, 700.0));
+                            kt = fma((double)j0, dk, kc);
+                            St = fma((double)j0, dS, Sc);
+                        }
+                        const int j1 = min(j0 + K, m - 1);
+                        int j = j0;
+                        // groups of four steps, renormalised once: D grows by at most
+                        // (1 + F)^4 in between, far from overflow for any optical-depth
+                        // step below ~1e37
+                        for (; j + 3 < j1; j += 4) {
+#pragma unroll
+                            for (int u = 0; u < 3; ++u) {
+                                g *= r;
+                                r *= c;
+                                kt += dk;
+                                St += dS;
+                                elim_step<F32, false>(kt * g, St, dzh, chi_prev, S_e, st);
+                            }
+                            g *= r;
+                            r *= c;
+                            kt += dk;
+                            St += dS;
+                            elim_step<F32, true>(kt * g, St, dzh, chi_prev, S_e, st);
+                        }
+                        for (; j < j1; ++j) {
+                            g *= r;
+                            r *= c;
+                            kt += dk;
+                            St += dS;
+                            elim_step<F32, true>(kt * g, St, dzh, chi_prev, S_e, st);
+                        }
+                    }
                 }
+                // the cell at the end of the segment gets its exact profile, so every
+                // segment's recurrence starts from an exact value
+                gn = profile(xn);
             }
-            elim_step<F32>(kn * profile(xn), Sn, dzh, chi_prev, S_e, st, a.tau_floor);
+            elim_step<F32, true>(kn * gn, Sn, dzh, chi_prev, S_e, st);
             x_cur = xn;
             k_cur = kn;
+            g_cur = gn;
         }
     }
     return st;
@@ -294,9 +403,10 @@ __global__ __launch_bounds__(64) void k_formal_solve(SolveArgs a)
             // u pairs I(n, x) with I(-n, -x): the antipode sweeps at the mirrored offset
             HalfState hf = half_sweep<F32>(a, rec, O, cO, r, (T)xq, slot, line0, nlw, ib);
             HalfState hb = half_sweep<F32>(a, rec, O, cO, rb, (T)(-xq), slot, line0, nlw, ib);
+            const double idf = 1.0 / hf.D, idb = 1.0 / hb.D;
             const double h = 0.5 * (hf.Dm + hb.Dm);
-            const double inv = 1.0 / (h + hf.Q + hb.Q);
-            const double yy = hf.y + hb.y;
+            const double inv = 1.0 / (h + fma(hf.N, idf, hb.N * idb));
+            const double yy = fma(hf.Y, idf, hb.Y * idb);
             accJ += (Acc)(wq * (fma(h, S_O, yy) * inv));
             accL += (Acc)(wq * (h * inv));
             accE += (Acc)(wq * (yy * inv));

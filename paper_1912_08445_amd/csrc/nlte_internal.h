@@ -70,7 +70,7 @@ struct SolveArgs {
     const double *qx, *qw;   // [n_q]
     const double *ibdy;      // [n_lines] boundary intensity
     double f_sub;
-    double tau_floor;
+    double xq_max;           // max |x_q| of the quadrature
     double norm;             // 2 / n_rays
     int64_t P;
     int n_rays, n_pairs, n_q, n_lines;
@@ -125,6 +125,7 @@ struct nlte_ctx {
     int n_q = 0;
     double *d_qx = nullptr, *d_qw = nullptr;
     double *d_ibdy = nullptr;
+    double xq_max = 0.0;
 
     // ray cache
     bool traced = false;

@@ -101,7 +101,7 @@ def test_table1_species_fixture():
 # ---------------------------------------------------------------- Feautrier solve
 
 
-def dense_system(z, chi, S, I_lo, I_hi, tau_floor=1e-30):
+def dense_system(z, chi, S, I_lo, I_hi, tau_floor=1e-100):
     """Dense matrix of the discretised second-order equation: centred second
     differences inside, second-order (Taylor) boundary rows at both ends."""
     N = len(z)
