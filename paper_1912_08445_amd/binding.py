@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnlte.so")
+# NLTE_LIB selects another build of the library (same ABI); default: the in-tree one
+LIB_PATH = os.environ.get("NLTE_LIB") or os.path.join(_HERE, "libnlte.so")
 
 NLTE_OK = 0
 NLTE_E_INVALID_ARG = -1

@@ -143,15 +143,13 @@ SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
     a.n_pairs = c->n_pairs;
     a.n_q = c->n_q;
     a.n_lines = c->n_lines;
-    if (c->n_q <= kWave) {
-        a.lines_per_wave = std::min(2, kWave / c->n_q);
-        a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
-        a.fchunks = 1;
-    } else {
-        a.lines_per_wave = 0;
-        a.groups = c->n_lines;
-        a.fchunks = (c->n_q + kWave - 1) / kWave;
-    }
+    // A wave takes one or two groups of n_q lanes (one frequency each) and LPL lines per
+    // group (1 or 2; more lines per lane exceed the register budget of the sweep).
+    const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
+    a.fchunks = (c->n_q <= kWave) ? 1 : (c->n_q + kWave - 1) / kWave;
+    const int lpl = std::min(2, (c->n_lines + ngrp - 1) / ngrp);
+    a.lines_per_wave = ngrp * lpl;
+    a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
     a.n_blocks = c->P * a.groups;
     a.J = J;
     a.Jeff = Jeff;

@@ -92,21 +92,30 @@ struct Bulk<true> {
     using T2 = float2;
 };
 
+// A wave serves one origin point, one frequency per lane and NLW = 2 LPL lines: lanes
+// [0, n_q) handle lines line0 .. line0+LPL-1 ("group" 0), lanes [n_q, 2 n_q) the next LPL
+// lines (group 1).  The Doppler offset of a node depends on the frequency only (the line
+// width is proportional to the line frequency), so the profile and its recurrence are
+// shared by the LPL lines of a lane; only kappa, S and the elimination state are per line.
+
 // One staged node of a half ray.  (a, b) give the Doppler offset of a lane's frequency
 // x_q at this node as x = a x_q - b.  The segment to the next node toward O has m
-// sub-intervals of half-length dzh; per sub-interval x changes by da x_q - db and kappa,
-// S by dk, dS (per staged line); K is the restart interval of the profile recurrence.
-template <typename T>
+// sub-intervals of length 4 dzq; per sub-interval x changes by da x_q - db.  maxdx bounds
+// |dx| over all frequencies, K is the restart interval of the profile recurrence (0:
+// evaluate every profile directly).  kap, S: line-centre opacity and source function of
+// the wave's lines.
+template <typename T, int NLW>
 struct NodeRec {
-    T a, b, dzh, da, db;
-    T kap[2], S[2], dk[2], dS[2];
+    T a, b, dzq, da, db, inv_m, maxdx;
     int m, K;
+    T kap[NLW], S[NLW];
 };
 
 // Elimination state of a half sweep in homogeneous form: the Rybicki-Hummer quantities
-// Q = N / D and y = Y / D (see the file comment), and the previous optical-depth step.
+// Q = N / D and y = Y / D (see the file comment), and Hm, half the previous
+// optical-depth step.
 struct HalfState {
-    double N, D, Y, Dm;
+    double N, D, Y, Hm;
 };
 
 // e^y for y <= 700 in FP64: y = n ln2 + r with |r| <= ln2/2 (two-part ln2), e^r by its
@@ -134,6 +143,25 @@ __device__ __forceinline__ double exp_le700(double y)
     return ldexp(p, ni);
 }
 
+// e^{-u} for 0 <= u <= 0.5 by its degree-13 Taylor polynomial (truncation < 1e-15).
+__device__ __forceinline__ double exp_neg_small(double u)
+{
+    double p = -1.60590438368216145994e-10;          // -1/13!
+    p = fma(p, u, 2.08767569878680989792e-09);       // 1/12!
+    p = fma(p, u, -2.50521083854417187751e-08);
+    p = fma(p, u, 2.75573192239858906526e-07);
+    p = fma(p, u, -2.75573192239858906526e-06);
+    p = fma(p, u, 2.48015873015873015873e-05);
+    p = fma(p, u, -1.98412698412698412698e-04);
+    p = fma(p, u, 1.38888888888888888889e-03);
+    p = fma(p, u, -8.33333333333333333333e-03);
+    p = fma(p, u, 4.16666666666666666667e-02);
+    p = fma(p, u, -1.66666666666666666667e-01);
+    p = fma(p, u, 0.5);
+    p = fma(p, u, -1.0);
+    return fma(p, u, 1.0);
+}
+
 __device__ __forceinline__ double profile(double x) { return exp_le700(-(x * x)); }
 __device__ __forceinline__ float profile(float x)
 {
@@ -141,26 +169,25 @@ __device__ __forceinline__ float profile(float x)
     return __builtin_amdgcn_exp2f(-(x * x) * 1.44269504088896340736f);
 }
 
-// One elimination step: node with source S_e (between optical-depth steps Dm and Dp) is
-// eliminated.  With h = (Dm + Dp)/2 the Rybicki-Hummer update
-//   T = h + Q, E = 1/(1 + Dp T), Q' = T E, y' = (S h + y) E
+// One elimination step.  a_prev, a_t are chi dz/4 at the two ends of the step, so
+// Hp = a_prev + a_t is half its trapezoid optical depth D_+, and h = Hm + Hp.  The
+// Rybicki-Hummer update  T = h + Q, E = 1/(1 + D_+ T), Q' = T E, y' = (S h + y) E
 // becomes, for Q = N/D and y = Y/D,
-//   N' = N + h D,  Y' = Y + S h D,  D' = D + Dp N'
-// (only products and sums of non-negative numbers).  RENORM rescales N, D, Y by the
+//   N' = N + h D,  Y' = Y + S h D,  D' = D + D_+ N'
+// (products and sums of non-negative numbers only).  RENORM rescales N, D, Y by the
 // power of two that brings D into [0.5, 1), which is exact.
 template <bool F32, bool RENORM>
-__device__ __forceinline__ void elim_step(typename Bulk<F32>::T chi_t, typename Bulk<F32>::T S_t,
-                                          typename Bulk<F32>::T dzh, typename Bulk<F32>::T &chi_prev,
-                                          typename Bulk<F32>::T &S_e, HalfState &st)
+__device__ __forceinline__ void elim_step(typename Bulk<F32>::T a_t, typename Bulk<F32>::T S_t,
+                                          typename Bulk<F32>::T &a_prev, typename Bulk<F32>::T &S_e,
+                                          HalfState &st)
 {
-    // trapezoid optical depth of the step; zero is allowed (nothing divides by it)
-    const double Dp = (double)((chi_prev + chi_t) * dzh);
-    const double hD = (0.5 * (st.Dm + Dp)) * st.D;
+    const double Hp = (double)(a_prev + a_t);
+    const double hD = (st.Hm + Hp) * st.D;
     st.N = st.N + hD;
     st.Y = fma((double)S_e, hD, st.Y);
-    st.D = fma(Dp, st.N, st.D);
-    st.Dm = Dp;
-    chi_prev = chi_t;
+    st.D = fma(Hp + Hp, st.N, st.D);
+    st.Hm = Hp;
+    a_prev = a_t;
     S_e = S_t;
     if (RENORM) {
         const int e = __builtin_amdgcn_frexp_exp(st.D);
@@ -170,35 +197,67 @@ __device__ __forceinline__ void elim_step(typename Bulk<F32>::T chi_t, typename 
     }
 }
 
+// Per-line state of a lane during a half sweep.
+template <typename T, int LPL>
+struct LineState {
+    HalfState st[LPL];
+    T k_cur[LPL], S_e[LPL], chi_cur[LPL];
+};
+
+// One recurrence step of all LPL lines: g <- g r, r <- r c (shared), then the linear
+// kappa dz/4 and S of each line and its elimination step.
+template <bool F32, int LPL, bool RENORM>
+__device__ __forceinline__ void recur_step(double &g, double &r, double c, double (&kq)[LPL],
+                                           const double (&dkq)[LPL], double (&St)[LPL],
+                                           const double (&dS)[LPL], typename Bulk<F32>::T (&a_prev)[LPL],
+                                           LineState<typename Bulk<F32>::T, LPL> &ls)
+{
+    g *= r;
+    r *= c;
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+        kq[l] += dkq[l];
+        St[l] += dS[l];
+        elim_step<F32, RENORM>(kq[l] * g, St[l], a_prev[l], ls.S_e[l], ls.st[l]);
+    }
+}
+
 // Half-sweep along ray `ray` from its far end to O for Doppler offset xq of this lane.
-template <bool F32>
-__device__ HalfState half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T> *rec, int64_t O,
-                                const CellRec &cO, int ray, typename Bulk<F32>::T xq, int slot,
-                                int line0, int nlw, double ib)
+// The result is left in ls.st (one HalfState per line of the lane).
+template <bool F32, int LPL>
+__device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 * LPL> *rec, int64_t O,
+                           const CellRec &cO, int ray, typename Bulk<F32>::T xq, int grp, int line0,
+                           int nlw, const double (&ib)[LPL], LineState<typename Bulk<F32>::T, LPL> &ls)
 {
     using T = typename Bulk<F32>::T;
     using T2 = typename Bulk<F32>::T2;
+    constexpr int NLW = 2 * LPL;
     const T2 *lc = reinterpret_cast<const T2 *>(a.lc);
     const int lane = threadIdx.x;
-    HalfState st;
-    st.N = 1.0;
-    st.D = 1.0;
-    st.Y = ib;
-    st.Dm = 0.0;
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+        ls.st[l].N = 1.0;
+        ls.st[l].D = 1.0;
+        ls.st[l].Y = ib[l];
+        ls.st[l].Hm = 0.0;
+    }
     const int64_t base = O * a.n_rays + ray;
     const int64_t beg = a.roff[base];
     const int L = (int)(a.roff[base + 1] - beg);
-    if (L == 0) return st;
+    if (L == 0) return;
     const double nx = a.dir[3 * ray], ny = a.dir[3 * ray + 1], nz = a.dir[3 * ray + 2];
-    T x_cur = 0, k_cur = 0, S_e = 0, chi_prev = 0, g_cur = 0;
+    // x_cur, g_cur: Doppler offset and profile at the current node; travel bounds how far
+    // x moved (any lane) since g was last evaluated exactly
+    T x_cur = 0, g_cur = 0;
+    double travel = 0.0;
     for (int b0 = 0; b0 < L; b0 += kWave - 1) {
         __syncthreads();
         // ---- stage nodes b0 .. b0+63 in sweep order (far end first, O last)
         const int s = b0 + lane;
         double Zs = 0.0, sv = 0.0, vw = 1.0, an = 0.0, bn = 0.0;
-        T k0 = 0, S0 = 0, k1 = 0, S1 = 0;
+        int64_t cidx = O;
         if (s <= L) {
-            int64_t cidx = (s < L) ? (int64_t)a.rcells[beg + (L - 1 - s)] : O;
+            cidx = (s < L) ? (int64_t)a.rcells[beg + (L - 1 - s)] : O;
             const CellRec c = a.cell[cidx];
             double dx = c.px - cO.px, dy = c.py - cO.py, dz = c.pz - cO.pz;
             Zs = (dx * nx + dy * ny) + dz * nz;
@@ -207,32 +266,24 @@ __device__ HalfState half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::
             vw = c.vw;
             an = cO.vw / vw;
             bn = sv / vw;
-            T2 c0 = lc[cidx * a.n_lines + line0];
-            k0 = c0.x;
-            S0 = c0.y;
-            if (nlw > 1) {
-                T2 c1 = lc[cidx * a.n_lines + line0 + 1];
-                k1 = c1.x;
-                S1 = c1.y;
-            }
         }
         const double Zn = __shfl_down(Zs, 1), sn = __shfl_down(sv, 1), vwn = __shfl_down(vw, 1);
         const double an1 = __shfl_down(an, 1), bn1 = __shfl_down(bn, 1);
-        const T k0n = __shfl_down(k0, 1), S0n = __shfl_down(S0, 1);
-        const T k1n = __shfl_down(k1, 1), S1n = __shfl_down(S1, 1);
         if (s <= L) {
-            NodeRec<T> r;
+            NodeRec<T, NLW> r;
             r.a = (T)an;
             r.b = (T)bn;
-            r.kap[0] = k0;
-            r.S[0] = S0;
-            r.kap[1] = k1;
-            r.S[1] = S1;
+#pragma unroll
+            for (int l = 0; l < NLW; ++l) {
+                T2 cl = l < nlw ? lc[cidx * a.n_lines + line0 + l] : T2{0, 0};
+                r.kap[l] = cl.x;
+                r.S[l] = cl.y;
+            }
             r.m = 1;
             r.K = 64;
-            r.dzh = 0;
-            r.da = r.db = 0;
-            r.dk[0] = r.dk[1] = r.dS[0] = r.dS[1] = 0;
+            r.dzq = 0;
+            r.da = r.db = r.maxdx = 0;
+            r.inv_m = 1;
             if (s < L && lane < kWave - 1) {
                 // velocity sub-steps (Sec. 3.2): split when the projected velocity changes
                 // by more than f_sub of the smaller line-width speed
@@ -245,16 +296,14 @@ __device__ HalfState half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::
                 }
                 const double im = 1.0 / (double)m;
                 r.m = m;
-                r.dzh = (T)(0.5 * (Zs - Zn) * im);
+                r.inv_m = (T)im;
+                r.dzq = (T)(0.25 * (Zs - Zn) * im);
                 r.da = (T)((an1 - an) * im);
                 r.db = (T)((bn1 - bn) * im);
-                r.dk[0] = (T)((k0n - k0) * (T)im);
-                r.dS[0] = (T)((S0n - S0) * (T)im);
-                r.dk[1] = (T)((k1n - k1) * (T)im);
-                r.dS[1] = (T)((S1n - S1) * (T)im);
                 // bound on |dx| over every frequency of the quadrature; the recurrence of
                 // the profile restarts after at most 16 widths of travel in x
                 const double maxdx = (fabs(an1 - an) * a.xq_max + fabs(bn1 - bn)) * im;
+                r.maxdx = (T)maxdx;
                 r.K = maxdx > 4.0 ? 0 : (maxdx > 0.25 ? (int)(16.0 / maxdx) : 64);
             }
             rec[lane] = r;
@@ -264,99 +313,137 @@ __device__ HalfState half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::
         const int nseg = min(kWave - 1, L - b0);
         if (b0 == 0) {
             x_cur = rec[0].a * xq - rec[0].b;
-            k_cur = rec[0].kap[slot];
-            S_e = rec[0].S[slot];
             g_cur = profile(x_cur);
-            chi_prev = k_cur * g_cur;
+#pragma unroll
+            for (int l = 0; l < LPL; ++l) {
+                ls.k_cur[l] = rec[0].kap[grp * LPL + l];
+                ls.S_e[l] = rec[0].S[grp * LPL + l];
+                ls.chi_cur[l] = ls.k_cur[l] * g_cur;
+            }
         }
         for (int i = 0; i < nseg; ++i) {
             const int m = rec[i].m;
-            const T dzh = rec[i].dzh;
+            const T dzq = rec[i].dzq;
             const T xn = rec[i + 1].a * xq - rec[i + 1].b;
-            const T kn = rec[i + 1].kap[slot], Sn = rec[i + 1].S[slot];
+            T kn[LPL], Sn[LPL], a_prev[LPL];
+#pragma unroll
+            for (int l = 0; l < LPL; ++l) {
+                kn[l] = rec[i + 1].kap[grp * LPL + l];
+                Sn[l] = rec[i + 1].S[grp * LPL + l];
+                a_prev[l] = ls.chi_cur[l] * dzq;
+            }
             T gn;
             if (m == 1) {
                 gn = profile(xn);
+                travel = 0.0;
             } else {
+                const T im = rec[i].inv_m;
                 const T dx = rec[i].da * xq - rec[i].db;
-                const T dk = rec[i].dk[slot], dS = rec[i].dS[slot];
                 const int K = rec[i].K;
                 if (F32 || K == 0) {
-                    const T S0 = S_e;
+                    T S0[LPL], dk[LPL], dS[LPL];
+#pragma unroll
+                    for (int l = 0; l < LPL; ++l) {
+                        S0[l] = ls.S_e[l];
+                        dk[l] = (kn[l] - ls.k_cur[l]) * im;
+                        dS[l] = (Sn[l] - S0[l]) * im;
+                    }
                     for (int j = 1; j < m; ++j) {
                         const T tj = (T)j;
-                        elim_step<F32, true>((k_cur + tj * dk) * profile(x_cur + tj * dx), S0 + tj * dS, dzh,
-                                             chi_prev, S_e, st);
+                        const T gq = profile(x_cur + tj * dx) * dzq;
+#pragma unroll
+                        for (int l = 0; l < LPL; ++l)
+                            elim_step<F32, true>((ls.k_cur[l] + tj * dk[l]) * gq, S0[l] + tj * dS[l], a_prev[l],
+                                                 ls.S_e[l], ls.st[l]);
                     }
+                    gn = profile(xn);
+                    travel = 0.0;
                 } else {
                     // x is linear in the sub-step index j, so g_j = e^{-x_j^2} obeys
                     // g_{j+1} = g_j r_j, r_{j+1} = r_j c with r_j = e^{-2 x_j dx - dx^2} and
-                    // c = e^{-2 dx^2}.  It starts from the exact value at the segment's
-                    // first node and restarts from exact values every K sub-steps, K such
-                    // that x moves by at most 16 widths in between: a value that
+                    // c = e^{-2 dx^2}.  Values are recomputed exactly whenever x may have
+                    // moved by more than 16 widths since the last exact value, so one that
                     // underflowed (|x| > 27) cannot hide a profile above e^{-121}.
-                    const double c = exp_le700(-2.0 * dx * dx);
-                    double g = g_cur, r = exp_le700(fmin(-(2.0 * x_cur + dx) * dx, 700.0));
-                    double kt = k_cur, St = S_e;
-                    const double kc = k_cur, Sc = S_e;
-                    for (int j0 = 0; j0 < m - 1; j0 += K) {
-                        if (j0 > 0) {
-                            const double xj = fma((double)j0, dx, x_cur);
-                            g = exp_le700(-(xj * xj));
-                            r = exp_le700(fmin(-(2.0 * xj + dx) * dx, 700.0));
-                            kt = fma((double)j0, dk, kc);
-                            St = fma((double)j0, dS, Sc);
-                        }
-                        const int j1 = min(j0 + K, m - 1);
-                        int j = j0;
-                        // groups of four steps, renormalised once: D grows by at most
-                        // (1 + F)^4 in between, far from overflow for any optical-depth
-                        // step below ~1e37
-                        for (; j + 3 < j1; j += 4) {
+                    const double mdx = (double)rec[i].maxdx;
+                    const double u2 = 2.0 * dx * dx;
+                    const double c = mdx <= 0.5 ? exp_neg_small(u2) : exp_le700(-u2);
+                    double kq0[LPL], dkq[LPL], Sc[LPL], dS[LPL], kq[LPL], St[LPL];
 #pragma unroll
-                            for (int u = 0; u < 3; ++u) {
-                                g *= r;
-                                r *= c;
-                                kt += dk;
-                                St += dS;
-                                elim_step<F32, false>(kt * g, St, dzh, chi_prev, S_e, st);
-                            }
-                            g *= r;
-                            r *= c;
-                            kt += dk;
-                            St += dS;
-                            elim_step<F32, true>(kt * g, St, dzh, chi_prev, S_e, st);
-                        }
-                        for (; j < j1; ++j) {
-                            g *= r;
-                            r *= c;
-                            kt += dk;
-                            St += dS;
-                            elim_step<F32, true>(kt * g, St, dzh, chi_prev, S_e, st);
-                        }
+                    for (int l = 0; l < LPL; ++l) {
+                        kq0[l] = (double)(ls.k_cur[l] * dzq);
+                        dkq[l] = (double)((kn[l] - ls.k_cur[l]) * im * dzq);
+                        Sc[l] = (double)ls.S_e[l];
+                        dS[l] = (double)((Sn[l] - ls.S_e[l]) * im);
+                        kq[l] = kq0[l];
+                        St[l] = Sc[l];
                     }
+                    double g = g_cur, r = exp_le700(fmin(-(2.0 * x_cur + dx) * dx, 700.0));
+                    int budget = K;
+                    if (mdx > 0.0) budget = (int)fminf((16.0f - (float)travel) * __builtin_amdgcn_rcpf((float)mdx),
+                                                       (float)K);
+                    if (budget < 1) {
+                        g = profile((double)x_cur);
+                        travel = 0.0;
+                        budget = K;
+                    }
+                    int j = 0;
+                    for (;;) {
+                        const int jend = min(j + budget, m);
+                        const int jint = min(jend, m - 1);
+                        int jj = j;
+                        for (; jj + 3 < jint; jj += 4) {
+                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, true>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                        }
+                        for (; jj < jint; ++jj) recur_step<F32, LPL, true>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                        travel += mdx * (double)(jint - j);
+                        j = jint;
+                        if (jend == m) {
+                            g *= r;          // the cell at the end of the segment
+                            travel += mdx;
+                            break;
+                        }
+                        const double xj = fma((double)j, dx, (double)x_cur);
+                        g = exp_le700(-(xj * xj));
+                        r = exp_le700(fmin(-(2.0 * xj + dx) * dx, 700.0));
+#pragma unroll
+                        for (int l = 0; l < LPL; ++l) {
+                            kq[l] = fma((double)j, dkq[l], kq0[l]);
+                            St[l] = fma((double)j, dS[l], Sc[l]);
+                        }
+                        travel = 0.0;
+                        budget = K;
+                    }
+                    gn = g;
                 }
-                // the cell at the end of the segment gets its exact profile, so every
-                // segment's recurrence starts from an exact value
-                gn = profile(xn);
             }
-            elim_step<F32, true>(kn * gn, Sn, dzh, chi_prev, S_e, st);
+#pragma unroll
+            for (int l = 0; l < LPL; ++l) {
+                const T chi_n = kn[l] * gn;
+                elim_step<F32, true>(chi_n * dzq, Sn[l], a_prev[l], ls.S_e[l], ls.st[l]);
+                ls.k_cur[l] = kn[l];
+                ls.chi_cur[l] = chi_n;
+            }
             x_cur = xn;
-            k_cur = kn;
             g_cur = gn;
         }
     }
-    return st;
 }
 
-template <bool F32>
-__global__ __launch_bounds__(64) void k_formal_solve(SolveArgs a)
+// Occupancy hint: at least 3 waves per SIMD (4 with one line per lane).  Measured on
+// the 50,000-point outflow model this beats the compiler's default register budget
+// (two waves) even though a few bytes of the sweep's live values then go to scratch.
+template <bool F32, int LPL>
+__global__ __launch_bounds__(64, LPL == 1 ? 4 : 3) void k_formal_solve(SolveArgs a)
 {
     using T = typename Bulk<F32>::T;
     using T2 = typename Bulk<F32>::T2;
     using Acc = typename Bulk<F32>::T;
-    __shared__ NodeRec<T> rec[kWave];
-    __shared__ double red[3][kWave];
+    constexpr int NLW = 2 * LPL;
+    __shared__ NodeRec<T, NLW> rec[kWave];
+    __shared__ double red[3][LPL][kWave];
     const int lane = threadIdx.x;
     // Consecutive hardware workgroups go round-robin to the 8 XCDs; give each XCD a
     // contiguous range of origin points so that the cells their rays share stay in
@@ -365,82 +452,103 @@ __global__ __launch_bounds__(64) void k_formal_solve(SolveArgs a)
     const int64_t lb = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
     if (lb >= a.n_blocks) return;
     const int64_t O = lb / a.groups;
-    const int g = (int)(lb - O * a.groups);
+    const int w = (int)(lb - O * a.groups);
 
-    int slot, nidx0, line, line0, nlw;
-    bool active;
-    if (a.lines_per_wave > 0) {
-        slot = lane / a.n_q;
-        nidx0 = lane - slot * a.n_q;
-        line0 = g * a.lines_per_wave;
-        line = line0 + slot;
-        nlw = min(a.lines_per_wave, a.n_lines - line0);
-        active = slot < a.lines_per_wave && line < a.n_lines;
+    // lane -> (group, frequency); a wave owns lines line0 .. line0 + nlw - 1
+    const int ngrp = a.lines_per_wave / LPL;     // 1 or 2 groups of lanes
+    const int line0 = w * a.lines_per_wave;
+    const int nlw = min(a.lines_per_wave, a.n_lines - line0);
+    int grp, nidx0;
+    if (a.fchunks == 1) {
+        grp = lane / a.n_q;
+        nidx0 = lane - grp * a.n_q;
     } else {
-        slot = 0;
+        grp = 0;
         nidx0 = lane;
-        line0 = g;
-        line = g;
-        nlw = 1;
-        active = true;
     }
-    if (!active) {
-        slot = 0;
-        line = line0;
-    }
+    const bool lane_ok = grp < ngrp;
+    if (!lane_ok) grp = 0;
     const T2 *lc = reinterpret_cast<const T2 *>(a.lc);
     const CellRec cO = a.cell[O];
-    const double S_O = (double)lc[O * a.n_lines + line].y;
-    const double ib = a.ibdy[line];
-    Acc accJ = 0, accL = 0, accE = 0;
+    double S_O[LPL], ib[LPL];
+    bool lact[LPL];
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+        const int li = grp * LPL + l;
+        lact[l] = lane_ok && li < nlw;
+        const int line = line0 + (li < nlw ? li : 0);
+        S_O[l] = (double)lc[O * a.n_lines + line].y;
+        ib[l] = a.ibdy[line];
+    }
+    Acc accJ[LPL], accL[LPL], accE[LPL];
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) accJ[l] = accL[l] = accE[l] = 0;
+    LineState<T, LPL> ls;
     for (int p = 0; p < a.n_pairs; ++p) {
         const int r = a.pair_r[p], rb = a.anti[r];
         for (int c = 0; c < a.fchunks; ++c) {
-            const int nidx = (a.lines_per_wave > 0) ? nidx0 : c * kWave + lane;
-            const bool act = active && nidx < a.n_q;
+            const int nidx = (a.fchunks == 1) ? nidx0 : c * kWave + lane;
+            const bool act = lane_ok && nidx < a.n_q;
             const double xq = act ? a.qx[nidx] : 0.0;
             const double wq = act ? a.qw[nidx] : 0.0;
             // u pairs I(n, x) with I(-n, -x): the antipode sweeps at the mirrored offset
-            HalfState hf = half_sweep<F32>(a, rec, O, cO, r, (T)xq, slot, line0, nlw, ib);
-            HalfState hb = half_sweep<F32>(a, rec, O, cO, rb, (T)(-xq), slot, line0, nlw, ib);
-            const double idf = 1.0 / hf.D, idb = 1.0 / hb.D;
-            const double h = 0.5 * (hf.Dm + hb.Dm);
-            const double inv = 1.0 / (h + fma(hf.N, idf, hb.N * idb));
-            const double yy = fma(hf.Y, idf, hb.Y * idb);
-            accJ += (Acc)(wq * (fma(h, S_O, yy) * inv));
-            accL += (Acc)(wq * (h * inv));
-            accE += (Acc)(wq * (yy * inv));
+            half_sweep<F32, LPL>(a, rec, O, cO, r, (T)xq, grp, line0, nlw, ib, ls);
+            double Qf[LPL], yf[LPL], Hf[LPL];
+#pragma unroll
+            for (int l = 0; l < LPL; ++l) {
+                const double id = 1.0 / ls.st[l].D;
+                Qf[l] = ls.st[l].N * id;
+                yf[l] = ls.st[l].Y * id;
+                Hf[l] = ls.st[l].Hm;
+            }
+            half_sweep<F32, LPL>(a, rec, O, cO, rb, (T)(-xq), grp, line0, nlw, ib, ls);
+#pragma unroll
+            for (int l = 0; l < LPL; ++l) {
+                const double id = 1.0 / ls.st[l].D;
+                const double h = Hf[l] + ls.st[l].Hm;
+                const double inv = 1.0 / (h + fma(ls.st[l].N, id, Qf[l]));
+                const double yy = fma(ls.st[l].Y, id, yf[l]);
+                accJ[l] += (Acc)(wq * (fma(h, S_O[l], yy) * inv));
+                accL[l] += (Acc)(wq * (h * inv));
+                accE[l] += (Acc)(wq * (yy * inv));
+            }
         }
     }
-    red[0][lane] = (double)accJ;
-    red[1][lane] = (double)accL;
-    red[2][lane] = (double)accE;
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+        red[0][l][lane] = lact[l] ? (double)accJ[l] : 0.0;
+        red[1][l][lane] = lact[l] ? (double)accL[l] : 0.0;
+        red[2][l][lane] = lact[l] ? (double)accE[l] : 0.0;
+    }
     __syncthreads();
-    if (a.lines_per_wave > 0) {
-        if (lane < nlw) {
-            Acc sJ = 0, sL = 0, sE = 0;
-            for (int i = lane * a.n_q; i < (lane + 1) * a.n_q; ++i) {
-                sJ += (Acc)red[0][i];
-                sL += (Acc)red[1][i];
-                sE += (Acc)red[2][i];
-            }
-            const int64_t o = O * a.n_lines + line0 + lane;
-            a.J[o] = a.norm * (double)sJ;
-            a.L[o] = a.norm * (double)sL;
-            a.Jeff[o] = a.norm * (double)sE;
-        }
-    } else if (lane == 0) {
+    // lane t < nlw sums line t over the frequencies of its group in a fixed order
+    if (lane < nlw) {
+        const int g = lane / LPL, l = lane - g * LPL;
+        const int n0 = (a.fchunks == 1) ? g * a.n_q : 0;
+        const int n1 = (a.fchunks == 1) ? n0 + a.n_q : kWave;
         Acc sJ = 0, sL = 0, sE = 0;
-        for (int i = 0; i < kWave; ++i) {
-            sJ += (Acc)red[0][i];
-            sL += (Acc)red[1][i];
-            sE += (Acc)red[2][i];
+        for (int i = n0; i < n1; ++i) {
+            sJ += (Acc)red[0][l][i];
+            sL += (Acc)red[1][l][i];
+            sE += (Acc)red[2][l][i];
         }
-        const int64_t o = O * a.n_lines + g;
+        const int64_t o = O * a.n_lines + line0 + lane;
         a.J[o] = a.norm * (double)sJ;
         a.L[o] = a.norm * (double)sL;
         a.Jeff[o] = a.norm * (double)sE;
     }
+}
+
+template <bool F32>
+hipError_t launch_fs(const SolveArgs &a, dim3 grid, hipStream_t s)
+{
+    const int lpl = a.lines_per_wave / (a.fchunks == 1 && 2 * a.n_q <= kWave ? 2 : 1);
+    switch (lpl) {
+    case 1: hipLaunchKernelGGL((k_formal_solve<F32, 1>), grid, dim3(kWave), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_formal_solve<F32, 2>), grid, dim3(kWave), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_formal_solve(const SolveArgs &a, int fp32, hipStream_t s)
@@ -448,11 +556,7 @@ hipError_t launch_formal_solve(const SolveArgs &a, int fp32, hipStream_t s)
     if (a.n_blocks == 0) return hipSuccess;
     const int64_t nb8 = (a.n_blocks + 7) / 8;
     dim3 grid((unsigned)(nb8 * 8));
-    if (fp32)
-        hipLaunchKernelGGL(k_formal_solve<true>, grid, dim3(kWave), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_formal_solve<false>, grid, dim3(kWave), 0, s, a);
-    return hipGetLastError();
+    return fp32 ? launch_fs<true>(a, grid, s) : launch_fs<false>(a, grid, s);
 }
 
 // Elimination steps per frequency over all half rays: the cells of every cached walk

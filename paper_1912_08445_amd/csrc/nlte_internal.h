@@ -75,8 +75,8 @@ struct SolveArgs {
     int64_t P;
     int n_rays, n_pairs, n_q, n_lines;
     int groups;              // waves per point
-    int lines_per_wave;      // > 0 when n_q <= 64
-    int fchunks;             // frequency chunks per wave when n_q > 64
+    int lines_per_wave;      // lines one wave serves (lane groups x lines per lane)
+    int fchunks;             // frequency chunks per wave (n_q > 64), else 1
     int64_t n_blocks;        // logical blocks (P * groups)
     double *J, *Jeff, *L;    // [P][n_lines]
 };

@@ -127,6 +127,24 @@ def test_formal_solve_edge_cases():
     check_solve(w2, s, o, o.lte())
 
 
+def test_formal_solve_line_core_after_far_wing():
+    """A velocity ramp of about 0.3 line widths per cell over 300 cells: every segment
+    has a couple of sub-steps, and each frequency meets the line core only after tens of
+    segments in the far wing where e^{-x^2} underflows.  Guards the profile recurrence
+    against carrying an underflowed value into the core."""
+    n = 300
+    x = np.linspace(-1.5e16, 1.5e16, n)
+    sp = species.two_level(nu=100e9, mass_amu=28.0)
+    vw = np.sqrt(2 * 1.380649e-16 * 20.0 / sp.mass + 1.5e4 ** 2)
+    m = chain_1d(x, 0.3 * vw * np.arange(n), 1e6, 20.0, 1.5e4, 1e-6)
+    qx, qw = directions.uniform_grid(31)
+    w = Workload("ramp", m, sp, directions.axis_pair(), qx, qw)
+    s, o = solver_for(w), oracle_for(w)
+    J, Je, L = check_solve(w, s, o, o.lte())
+    tot, mx, steps = s.trace_stats()
+    assert steps > 1.5 * tot       # sub-steps are present
+
+
 def test_formal_solve_max_levels():
     w = small_outflow(500, seed=8)
     w.species = species.linear_rotor(16)
