@@ -59,6 +59,18 @@ def cpu_baseline(w, target_s=15.0):
 
     import oracle
     oracle.build(force=False)
+    if w.offsets is not None:
+        # models stored back to back: give the oracle global neighbour indices
+        from synth.configs import Workload
+        from synth.models import Model
+        m = w.model
+        nbr = m.nbr.copy()
+        for i in range(w.n_models):
+            o0, o1 = w.offsets[i], w.offsets[i + 1]
+            blk = nbr[o0:o1]
+            blk[blk >= 0] += o0
+        w = Workload(w.name, Model(m.pos, m.vel, m.n_h2, m.temperature, m.v_turb, m.abundance, nbr),
+                     w.species, w.rays, w.quad_x, w.quad_w)
     o = oracle.from_workload(w)
     pops = o.lte()
     rng = np.random.default_rng(12345)
@@ -84,7 +96,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="outflow5", choices=["outflow5", "sphere2", "disc10"])
+    ap.add_argument("--workload", default="outflow5", choices=["outflow5", "sphere2", "disc10", "batch256"])
+    ap.add_argument("--autotune", default=None, metavar="CACHE",
+                    help="pick the formal-solve launch variant by timing (cache file path)")
     ap.add_argument("--points", type=int, default=None, help="override the point count")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -117,9 +131,15 @@ def main():
     from paper_1912_08445_amd.binding import Solver
     from synth import configs
 
-    make = {"outflow5": configs.outflow5, "sphere2": configs.sphere2, "disc10": configs.disc10}[args.workload]
+    make = {"outflow5": configs.outflow5, "sphere2": configs.sphere2, "disc10": configs.disc10,
+            "batch256": configs.batch256}[args.workload]
     t0 = time.perf_counter()
-    w = make() if args.points is None else make(n_points=args.points)
+    if args.points is None:
+        w = make()
+    elif args.workload == "batch256":
+        w = make(n_models=args.points)
+    else:
+        w = make(n_points=args.points)
     log(f"workload {w.name}: {w.n_points} points, {w.rays.shape[0]} rays, {w.species.n_lines} lines x "
         f"{w.quad_x.shape[0]} freqs ({time.perf_counter() - t0:.1f} s to generate)")
 
@@ -129,6 +149,11 @@ def main():
     total_cells, max_len, steps_per_freq = s.trace_stats()
     log(f"traced in {time.perf_counter() - t0:.2f} s: {total_cells} cells, longest ray {max_len}, "
         f"{steps_per_freq} elimination steps per frequency")
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuned = s.autotune(args.autotune, trials=3)
+        log(f"autotune: {tuned} ({time.perf_counter() - t0:.1f} s)")
 
     dev = torch.device("cuda:0")
     P, nlev, nl = w.n_points, w.species.n_lev, w.species.n_lines
@@ -196,7 +221,8 @@ def main():
         wall = time.perf_counter() - t0
         ali = {"iterations": rep["iterations"], "converged": rep["converged"], "wall_s": wall,
                "final_max_change": rep["max_change"][-1] if rep["max_change"] else None,
-               "tol": 1e-4, "start": "LTE"}
+               "tol": 1e-4, "start": "LTE", "models": w.n_models,
+               "models_converged": rep["n_models_converged"], "graph": True}
         log(f"ALI to 1e-4: {rep['iterations']} iterations, {wall:.2f} s")
 
     cpu = None
@@ -223,7 +249,7 @@ def main():
         "config": {"workload": desc, "points": P, "rays": int(w.rays.shape[0]), "lines": nl,
                    "frequencies": int(w.quad_x.shape[0]), "levels": nlev,
                    "precision": args.precision, "cells_cached": total_cells,
-                   "node_freq_per_sweep": node_freq},
+                   "node_freq_per_sweep": node_freq, "models": w.n_models, "launch": tuned},
         "node_freq_per_s": node_freq / (ms_step * 1e-3),
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -58,7 +58,13 @@ typedef struct {
     int max_iter;     /* ALI iteration cap */
     int use_alo;      /* 1: diagonal ALO (Sec. 3.4); 0: plain Lambda iteration */
     int precision;    /* NLTE_PREC_* */
-    int profile;      /* 1: time every kernel with HIP events (nlte_kernel_stats) */
+    int profile;      /* 1: time every kernel with HIP events (nlte_kernel_stats); the ALI
+                         then launches kernels one by one instead of replaying a graph */
+    int use_graph;    /* 1: capture one ALI iteration as a hipGraph and replay it.  1 */
+    int lines_per_lane; /* formal-solve lines per lane: 0 = by rule, 1 or 2.  0 */
+    int high_occupancy; /* 1: formal-solve kernels built for 3-4 waves per SIMD.  1 */
+    int persistent;   /* 1: persistent formal solve taking points from a work queue in
+                         decreasing order of their cached step counts.  0 */
 } nlte_params;
 
 /* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0. */
@@ -67,8 +73,10 @@ void nlte_default_params(nlte_params *p);
 typedef struct {
     int iterations;          /* ALI iterations performed */
     int converged;           /* 1 if the last change was below tol */
-    double max_change[1024]; /* per-iteration max relative change (first min(iters,1024)) */
+    double max_change[1024]; /* per-iteration max relative change over the models still
+                                iterating (first min(iters,1024)) */
     double mean_change[1024];/* per-iteration mean relative change over the same entries */
+    int64_t n_models_converged; /* models whose change fell below tol */
     int64_t n_fallback;      /* stat-eq solves that fell back to plain Lambda (last iteration) */
     int64_t n_kept;          /* points that kept their previous populations (last iteration) */
     int64_t n_maser;         /* (point, line) pairs with non-positive opacity (last iteration) */
@@ -202,13 +210,31 @@ nlte_status nlte_stateq_dev(nlte_ctx *ctx, const double *d_pops_old, const doubl
  * Accelerated Lambda iteration (Sec. 2.2.1, 3.4) from pops_init (NULL = LTE): repeat
  * formal solve + statistical equilibrium until the maximum relative change
  * |n_new - n_old| / n_new over levels with n_i / (abundance n_h2) > 1e-10 drops below
- * tol, or max_iter iterations ran.  pops_out [P][n_lev]; rep (nullable) gets the report.
- * Returns NLTE_W_NOT_CONVERGED if tol was not reached.
+ * tol, or max_iter iterations ran.  Each model stops on its own: once its change is below
+ * tol its points are no longer solved and keep their populations.  pops_out [P][n_lev];
+ * rep (nullable) gets the report.  Returns NLTE_W_NOT_CONVERGED if some model did not
+ * reach tol.  The _dev form orders its work after the caller's stream and returns when
+ * pops_out is written.
  */
 nlte_status nlte_run_ali(nlte_ctx *ctx, const double *pops_init, double *pops_out,
                          nlte_ali_report *rep);
 nlte_status nlte_run_ali_dev(nlte_ctx *ctx, const double *d_pops_init, double *d_pops_out,
                              nlte_ali_report *rep, void *stream);
+
+/* Per model after the last nlte_run_ali: iterations it took, whether it converged and its
+ * last maximum relative change ([n_models] each; any pointer may be NULL). */
+nlte_status nlte_get_model_status(nlte_ctx *ctx, int32_t *iterations, uint8_t *converged,
+                                  double *last_change);
+
+/*
+ * Time the formal-solve launch variants (lines per lane 1/2, occupancy hint on/off, grid or
+ * persistent work queue) on the current model with LTE populations, `trials` launches
+ * each (after one warm-up), and keep the fastest (median) in the context's parameters.
+ * cache_path (nullable): text file of earlier choices keyed by device, model size, ray,
+ * line and frequency counts, step count and precision; a hit skips the timing, a miss
+ * appends the new choice.  choice (nullable, cap bytes) receives a description.
+ */
+nlte_status nlte_autotune(nlte_ctx *ctx, const char *cache_path, int trials, char *choice, int cap);
 
 /* ---------------------------------------------------------------- profiling */
 

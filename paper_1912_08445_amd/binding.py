@@ -32,19 +32,22 @@ EXPORTS = (
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
     "nlte_get_ray", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_stateq", "nlte_stateq_dev",
-    "nlte_run_ali", "nlte_run_ali_dev", "nlte_kernel_stats", "nlte_reset_kernel_stats",
+    "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
+    "nlte_kernel_stats", "nlte_reset_kernel_stats",
 )
 
 
 class Params(C.Structure):
     _fields_ = [("t_cmb", C.c_double), ("f_sub", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("use_alo", C.c_int), ("precision", C.c_int),
-                ("profile", C.c_int)]
+                ("profile", C.c_int), ("use_graph", C.c_int), ("lines_per_lane", C.c_int),
+                ("high_occupancy", C.c_int), ("persistent", C.c_int)]
 
 
 class AliReport(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int),
                 ("max_change", C.c_double * 1024), ("mean_change", C.c_double * 1024),
+                ("n_models_converged", C.c_int64),
                 ("n_fallback", C.c_int64), ("n_kept", C.c_int64), ("n_maser", C.c_int64),
                 ("ms_total", C.c_double)]
 
@@ -86,6 +89,8 @@ def load():
     L.nlte_stateq_dev.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.nlte_run_ali.argtypes = [vp, vp, vp, C.POINTER(AliReport)]
     L.nlte_run_ali_dev.argtypes = [vp, vp, vp, C.POINTER(AliReport), vp]
+    L.nlte_get_model_status.argtypes = [vp, vp, vp, vp]
+    L.nlte_autotune.argtypes = [vp, C.c_char_p, C.c_int, C.c_char_p, C.c_int]
     L.nlte_kernel_stats.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.nlte_reset_kernel_stats.argtypes = [vp]
     for name in EXPORTS:
@@ -281,6 +286,26 @@ class Solver:
                                                _stream(stream)), warn_ok=True)
         return report_dict(rep, rc)
 
+    def model_status(self):
+        """(iterations, converged, last max change) per model after run_ali"""
+        it = np.zeros(self.n_models, dtype=np.int32)
+        cv = np.zeros(self.n_models, dtype=np.uint8)
+        ch = np.zeros(self.n_models)
+        self._chk(self.L.nlte_get_model_status(self.h, _p(it), _p(cv), _p(ch)))
+        return it, cv.astype(bool), ch
+
+    def autotune(self, cache_path=None, trials=3):
+        """Time the formal-solve launch variants and keep the fastest (see nlte_autotune)."""
+        buf = C.create_string_buffer(256)
+        self._chk(self.L.nlte_autotune(self.h, cache_path.encode() if cache_path else None, int(trials),
+                                       buf, 256))
+        choice = buf.value.decode()
+        fields = dict(kv.split("=") for kv in choice.split() if "=" in kv)
+        self.params.lines_per_lane = int(fields["lpl"])
+        self.params.high_occupancy = int(fields["high"])
+        self.params.persistent = int(fields["persistent"])
+        return choice
+
     # ---------------------------------------------------------------- profiling
     def kernel_stats(self, name):
         ms, n = C.c_double(), C.c_int64()
@@ -294,6 +319,7 @@ class Solver:
 def report_dict(rep, rc):
     it = rep.iterations
     return dict(status=rc, iterations=it, converged=bool(rep.converged),
+                n_models_converged=rep.n_models_converged,
                 max_change=list(rep.max_change[:min(it, 1024)]),
                 mean_change=list(rep.mean_change[:min(it, 1024)]),
                 n_fallback=rep.n_fallback, n_kept=rep.n_kept, n_maser=rep.n_maser,

@@ -1,6 +1,7 @@
 // C ABI of the library (declared in include/nlte.h): input validation, device buffers,
 // the trace pipeline, one ALI step and the ALI loop.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -147,38 +148,99 @@ SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
     // group (1 or 2; more lines per lane exceed the register budget of the sweep).
     const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
     a.fchunks = (c->n_q <= kWave) ? 1 : (c->n_q + kWave - 1) / kWave;
-    const int lpl = std::min(2, (c->n_lines + ngrp - 1) / ngrp);
+    int lpl = std::min(2, (c->n_lines + ngrp - 1) / ngrp);
+    if (c->cfg.lpl == 1 || c->cfg.lpl == 2) lpl = std::min(lpl, c->cfg.lpl);
     a.lines_per_wave = ngrp * lpl;
     a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
     a.n_blocks = c->P * a.groups;
     a.J = J;
     a.Jeff = Jeff;
     a.L = L;
+    a.model_done = nullptr;
+    a.model_of = c->d_model_of;
+    a.order = c->d_order;
+    a.work_counter = c->d_work_counter;
     return a;
 }
 
+// Captured ALI iterations depend on every buffer and parameter; drop them on any change.
+void drop_graphs(nlte_ctx *c)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (c->graph_exec[i]) (void)hipGraphExecDestroy(c->graph_exec[i]);
+        c->graph_exec[i] = nullptr;
+        c->graph_buf[i] = nullptr;
+    }
+}
+
+// Line coefficients and the formal solve.  ali: skip points of converged models.
+// capture: enqueue only (no per-kernel event timing, which would synchronise).
 nlte_status formal_solve_impl(nlte_ctx *c, const double *d_pops, double *d_J, double *d_Jeff,
-                              double *d_L, hipStream_t s)
+                              double *d_L, hipStream_t s, bool ali = false, bool capture = false)
 {
     const int fp32 = c->params.precision == NLTE_PREC_FP32_BULK;
-    HIPCHK(c, timed(c, c->st_line_coef, s, [&] {
-               return launch_line_coef(c->sp, c->d_cell, d_pops, c->P, fp32, c->d_lc, c->d_maser, s);
-           }));
+    auto lc = [&] { return launch_line_coef(c->sp, c->d_cell, d_pops, c->P, fp32, c->d_lc, c->d_maser, s); };
+    HIPCHK(c, capture ? lc() : timed(c, c->st_line_coef, s, lc));
     SolveArgs a = solve_args(c, d_J, d_Jeff, d_L);
-    HIPCHK(c, timed(c, c->st_formal, s, [&] { return launch_formal_solve(a, fp32, s); }));
+    if (ali) a.model_done = c->d_model_done;
+    if (c->cfg.persistent) HIPCHK(c, launch_fill_u64(c->d_work_counter, 1, 0ull, s));
+    auto fs = [&] { return launch_formal_solve(a, c->cfg, fp32, s); };
+    HIPCHK(c, capture ? fs() : timed(c, c->st_formal, s, fs));
     return NLTE_OK;
 }
 
 nlte_status stateq_impl(nlte_ctx *c, const double *d_old, const double *d_J, const double *d_Jeff,
                         const double *d_L, double *d_new, uint8_t *d_flags, ConvResult *d_conv,
-                        hipStream_t s)
+                        hipStream_t s, bool ali = false, bool capture = false)
 {
     const int64_t nb = stateq_blocks(c->P);
-    HIPCHK(c, timed(c, c->st_stateq, s, [&] {
-               return launch_stateq(c->sp, c->d_cell, c->d_nh2, c->d_T, c->P, c->params.use_alo,
-                                    d_old, d_J, d_Jeff, d_L, d_new, d_flags, c->d_partials, nb, s);
-           }));
+    auto sq = [&] {
+        return launch_stateq(c->sp, c->d_cell, c->d_nh2, c->d_T, c->P, c->params.use_alo, d_old, d_J, d_Jeff,
+                             d_L, d_new, d_flags, c->d_partials, nb, ali ? c->d_model_done : nullptr,
+                             c->d_model_of, ali ? c->d_model_change : nullptr, s);
+    };
+    HIPCHK(c, capture ? sq() : timed(c, c->st_stateq, s, sq));
     if (d_conv) HIPCHK(c, launch_conv_final(c->d_partials, nb, d_conv, s));
+    return NLTE_OK;
+}
+
+// One ALI iteration cur -> nxt with per-model convergence; ends with the number of
+// models still iterating and the change summary in pinned host memory.
+nlte_status enqueue_iteration(nlte_ctx *c, const double *cur, double *nxt, hipStream_t s, bool capture)
+{
+    nlte_status st;
+    HIPCHK(c, launch_fill_u64(c->d_model_change, c->n_models, 0ull, s));
+    HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->d_maser), 1, 0ull, s));
+    HIPCHK(c, launch_fill_u8(reinterpret_cast<uint8_t *>(c->d_active), sizeof(int32_t), 0, s));
+    if ((st = formal_solve_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, s, true, capture))) return st;
+    if ((st = stateq_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, nxt, c->d_flags, c->d_conv, s, true, capture)))
+        return st;
+    HIPCHK(c, launch_model_update(c->n_models, c->d_model_change, c->d_model_done, c->d_model_iters,
+                                  c->d_model_last, c->params.tol, c->d_active, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_conv, c->d_conv, sizeof(ConvResult), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    return NLTE_OK;
+}
+
+// Capture the iteration cur -> nxt as a graph (once per buffer pair and parameter set).
+nlte_status ensure_graph(nlte_ctx *c, int slot, const double *cur, double *nxt)
+{
+    if (c->graph_exec[slot] && c->graph_buf[slot] == cur) return NLTE_OK;
+    if (c->graph_exec[slot]) (void)hipGraphExecDestroy(c->graph_exec[slot]);
+    c->graph_exec[slot] = nullptr;
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    nlte_status st = enqueue_iteration(c, cur, nxt, c->stream, true);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(c, NLTE_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph_exec[slot], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, NLTE_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    c->graph_buf[slot] = cur;
     return NLTE_OK;
 }
 
@@ -196,6 +258,10 @@ void nlte_default_params(nlte_params *p)
     p->use_alo = 1;
     p->precision = NLTE_PREC_FP64;
     p->profile = 0;
+    p->use_graph = 1;
+    p->lines_per_lane = 0;
+    p->high_occupancy = 1;
+    p->persistent = 0;
 }
 
 nlte_status nlte_create(nlte_ctx **out, int hip_device)
@@ -213,10 +279,20 @@ nlte_status nlte_create(nlte_ctx **out, int hip_device)
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipMalloc((void **)&c->d_maser, sizeof(int64_t)) != hipSuccess ||
         hipMalloc((void **)&c->d_conv, sizeof(ConvResult) * 1025) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_conv, sizeof(ConvResult) * 1025, 0) != hipSuccess) {
+        hipHostMalloc((void **)&c->h_conv, sizeof(ConvResult) * 1025, 0) != hipSuccess ||
+        hipMalloc((void **)&c->d_active, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_active, sizeof(int32_t), 0) != hipSuccess ||
+        hipMalloc((void **)&c->d_work_counter, sizeof(unsigned long long)) != hipSuccess) {
         nlte_destroy(c);
         return NLTE_E_HIP;
     }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
+        c->n_cu = prop.multiProcessorCount;
+        c->device_name = prop.gcnArchName;
+    }
+    if (c->n_cu <= 0) c->n_cu = 256;
+    c->cfg.n_wg = c->n_cu * 16;
     *out = c;
     return NLTE_OK;
 }
@@ -250,7 +326,17 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_partials);
     dfree(c->d_conv);
     dfree(c->d_maser);
+    dfree(c->d_active);
+    dfree(c->d_work_counter);
+    dfree(c->d_order);
+    dfree(c->d_model_of);
+    dfree(c->d_model_done);
+    dfree(c->d_model_change);
+    dfree(c->d_model_iters);
+    dfree(c->d_model_last);
+    drop_graphs(c);
     if (c->h_conv) (void)hipHostFree(c->h_conv);
+    if (c->h_active) (void)hipHostFree(c->h_active);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -350,6 +436,7 @@ nlte_status nlte_set_species(nlte_ctx *c, int n_lev, const double *E, const doub
     c->n_coll = n_coll;
     c->n_T = n_T;
     c->mass = mass;
+    drop_graphs(c);
     c->have_species = true;
     // line widths and work buffers depend on the species: the model must be set again
     c->have_model = false;
@@ -439,6 +526,20 @@ nlte_status nlte_set_models(nlte_ctx *c, int n_models, const int64_t *offsets, c
     c->offsets = off;
     c->have_model = true;
     c->traced = false;
+    drop_graphs(c);
+    // point -> model map and per-model convergence state
+    std::vector<int32_t> mo(P);
+    for (int m = 0; m < n_models; ++m)
+        for (int64_t p = off[m]; p < off[m + 1]; ++p) mo[p] = m;
+    nlte_status st2;
+    if ((st2 = dalloc(c, &c->d_model_of, P)) || (st2 = dalloc(c, &c->d_model_done, n_models)) ||
+        (st2 = dalloc(c, &c->d_model_change, n_models)) || (st2 = dalloc(c, &c->d_model_iters, n_models)) ||
+        (st2 = dalloc(c, &c->d_model_last, n_models)))
+        return st2;
+    HIPCHK(c, hipMemcpy(c->d_model_of, mo.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->d_model_done, 0, n_models));
+    HIPCHK(c, hipMemset(c->d_model_iters, 0, sizeof(int32_t) * n_models));
+    HIPCHK(c, hipMemset(c->d_model_last, 0, sizeof(double) * n_models));
     return ensure_work(c);
 }
 
@@ -477,6 +578,7 @@ nlte_status nlte_set_rays(nlte_ctx *c, int n_rays, const double *dir)
     c->pair_r = pr;
     c->have_rays = true;
     c->traced = false;
+    drop_graphs(c);
     return NLTE_OK;
 }
 
@@ -501,6 +603,7 @@ nlte_status nlte_set_quadrature(nlte_ctx *c, int n_q, const double *x, const dou
     c->xq_max = 0.0;
     for (int n = 0; n < n_q; ++n) c->xq_max = std::max(c->xq_max, fabs(x[n]));
     c->have_quad = true;
+    drop_graphs(c);
     return NLTE_OK;
 }
 
@@ -508,9 +611,14 @@ nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
 {
     if (!c || !p) return NLTE_E_INVALID_ARG;
     if (!(p->t_cmb > 0.0) || !(p->f_sub > 0.0) || !(p->tol >= 0.0) || p->max_iter < 1 ||
-        p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK))
+        p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
+        p->lines_per_lane < 0 || p->lines_per_lane > 2)
         return fail(c, NLTE_E_INVALID_ARG, "parameter out of range");
     c->params = *p;
+    c->cfg.lpl = p->lines_per_lane;
+    c->cfg.high_occupancy = p->high_occupancy ? 1 : 0;
+    c->cfg.persistent = p->persistent ? 1 : 0;
+    drop_graphs(c);
     return upload_ibdy(c);
 }
 
@@ -550,12 +658,23 @@ nlte_status nlte_trace(nlte_ctx *c)
     for (int64_t i = 0; i < n; ++i) mx = std::max<int>(mx, (int)(off[i + 1] - off[i]));
     c->total_cells = total;
     c->max_len = mx;
-    // elimination steps per frequency (cells + velocity sub-steps)
-    HIPCHK(c, hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s));
+    // elimination steps per frequency (cells + velocity sub-steps), per-point cost and
+    // the points in decreasing-cost order for the persistent formal solve
+    unsigned long long *cost = nullptr;
+    if ((st = dalloc(c, &cost, c->P))) return st;
+    if ((st = dalloc(c, &c->d_order, c->P))) {
+        dfree(cost);
+        return st;
+    }
+    hipError_t e2 = hipMemsetAsync(cost, 0, sizeof(unsigned long long) * c->P, s);
+    if (e2 == hipSuccess) e2 = hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s);
     SolveArgs a = solve_args(c, nullptr, nullptr, nullptr);
-    HIPCHK(c, launch_count_steps(a, c->d_maser, s));
-    HIPCHK(c, hipMemcpyAsync(&c->total_steps, c->d_maser, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    if (e2 == hipSuccess) e2 = launch_count_steps(a, c->d_maser, cost, s);
+    if (e2 == hipSuccess) e2 = hipMemcpyAsync(&c->total_steps, c->d_maser, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = sort_by_cost(cost, c->d_order, c->P, s);
+    dfree(cost);
+    if (e2 != hipSuccess) return fail(c, NLTE_E_HIP, std::string("step count: ") + hipGetErrorString(e2));
+    drop_graphs(c);
     c->traced = true;
     return NLTE_OK;
 }
@@ -687,36 +806,47 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
     if (st) return st;
     if (!d_out) return fail(c, NLTE_E_INVALID_ARG, "null output");
     (void)hipSetDevice(c->device);
-    hipStream_t s = pick(c, stream);
+    // the iterations run on the context's stream, ordered after the caller's stream
+    hipStream_t s = c->stream;
+    hipStream_t us = stream ? (hipStream_t)stream : c->stream;
+    if (us != s) {
+        HIPCHK(c, hipEventRecord(c->ev0, us));
+        HIPCHK(c, hipStreamWaitEvent(s, c->ev0, 0));
+    }
     const size_t np = sizeof(double) * c->P * c->n_lev;
     auto t0 = std::chrono::steady_clock::now();
     if (d_init)
         HIPCHK(c, hipMemcpyAsync(c->d_pops_a, d_init, np, hipMemcpyDeviceToDevice, s));
     else
         HIPCHK(c, launch_lte(c->sp, c->d_cell, c->d_T, c->P, c->d_pops_a, s));
-    double *cur = c->d_pops_a, *nxt = c->d_pops_b;
+    HIPCHK(c, launch_fill_u8(c->d_model_done, c->n_models, 0, s));
+    HIPCHK(c, hipMemsetAsync(c->d_model_iters, 0, sizeof(int32_t) * c->n_models, s));
+    double *buf[2] = {c->d_pops_a, c->d_pops_b};
+    const bool graph = c->params.use_graph != 0 && !c->params.profile;
+    if (graph) {
+        if ((st = ensure_graph(c, 0, buf[0], buf[1]))) return st;
+        if ((st = ensure_graph(c, 1, buf[1], buf[0]))) return st;
+    }
     if (rep) memset(rep, 0, sizeof(*rep));
-    int it = 0;
-    bool conv = false;
+    int it = 0, active = c->n_models;
     ConvResult last{};
     while (it < c->params.max_iter) {
-        HIPCHK(c, hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s));
-        if ((st = formal_solve_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, s))) return st;
-        if ((st = stateq_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, nxt, c->d_flags, c->d_conv, s))) return st;
-        HIPCHK(c, hipMemcpyAsync(c->h_conv, c->d_conv, sizeof(ConvResult), hipMemcpyDeviceToHost, s));
+        const int slot = it & 1;
+        if (graph)
+            HIPCHK(c, hipGraphLaunch(c->graph_exec[slot], s));
+        else if ((st = enqueue_iteration(c, buf[slot], buf[slot ^ 1], s, false)))
+            return st;
         HIPCHK(c, hipStreamSynchronize(s));
         last = *c->h_conv;
+        active = *c->h_active;
         if (rep && it < 1024) {
             rep->max_change[it] = last.max_change;
             rep->mean_change[it] = last.mean_change;
         }
-        std::swap(cur, nxt);
         ++it;
-        if (last.max_change < c->params.tol) {
-            conv = true;
-            break;
-        }
+        if (active == 0) break;
     }
+    const double *cur = buf[it & 1];
     HIPCHK(c, hipMemcpyAsync(d_out, cur, np, hipMemcpyDeviceToDevice, s));
     int64_t maser = 0;
     HIPCHK(c, hipMemcpyAsync(&maser, c->d_maser, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -724,13 +854,14 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
     auto t1 = std::chrono::steady_clock::now();
     if (rep) {
         rep->iterations = it;
-        rep->converged = conv ? 1 : 0;
+        rep->converged = active == 0 ? 1 : 0;
+        rep->n_models_converged = c->n_models - active;
         rep->n_fallback = last.n_fallback;
         rep->n_kept = last.n_kept;
         rep->n_maser = maser;
         rep->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
-    if (!conv) {
+    if (active != 0) {
         c->err = "ALI stopped at max_iter above tol";
         return NLTE_W_NOT_CONVERGED;
     }
@@ -768,6 +899,107 @@ nlte_status nlte_run_ali(nlte_ctx *c, const double *pops_init, double *pops_out,
     dfree(d_in);
     dfree(d_out);
     return rs;
+}
+
+nlte_status nlte_get_model_status(nlte_ctx *c, int32_t *iterations, uint8_t *converged, double *last_change)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!c->have_model) return fail(c, NLTE_E_STATE, "no model");
+    const int n = c->n_models;
+    if (iterations) HIPCHK(c, hipMemcpy(iterations, c->d_model_iters, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (converged) HIPCHK(c, hipMemcpy(converged, c->d_model_done, n, hipMemcpyDeviceToHost));
+    if (last_change) HIPCHK(c, hipMemcpy(last_change, c->d_model_last, sizeof(double) * n, hipMemcpyDeviceToHost));
+    return NLTE_OK;
+}
+
+nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char *choice, int cap)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (trials < 1) trials = 3;
+    (void)hipSetDevice(c->device);
+    hipStream_t s = c->stream;
+    char key[512];
+    snprintf(key, sizeof key, "%s|P=%lld|rays=%d|lines=%d|nq=%d|steps=%lld|prec=%d", c->device_name.c_str(),
+             (long long)c->P, c->n_rays, c->n_lines, c->n_q, (long long)c->total_steps, c->params.precision);
+    SolveConfig best = c->cfg;
+    double best_ms = -1.0;
+    bool cached = false;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char line[1024];
+            while (fgets(line, sizeof line, f)) {
+                char k2[512];
+                int lpl, hi, pe;
+                double ms;
+                if (sscanf(line, "%511s lpl=%d high=%d persistent=%d ms=%lf", k2, &lpl, &hi, &pe, &ms) == 5 &&
+                    strcmp(k2, key) == 0) {
+                    best.lpl = lpl;
+                    best.high_occupancy = hi;
+                    best.persistent = pe;
+                    best_ms = ms;
+                    cached = true;
+                }
+            }
+            fclose(f);
+        }
+    }
+    if (!cached) {
+        // time every launch variant on the current model with LTE populations
+        HIPCHK(c, launch_lte(c->sp, c->d_cell, c->d_T, c->P, c->d_pops_a, s));
+        const int saved_profile = c->params.profile;
+        c->params.profile = 0;
+        const SolveConfig saved = c->cfg;
+        for (int lpl = 1; lpl <= 2; ++lpl)
+            for (int hi = 0; hi <= 1; ++hi)
+                for (int pe = 0; pe <= 1; ++pe) {
+                    c->cfg.lpl = lpl;
+                    c->cfg.high_occupancy = hi;
+                    c->cfg.persistent = pe;
+                    if (lpl == 2 && solve_args(c, nullptr, nullptr, nullptr).lines_per_wave / 2 < 1) continue;
+                    std::vector<float> t;
+                    for (int k = 0; k <= trials; ++k) {
+                        HIPCHK(c, hipEventRecord(c->ev0, s));
+                        if ((st = formal_solve_impl(c, c->d_pops_a, c->d_J, c->d_Jeff, c->d_L, s))) {
+                            c->cfg = saved;
+                            c->params.profile = saved_profile;
+                            return st;
+                        }
+                        HIPCHK(c, hipEventRecord(c->ev1, s));
+                        HIPCHK(c, hipEventSynchronize(c->ev1));
+                        float ms = 0.f;
+                        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                        if (k > 0) t.push_back(ms);   // the first launch is a warm-up
+                    }
+                    std::sort(t.begin(), t.end());
+                    const double med = t[t.size() / 2];
+                    if (best_ms < 0 || med < best_ms) {
+                        best_ms = med;
+                        best = c->cfg;
+                    }
+                }
+        c->params.profile = saved_profile;
+        if (cache_path) {
+            FILE *f = fopen(cache_path, "a");
+            if (f) {
+                fprintf(f, "%s lpl=%d high=%d persistent=%d ms=%.4f\n", key, best.lpl, best.high_occupancy,
+                        best.persistent, best_ms);
+                fclose(f);
+            }
+        }
+    }
+    c->cfg.lpl = best.lpl;
+    c->cfg.high_occupancy = best.high_occupancy;
+    c->cfg.persistent = best.persistent;
+    c->params.lines_per_lane = best.lpl;
+    c->params.high_occupancy = best.high_occupancy;
+    c->params.persistent = best.persistent;
+    drop_graphs(c);
+    if (choice && cap > 0)
+        snprintf(choice, cap, "lpl=%d high=%d persistent=%d ms=%.4f%s", best.lpl, best.high_occupancy,
+                 best.persistent, best_ms, cached ? " (cached)" : "");
+    return NLTE_OK;
 }
 
 nlte_status nlte_kernel_stats(nlte_ctx *c, const char *name, double *ms, int64_t *launches)

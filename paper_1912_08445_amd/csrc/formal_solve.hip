@@ -432,28 +432,19 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
     }
 }
 
-// Occupancy hint: at least 3 waves per SIMD (4 with one line per lane).  Measured on
-// the 50,000-point outflow model this beats the compiler's default register budget
-// (two waves) even though a few bytes of the sweep's live values then go to scratch.
+// All (line, frequency) work of one wave for origin point O and line block w, accumulated
+// over every ray pair and written to J, L*, Jeff.  Points of models that already
+// converged are skipped (their outputs are not needed).
 template <bool F32, int LPL>
-__global__ __launch_bounds__(64, LPL == 1 ? 4 : 3) void k_formal_solve(SolveArgs a)
+__device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
+                                           NodeRec<typename Bulk<F32>::T, 2 * LPL> *rec,
+                                           double (*red)[LPL][kWave])
 {
     using T = typename Bulk<F32>::T;
     using T2 = typename Bulk<F32>::T2;
     using Acc = typename Bulk<F32>::T;
-    constexpr int NLW = 2 * LPL;
-    __shared__ NodeRec<T, NLW> rec[kWave];
-    __shared__ double red[3][LPL][kWave];
     const int lane = threadIdx.x;
-    // Consecutive hardware workgroups go round-robin to the 8 XCDs; give each XCD a
-    // contiguous range of origin points so that the cells their rays share stay in
-    // that XCD's L2.
-    const int64_t nb8 = (a.n_blocks + 7) / 8;
-    const int64_t lb = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
-    if (lb >= a.n_blocks) return;
-    const int64_t O = lb / a.groups;
-    const int w = (int)(lb - O * a.groups);
-
+    if (a.model_done != nullptr && a.model_done[a.model_of[O]]) return;
     // lane -> (group, frequency); a wave owns lines line0 .. line0 + nlw - 1
     const int ngrp = a.lines_per_wave / LPL;     // 1 or 2 groups of lanes
     const int line0 = w * a.lines_per_wave;
@@ -539,30 +530,81 @@ __global__ __launch_bounds__(64, LPL == 1 ? 4 : 3) void k_formal_solve(SolveArgs
     }
 }
 
-template <bool F32>
-hipError_t launch_fs(const SolveArgs &a, dim3 grid, hipStream_t s)
+// Grid form: one workgroup per (point, line block).  Consecutive hardware workgroups go
+// round-robin to the 8 XCDs; each XCD gets a contiguous range of origin points so that
+// the cells their rays share stay in that XCD's L2.  HIGH asks for at least 3 waves per
+// SIMD (4 with one line per lane): measured on the 50,000-point outflow model this beats
+// the compiler's default register budget (two waves) although a few bytes of the sweep's
+// live values then go to scratch.
+template <bool F32, int LPL, bool HIGH>
+__global__ __launch_bounds__(64, HIGH ? (LPL == 1 ? 4 : 3) : 1) void k_formal_solve(SolveArgs a)
 {
-    const int lpl = a.lines_per_wave / (a.fchunks == 1 && 2 * a.n_q <= kWave ? 2 : 1);
-    switch (lpl) {
-    case 1: hipLaunchKernelGGL((k_formal_solve<F32, 1>), grid, dim3(kWave), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_formal_solve<F32, 2>), grid, dim3(kWave), 0, s, a); break;
-    default: return hipErrorInvalidValue;
+    __shared__ NodeRec<typename Bulk<F32>::T, 2 * LPL> rec[kWave];
+    __shared__ double red[3][LPL][kWave];
+    const int64_t nb8 = (a.n_blocks + 7) / 8;
+    const int64_t lb = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
+    if (lb >= a.n_blocks) return;
+    const int64_t O = lb / a.groups;
+    solve_item<F32, LPL>(a, O, (int)(lb - O * a.groups), rec, red);
+}
+
+// Persistent form: a fixed grid of workgroups takes (point, line block) items from an
+// atomic counter in the order a.order gives (points by decreasing cached step count, so
+// the longest items start first and the tail is short).  Every workgroup leaves the loop
+// once the counter has passed the last item.
+template <bool F32, int LPL, bool HIGH>
+__global__ __launch_bounds__(64, HIGH ? (LPL == 1 ? 4 : 3) : 1) void k_formal_solve_queue(SolveArgs a)
+{
+    __shared__ NodeRec<typename Bulk<F32>::T, 2 * LPL> rec[kWave];
+    __shared__ double red[3][LPL][kWave];
+    __shared__ unsigned long long item_s;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1ull);
+        __syncthreads();
+        const int64_t item = (int64_t)item_s;
+        if (item >= a.n_blocks) break;
+        const int64_t rank = item / a.groups;
+        solve_item<F32, LPL>(a, (int64_t)a.order[rank], (int)(item - rank * a.groups), rec, red);
+    }
+}
+
+template <bool F32, int LPL, bool HIGH>
+hipError_t launch_variant(const SolveArgs &a, int persistent, int n_wg, hipStream_t s)
+{
+    if (persistent) {
+        hipLaunchKernelGGL((k_formal_solve_queue<F32, LPL, HIGH>), dim3(n_wg), dim3(kWave), 0, s, a);
+    } else {
+        const int64_t nb8 = (a.n_blocks + 7) / 8;
+        hipLaunchKernelGGL((k_formal_solve<F32, LPL, HIGH>), dim3((unsigned)(nb8 * 8)), dim3(kWave), 0, s, a);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_formal_solve(const SolveArgs &a, int fp32, hipStream_t s)
+template <bool F32>
+hipError_t launch_fs(const SolveArgs &a, const SolveConfig &cfg, hipStream_t s)
+{
+    const int lpl = a.lines_per_wave / ((a.fchunks == 1 && 2 * a.n_q <= kWave) ? 2 : 1);
+    if (lpl == 1)
+        return cfg.high_occupancy ? launch_variant<F32, 1, true>(a, cfg.persistent, cfg.n_wg, s)
+                                  : launch_variant<F32, 1, false>(a, cfg.persistent, cfg.n_wg, s);
+    if (lpl == 2)
+        return cfg.high_occupancy ? launch_variant<F32, 2, true>(a, cfg.persistent, cfg.n_wg, s)
+                                  : launch_variant<F32, 2, false>(a, cfg.persistent, cfg.n_wg, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_formal_solve(const SolveArgs &a, const SolveConfig &cfg, int fp32, hipStream_t s)
 {
     if (a.n_blocks == 0) return hipSuccess;
-    const int64_t nb8 = (a.n_blocks + 7) / 8;
-    dim3 grid((unsigned)(nb8 * 8));
-    return fp32 ? launch_fs<true>(a, grid, s) : launch_fs<false>(a, grid, s);
+    return fp32 ? launch_fs<true>(a, cfg, s) : launch_fs<false>(a, cfg, s);
 }
 
 // Elimination steps per frequency over all half rays: the cells of every cached walk
 // plus their velocity sub-steps, with the same sub-step rule as the sweep.  One thread
 // per (point, ray); block sums are added atomically (integer, order-independent).
-__global__ __launch_bounds__(256) void k_count_steps(SolveArgs a, unsigned long long *steps)
+__global__ __launch_bounds__(256) void k_count_steps(SolveArgs a, unsigned long long *steps,
+                                                     unsigned long long *point_cost)
 {
     __shared__ unsigned long long part[256];
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -590,6 +632,7 @@ __global__ __launch_bounds__(256) void k_count_steps(SolveArgs a, unsigned long 
             s_prev = sv;
             w_prev = c.vw;
         }
+        if (point_cost != nullptr) atomicAdd(&point_cost[O], n + 1);
     }
     part[threadIdx.x] = n;
     __syncthreads();
@@ -600,12 +643,13 @@ __global__ __launch_bounds__(256) void k_count_steps(SolveArgs a, unsigned long 
     if (threadIdx.x == 0) atomicAdd(steps, part[0]);
 }
 
-hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, hipStream_t s)
+hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, unsigned long long *point_cost,
+                              hipStream_t s)
 {
     const int64_t n = a.P * a.n_rays;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_count_steps, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a,
-                       reinterpret_cast<unsigned long long *>(steps));
+                       reinterpret_cast<unsigned long long *>(steps), point_cost);
     return hipGetLastError();
 }
 

@@ -77,8 +77,22 @@ struct SolveArgs {
     int groups;              // waves per point
     int lines_per_wave;      // lines one wave serves (lane groups x lines per lane)
     int fchunks;             // frequency chunks per wave (n_q > 64), else 1
-    int64_t n_blocks;        // logical blocks (P * groups)
+    int64_t n_blocks;        // work items (P * groups)
     double *J, *Jeff, *L;    // [P][n_lines]
+    // ALI only: points of converged models are skipped (null: solve every point)
+    const uint8_t *model_done;
+    const int32_t *model_of;
+    // persistent form: item order (points by decreasing cost) and the work counter
+    const int32_t *order;
+    unsigned long long *work_counter;
+};
+
+// Launch choices of the formal solve (picked by rule or by the autotuner).
+struct SolveConfig {
+    int lpl = 0;              // lines per lane (1 or 2; 0 = by rule)
+    int high_occupancy = 1;   // 1: ask for 3-4 waves per SIMD
+    int persistent = 0;       // 1: work-queue kernel in decreasing-cost order
+    int n_wg = 0;             // workgroups of the persistent kernel
 };
 
 struct KernelStat {
@@ -108,6 +122,11 @@ struct nlte_ctx {
     int k = 0;
     int n_models = 0;
     std::vector<int64_t> offsets;   // [n_models + 1]
+    int32_t *d_model_of = nullptr;  // [P]
+    uint8_t *d_model_done = nullptr;            // [n_models]
+    unsigned long long *d_model_change = nullptr;  // [n_models] max change as FP64 bits
+    int32_t *d_model_iters = nullptr;           // [n_models]
+    double *d_model_last = nullptr;             // [n_models]
     nlte::CellRec *d_cell = nullptr;
     double *d_nh2 = nullptr, *d_T = nullptr;
     int32_t *d_nbr = nullptr;  // global indices
@@ -127,7 +146,9 @@ struct nlte_ctx {
     double *d_ibdy = nullptr;
     double xq_max = 0.0;
 
-    // ray cache
+    // ray cache, per-point costs and the decreasing-cost order
+    int32_t *d_order = nullptr;                 // [P]
+    unsigned long long *d_work_counter = nullptr;
     bool traced = false;
     int64_t *d_roff = nullptr;
     int32_t *d_rcells = nullptr;
@@ -144,7 +165,16 @@ struct nlte_ctx {
     int64_t n_partials_cap = 0;
     nlte::ConvResult *d_conv = nullptr;
     nlte::ConvResult *h_conv = nullptr;  // pinned
+    int32_t *d_active = nullptr;         // models still iterating
+    int32_t *h_active = nullptr;         // pinned
     int64_t *d_maser = nullptr;
+
+    // launch choices and the captured ALI iterations (cur -> next, next -> cur)
+    nlte::SolveConfig cfg;
+    int n_cu = 0;
+    std::string device_name;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    const double *graph_buf[2] = {nullptr, nullptr};
 
     // profiling
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -169,12 +199,20 @@ hipError_t scan_lengths(int64_t *len_then_off, int64_t n, void *tmp, size_t *tmp
                         hipStream_t s);
 hipError_t launch_line_coef(const SpeciesDev &sp, const CellRec *cell, const double *pops,
                             int64_t P, int fp32, void *lc, int64_t *maser_count, hipStream_t s);
-hipError_t launch_formal_solve(const SolveArgs &a, int fp32, hipStream_t s);
-hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, hipStream_t s);
+hipError_t launch_formal_solve(const SolveArgs &a, const SolveConfig &cfg, int fp32, hipStream_t s);
+hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, unsigned long long *point_cost,
+                              hipStream_t s);
+hipError_t sort_by_cost(unsigned long long *cost, int32_t *order, int64_t P, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_model_update(int n_models, unsigned long long *change, uint8_t *done, int32_t *iters,
+                               double *last, double tol, int32_t *active, hipStream_t s);
 hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double *nh2,
                          const double *T, int64_t P, int use_alo, const double *pops_old,
                          const double *J, const double *Jeff, const double *L, double *pops_new,
-                         uint8_t *flags, ConvPartial *partials, int64_t n_blocks, hipStream_t s);
+                         uint8_t *flags, ConvPartial *partials, int64_t n_blocks,
+                         const uint8_t *model_done, const int32_t *model_of,
+                         unsigned long long *model_change, hipStream_t s);
 int64_t stateq_blocks(int64_t P);
 hipError_t launch_conv_final(const ConvPartial *partials, int64_t n, ConvResult *out,
                              hipStream_t s);

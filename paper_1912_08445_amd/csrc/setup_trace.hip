@@ -5,6 +5,8 @@
 // sub-steps) that must not depend on fused rounding.
 #include <hipcub/hipcub.hpp>
 
+#include <vector>
+
 #include "nlte_internal.h"
 
 namespace nlte {
@@ -139,6 +141,34 @@ hipError_t launch_walk_fill(const CellRec *cell, const int32_t *nbr, int k, cons
 hipError_t scan_lengths(int64_t *arr, int64_t n, void *tmp, size_t *tmp_bytes, hipStream_t s)
 {
     return hipcub::DeviceScan::InclusiveSum(tmp, *tmp_bytes, arr + 1, arr + 1, (int)n, s);
+}
+
+// Order of the points by decreasing cost (stable: equal costs keep increasing index).
+hipError_t sort_by_cost(unsigned long long *cost, int32_t *order, int64_t P, hipStream_t s)
+{
+    unsigned long long *keys_out = nullptr;
+    int32_t *idx_in = nullptr;
+    hipError_t e = hipMalloc((void **)&keys_out, sizeof(unsigned long long) * P);
+    if (e == hipSuccess) e = hipMalloc((void **)&idx_in, sizeof(int32_t) * P);
+    if (e == hipSuccess) {
+        std::vector<int32_t> h(P);
+        for (int64_t i = 0; i < P; ++i) h[i] = (int32_t)i;
+        e = hipMemcpy(idx_in, h.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice);
+    }
+    size_t tmp_bytes = 0;
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp_bytes, cost, keys_out, idx_in, order, (int)P,
+                                                         0, 64, s);
+    void *tmp = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 1);
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairsDescending(tmp, tmp_bytes, cost, keys_out, idx_in, order, (int)P, 0,
+                                                         64, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (tmp) (void)hipFree(tmp);
+    if (keys_out) (void)hipFree(keys_out);
+    if (idx_in) (void)hipFree(idx_in);
+    return e;
 }
 
 }  // namespace nlte

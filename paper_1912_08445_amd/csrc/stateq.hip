@@ -97,14 +97,22 @@ __global__ __launch_bounds__(256) void k_stateq(SpeciesDev sp, const CellRec *__
                                                 const double *__restrict__ Jeff,
                                                 const double *__restrict__ L,
                                                 double *__restrict__ pops_new,
-                                                uint8_t *__restrict__ flags, ConvPartial *partials)
+                                                uint8_t *__restrict__ flags, ConvPartial *partials,
+                                                const uint8_t *__restrict__ model_done,
+                                                const int32_t *__restrict__ model_of,
+                                                unsigned long long *__restrict__ model_change)
 {
     __shared__ double s_max[256], s_sum[256];
     __shared__ int64_t s_cnt[256], s_fb[256], s_kept[256];
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double mx = 0.0, sum = 0.0;
     int64_t cnt = 0, fb = 0, kept = 0;
-    if (p < P) {
+    const bool skip = p < P && model_done != nullptr && model_done[model_of[p]];
+    if (skip) {
+        // converged model: populations stay as they are
+        for (int i = 0; i < sp.n_lev; ++i) pops_new[p * sp.n_lev + i] = pops_old[p * sp.n_lev + i];
+        if (flags) flags[p] = 0;
+    } else if (p < P) {
         const int n = sp.n_lev, nl = sp.n_lines;
         const double T = Tg[p], nh = nh2[p], nt = cell[p].ntot;
         double x[kMaxLev];
@@ -131,6 +139,9 @@ __global__ __launch_bounds__(256) void k_stateq(SpeciesDev sp, const CellRec *__
         if (flags) flags[p] = f;
         fb = (f == 1);
         kept = (f == 2);
+        // per-model maximum: non-negative doubles order like their bit patterns
+        if (model_change != nullptr && cnt > 0)
+            atomicMax(&model_change[model_of[p]], (unsigned long long)__double_as_longlong(mx));
     }
     const int t = threadIdx.x;
     s_max[t] = mx;
@@ -165,11 +176,66 @@ int64_t stateq_blocks(int64_t P) { return (P + 255) / 256; }
 hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double *nh2,
                          const double *T, int64_t P, int use_alo, const double *pops_old,
                          const double *J, const double *Jeff, const double *L, double *pops_new,
-                         uint8_t *flags, ConvPartial *partials, int64_t n_blocks, hipStream_t s)
+                         uint8_t *flags, ConvPartial *partials, int64_t n_blocks,
+                         const uint8_t *model_done, const int32_t *model_of,
+                         unsigned long long *model_change, hipStream_t s)
 {
     if (P == 0) return hipSuccess;
     hipLaunchKernelGGL(k_stateq, dim3((unsigned)n_blocks), dim3(256), 0, s, sp, cell, nh2, T, P,
-                       use_alo, pops_old, J, Jeff, L, pops_new, flags, partials);
+                       use_alo, pops_old, J, Jeff, L, pops_new, flags, partials, model_done, model_of,
+                       model_change);
+    return hipGetLastError();
+}
+
+// Per-model convergence after an iteration: a model still iterating counts one more
+// iteration, records its maximum relative change and stops once it is below tol.
+__global__ void k_model_update(int n_models, const unsigned long long *__restrict__ change,
+                               uint8_t *__restrict__ done, int32_t *__restrict__ iters,
+                               double *__restrict__ last, double tol, int32_t *active)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_models || done[m]) return;
+    iters[m] += 1;
+    const double ch = __longlong_as_double((long long)change[m]);
+    last[m] = ch;
+    if (ch < tol)
+        done[m] = 1;
+    else
+        atomicAdd(active, 1);
+}
+
+hipError_t launch_model_update(int n_models, unsigned long long *change, uint8_t *done, int32_t *iters,
+                               double *last, double tol, int32_t *active, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_model_update, dim3((n_models + 255) / 256), dim3(256), 0, s, n_models, change, done,
+                       iters, last, tol, active);
+    return hipGetLastError();
+}
+
+// Fill kernels (used instead of memset nodes so that the iteration can be captured).
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -1,0 +1,108 @@
+"""Batched models, per-model convergence, graph replay, the persistent work queue and
+the autotuner, through the C ABI."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from _common import oracle_for, rel, solver_for
+from synth import configs
+from synth.configs import Workload
+from synth.models import concat_models
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(n_models=5, seed0=500):
+    w = configs.batch256(n_models=n_models, n_min=300, n_max=1500, seed0=seed0)
+    return w
+
+
+def split_workload(w, m):
+    o0, o1 = w.offsets[m], w.offsets[m + 1]
+    from synth.models import Model
+    mm = w.model
+    sub = Model(mm.pos[o0:o1], mm.vel[o0:o1], mm.n_h2[o0:o1], mm.temperature[o0:o1], mm.v_turb[o0:o1],
+                mm.abundance[o0:o1], mm.nbr[o0:o1])
+    return Workload(f"model{m}", sub, w.species, w.rays, w.quad_x, w.quad_w, max_iter=w.max_iter, tol=w.tol)
+
+
+def test_batched_equals_separate_models():
+    """Each model of a batch converges on its own and ends where a run of that model
+    alone ends; the batch report counts the converged models."""
+    w = small_batch()
+    w.tol, w.max_iter = 1e-6, 40
+    s = solver_for(w, use_graph=0)
+    pops, rep = s.run_ali()
+    iters, conv, last = s.model_status()
+    assert rep["n_models_converged"] == conv.sum() == w.n_models
+    for m in range(w.n_models):
+        wm = split_workload(w, m)
+        sm = solver_for(wm, use_graph=0)
+        pm, repm = sm.run_ali()
+        assert repm["iterations"] == iters[m]
+        o0, o1 = w.offsets[m], w.offsets[m + 1]
+        assert rel(pops[o0:o1], pm).max() <= 1e-13
+    assert len(set(iters.tolist())) >= 1
+
+
+def test_batched_first_iteration_vs_oracle():
+    w = small_batch(3, seed0=900)
+    s = solver_for(w, max_iter=1, tol=0.0)
+    lte = s.lte()
+    new, _ = s.run_ali(lte)
+    for m in range(w.n_models):
+        wm = split_workload(w, m)
+        o = oracle_for(wm)
+        o0, o1 = w.offsets[m], w.offsets[m + 1]
+        J, Je, L = o.formal_solve(lte[o0:o1])
+        po, _ = o.stateq(lte[o0:o1], J, Je, L)
+        assert rel(new[o0:o1], po).max() <= 1e-10
+
+
+def test_graph_replay_matches_eager():
+    """Graph replays (with host synchronisation between replays) give exactly the eager
+    iterations, also when the captured graphs are reused by a second run."""
+    w = small_batch(4, seed0=700)
+    w.tol, w.max_iter = 0.0, 12
+    se = solver_for(w, use_graph=0)
+    sg = solver_for(w, use_graph=1)
+    pe, re_ = se.run_ali()
+    pg, rg = sg.run_ali()
+    assert np.array_equal(pe, pg)
+    assert re_["max_change"] == rg["max_change"]
+    pg2, rg2 = sg.run_ali()
+    assert np.array_equal(pg, pg2)
+
+
+@pytest.mark.parametrize("kw", [dict(persistent=1), dict(lines_per_lane=1), dict(high_occupancy=0),
+                                dict(persistent=1, lines_per_lane=1, high_occupancy=0)])
+def test_launch_variants_identical(kw):
+    w = configs.outflow5(n_points=3000, seed=13)
+    base = solver_for(w)
+    pops = base.lte()
+    ref = base.formal_solve(pops)
+    var = solver_for(w, **kw)
+    out = var.formal_solve(pops)
+    for a, b in zip(ref, out):
+        assert rel(a, b).max() <= 1e-14
+
+
+def test_autotune_choice_and_cache():
+    w = configs.outflow5(n_points=4000, seed=14)
+    s = solver_for(w)
+    pops = s.lte()
+    ref = s.formal_solve(pops)
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "tune.txt")
+        c1 = s.autotune(cache, trials=2)
+        assert "lpl=" in c1 and "(cached)" not in c1
+        out = s.formal_solve(pops)
+        for a, b in zip(ref, out):
+            assert rel(a, b).max() <= 1e-14
+        s2 = solver_for(w)
+        c2 = s2.autotune(cache, trials=2)
+        assert c2.endswith("(cached)") and c2.split()[:3] == c1.split()[:3]
+        s2.set_params(max_iter=2)            # a later parameter change keeps the choice
+        assert s2.params.lines_per_lane == int(c1.split()[0].split("=")[1])
