@@ -69,6 +69,7 @@ def lib():
         L.or_run_ali.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int, C.c_double, _dp]
         L.or_walk_all.argtypes = [C.c_void_p, _lp, C.c_void_p]
         L.or_walk_all.restype = C.c_int64
+        L.or_features.argtypes = [C.c_void_p, _dp]
         _lib = L
     return _lib
 
@@ -168,6 +169,12 @@ class Oracle:
         cells = np.zeros(max(tot, 1), dtype=np.int32)
         self._L.or_walk_all(self.c, off, cells.ctypes.data)
         return off, cells[:tot]
+
+    def features(self):
+        """Warm-start surrogate inputs [P][8] (raw, unstandardised)."""
+        out = np.zeros((self.P, 8))
+        self._L.or_features(self.c, out)
+        return out
 
     def pair_nodes(self, pops, O, pair):
         pops = _f64(pops)

@@ -735,3 +735,78 @@ int64_t or_walk_all(const or_ctx *c, int64_t *off, int32_t *cells)
     }
     return off[n];
 }
+
+/* ------------------------------------------------------------------ warm-start features */
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Inputs of the warm-start surrogate (not part of the paper's method; they describe
+ * the local conditions its starting populations are predicted from).  Per point p,
+ * F[p][0..7]:
+ *   0  log10 n_H2,   1  log10 T,
+ *   2  log10 max(g, 1e-30) with g the mean over p's valid neighbours m of
+ *      |v_m - v_p| / |x_m - x_p| (0 without neighbours),
+ *   3..7  log10 max(N, 1) of the minimum, lower quartile, median, upper quartile and
+ *      maximum over all rays of the H2 column N from p to the end of its walk (Sec. 3.2):
+ *      the trapezoid sum of n_H2 over the projected distances between consecutive
+ *      cells, starting at p with projection 0.  A quantile at q is the linear
+ *      interpolation between order statistics at position q (n_rays - 1). */
+void or_features(const or_ctx *c, double *F)
+{
+    const int R = c->n_rays;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < c->P; ++p) {
+        double *f = F + 8 * p;
+        f[0] = log10(c->nh2[p]);
+        f[1] = log10(c->T[p]);
+        double gsum = 0.0;
+        int gcount = 0;
+        for (int s = 0; s < c->k; ++s) {
+            int32_t m = c->nbr[p * c->k + s];
+            if (m < 0) continue;
+            double dv[3], dx[3];
+            for (int d = 0; d < 3; ++d) {
+                dv[d] = c->vel[3 * (int64_t)m + d] - c->vel[3 * p + d];
+                dx[d] = c->pos[3 * (int64_t)m + d] - c->pos[3 * p + d];
+            }
+            double nv = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
+            double nx = sqrt((dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]);
+            gsum += nv / nx;
+            ++gcount;
+        }
+        double g = gcount > 0 ? gsum / gcount : 0.0;
+        f[2] = log10(g > 1e-30 ? g : 1e-30);
+
+        double *col = malloc(sizeof(double) * R);
+        for (int r = 0; r < R; ++r) {
+            int len = or_walk(c, p, r, NULL, NULL, 0);
+            int32_t *cells = malloc(sizeof(int32_t) * (len > 0 ? len : 1));
+            double *Zs = malloc(sizeof(double) * (len > 0 ? len : 1));
+            or_walk(c, p, r, cells, Zs, len);
+            double N = 0.0, n_prev = c->nh2[p], z_prev = 0.0;
+            for (int i = 0; i < len; ++i) {
+                double n_i = c->nh2[cells[i]];
+                N += 0.5 * (n_prev + n_i) * (Zs[i] - z_prev);
+                n_prev = n_i;
+                z_prev = Zs[i];
+            }
+            col[r] = N;
+            free(cells);
+            free(Zs);
+        }
+        qsort(col, R, sizeof(double), cmp_double);
+        static const double qs[5] = {0.0, 0.25, 0.5, 0.75, 1.0};
+        for (int j = 0; j < 5; ++j) {
+            double h = qs[j] * (R - 1);
+            int i = (int)floor(h);
+            double v = col[i];
+            if (i + 1 < R) v = col[i] + (h - i) * (col[i + 1] - col[i]);
+            f[3 + j] = log10(v > 1.0 ? v : 1.0);
+        }
+        free(col);
+    }
+}

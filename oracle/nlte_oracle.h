@@ -36,4 +36,6 @@ double or_rel_change(const or_ctx *c, const double *old, const double *nw, doubl
 int or_run_ali(const or_ctx *c, const double *pops_init, double *pops_out, int max_iter, double tol,
                double *max_change);
 int64_t or_walk_all(const or_ctx *c, int64_t *off, int32_t *cells);
+
+void or_features(const or_ctx *c, double *F);
 #endif
