@@ -236,6 +236,92 @@ nlte_status nlte_get_model_status(nlte_ctx *ctx, int32_t *iterations, uint8_t *c
  */
 nlte_status nlte_autotune(nlte_ctx *ctx, const char *cache_path, int trials, char *choice, int cap);
 
+/* ---------------------------------------------------------------- warm start */
+
+/*
+ * Learned starting populations for the ALI.  The paper's iteration (Sec. 2.2.1, 3.4)
+ * needs initial populations and is otherwise started in LTE; this surrogate predicts
+ * them from local conditions instead.  It is not part of the paper's method: the ALI
+ * run from the prediction is still what decides the result, and nlte_run_ali_warm falls
+ * back to an LTE start when it does not converge.
+ *
+ * Features, per point (nlte_features, FP64 [P][8], needs nlte_trace):
+ *   0 log10 n_H2; 1 log10 T; 2 log10 of the mean over the point's neighbours of
+ *   |v_m - v_p| / |x_m - x_p| (floored at 1e-30 s^-1); 3..7 log10 of the minimum, lower
+ *   quartile, median, upper quartile and maximum over all rays of the H2 column from the
+ *   point to the end of its cached walk (Sec. 3.2; trapezoid in the projected distance,
+ *   floored at 1 cm^-2; quantiles interpolate linearly between order statistics at
+ *   position q (n_rays - 1)).
+ * Network: 8 standardised inputs -> 128 -> 128 -> 128 -> n_out, erf GELU after each
+ * hidden layer; output i is the departure of level i from LTE, log10 (f_i / f_i^LTE),
+ * with f_i = n_i / (abundance n_H2) and f_i^LTE the Boltzmann fraction at the point's
+ * temperature (both floored at 1e-300); an output of zero is the LTE start.
+ * Parameters: one FP32 vector [nlte_mlp_param_count(n_out)], matrices row-major
+ * [out][in], order W1 [128][8], b1, W2 [128][128], b2, W3 [128][128], b3, W4 [n_out][128],
+ * b4.  Products use bfloat16 operands (inputs, weights, hidden activations and output
+ * gradients rounded to nearest even) with FP32 accumulation; biases, master weights and
+ * Adam moments are FP32.  Loss: mean squared error over rows and outputs.
+ */
+#define NLTE_MLP_INPUTS 8
+#define NLTE_MLP_HIDDEN 128
+
+typedef struct {
+    int64_t steps;   /* optimiser steps */
+    int batch;       /* rows per step (1..65536); step t (counted since init/set_weights) takes rows
+                        (t-1)*batch ... t*batch-1 modulo the row count */
+    double lr, beta1, beta2, eps;  /* Adam (Kingma & Ba 2015) */
+} nlte_train_params;
+
+/* steps 1000, batch 4096, lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8. */
+void nlte_default_train_params(nlte_train_params *p);
+
+/* Parameter count for n_out outputs (35,466 for 10); -1 if n_out is outside 1..16. */
+int64_t nlte_mlp_param_count(int n_out);
+
+/* Raw (unstandardised) features of every point, F [P][8]. */
+nlte_status nlte_features(nlte_ctx *ctx, double *F);
+nlte_status nlte_features_dev(nlte_ctx *ctx, double *d_F, void *stream);
+
+/* Fresh network with n_out (1..16) outputs: weights uniform in +-sqrt(6/(in+out)) from a
+ * SplitMix64 stream seeded with `seed` (layer by layer, row-major), zero biases; resets
+ * the optimiser and keeps the current standardisation (initially mean 0, std 1). */
+nlte_status nlte_mlp_init(nlte_ctx *ctx, int n_out, uint64_t seed);
+/* Replace the parameters (host FP32 vector as above; must be finite); resets the optimiser. */
+nlte_status nlte_mlp_set_weights(nlte_ctx *ctx, int n_out, const float *theta);
+nlte_status nlte_mlp_get_weights(nlte_ctx *ctx, float *theta);
+/* Feature standardisation used by predict: x = (F - mean) / std ([8] each, std > 0). */
+nlte_status nlte_mlp_set_norm(nlte_ctx *ctx, const double *mean, const double *std);
+
+/* Training rows of the current model from populations d_pops [P][n_lev] (device):
+ * standardised features d_X [P][8] (with the current standardisation, so it need not
+ * have weights yet) and targets d_T [P][n_lev], the departures log10 (f_i / f_i^LTE). */
+nlte_status nlte_mlp_rows_dev(nlte_ctx *ctx, const double *d_pops, float *d_X, float *d_T, void *stream);
+
+/* Network outputs Y [n][n_out] for standardised inputs X [n][8] (host FP32). */
+nlte_status nlte_mlp_forward(nlte_ctx *ctx, const float *X, int64_t n, float *Y);
+/* Loss and gradient over all n rows (1..65536) as one batch, without an update;
+ * grad [n_params] (nullable), loss (nullable). */
+nlte_status nlte_mlp_loss_grad(nlte_ctx *ctx, const float *X, const float *T, int64_t n, float *grad,
+                               double *loss);
+/* Adam on rows X [n][8] (standardised), targets T [n][n_out]; loss_curve [steps]
+ * (nullable) receives each step's batch loss before its update. */
+nlte_status nlte_mlp_train(nlte_ctx *ctx, const float *X, const float *T, int64_t n,
+                           const nlte_train_params *tp, float *loss_curve);
+nlte_status nlte_mlp_train_dev(nlte_ctx *ctx, const float *d_X, const float *d_T, int64_t n,
+                               const nlte_train_params *tp, float *d_loss_curve, void *stream);
+
+/* Starting populations pops [P][n_lev] for the current model (n_out must equal n_lev):
+ * abundance * n_H2 * w_i / sum_j w_j, w_i = f_i^LTE 10^y_i, from the network outputs y.  Points whose
+ * prediction is not finite get LTE populations; *n_fallback (nullable) counts them. */
+nlte_status nlte_mlp_predict(nlte_ctx *ctx, double *pops, int64_t *n_fallback);
+nlte_status nlte_mlp_predict_dev(nlte_ctx *ctx, double *d_pops, int64_t *n_fallback, void *stream);
+
+/* ALI from the predicted populations; if that stops at max_iter above tol it is run
+ * again from LTE.  *used_network (nullable) tells which start the result came from. */
+nlte_status nlte_run_ali_warm(nlte_ctx *ctx, double *pops_out, nlte_ali_report *rep, int *used_network);
+nlte_status nlte_run_ali_warm_dev(nlte_ctx *ctx, double *d_pops_out, nlte_ali_report *rep,
+                                  int *used_network, void *stream);
+
 /* ---------------------------------------------------------------- profiling */
 
 /* With params.profile = 1: accumulated HIP-event time [ms] and launch count of kernel

@@ -7,9 +7,10 @@ CPU-baseline leg are its only users.  The HIP library never imports or links it.
 
 The surrogate is not part of the paper's method; the paper's ALI (Sec. 2.2.1, 3.4)
 only needs some initial populations, which it otherwise takes in LTE.  Network:
-8 standardised features -> 128 -> 128 -> 128 -> n_out (one output per level, the
-log10 of the fractional population), erf-form GELU after each hidden layer, loss the
-mean squared error over rows and outputs, optimiser Adam.
+8 standardised features -> 128 -> 128 -> 128 -> n_out (one output per level, its
+departure from LTE log10 (f_i / f_i^LTE) with f the fractional population), erf-form
+GELU after each hidden layer, loss the mean squared error over rows and outputs,
+optimiser Adam.
 
 Parameters are one flat vector, in this order, every matrix row-major [out][in]:
     W1 [128][8], b1 [128], W2 [128][128], b2 [128], W3 [128][128], b3 [128],
@@ -149,8 +150,21 @@ def standardise(F, mean, std):
     return (np.asarray(F, dtype=np.float64) - mean) / std
 
 
-def populations(y, ntot):
-    """Level populations from predicted log10 fractions: ntot 10^y_i / sum_j 10^y_j."""
-    y = np.asarray(y, dtype=np.float64)
-    e = 10.0 ** (y - y.max(axis=1, keepdims=True))
-    return np.asarray(ntot, dtype=np.float64)[:, None] * e / e.sum(axis=1, keepdims=True)
+def targets(pops, lte_pops):
+    """Training targets: departures from LTE, log10 (f_i / f_i^LTE), with fractional
+    populations f = n / ntot (ntot = the sum over levels) floored at 1e-300."""
+    p = np.asarray(pops, dtype=np.float64)
+    q = np.asarray(lte_pops, dtype=np.float64)
+    f = np.maximum(p / p.sum(axis=1, keepdims=True), 1e-300)
+    fl = np.maximum(q / q.sum(axis=1, keepdims=True), 1e-300)
+    return np.log10(f) - np.log10(fl)
+
+
+def populations(y, lte_pops):
+    """Level populations from predicted departures y: ntot w_i / sum_j w_j with
+    w_i = f_i^LTE 10^y_i, ntot the sum of the LTE populations over levels."""
+    q = np.asarray(lte_pops, dtype=np.float64)
+    ntot = q.sum(axis=1, keepdims=True)
+    a = np.log10(np.maximum(q / ntot, 1e-300)) + np.asarray(y, dtype=np.float64)
+    w = 10.0 ** (a - a.max(axis=1, keepdims=True))
+    return ntot * w / w.sum(axis=1, keepdims=True)

@@ -34,7 +34,14 @@ EXPORTS = (
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_stateq", "nlte_stateq_dev",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
     "nlte_kernel_stats", "nlte_reset_kernel_stats",
+    "nlte_default_train_params", "nlte_mlp_param_count", "nlte_features", "nlte_features_dev",
+    "nlte_mlp_init", "nlte_mlp_set_weights", "nlte_mlp_get_weights", "nlte_mlp_set_norm",
+    "nlte_mlp_forward", "nlte_mlp_loss_grad", "nlte_mlp_train", "nlte_mlp_train_dev",
+    "nlte_mlp_predict", "nlte_mlp_predict_dev", "nlte_mlp_rows_dev", "nlte_run_ali_warm", "nlte_run_ali_warm_dev",
 )
+
+MLP_INPUTS = 8
+MLP_HIDDEN = 128
 
 
 class Params(C.Structure):
@@ -52,6 +59,11 @@ class AliReport(C.Structure):
                 ("ms_total", C.c_double)]
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("batch", C.c_int), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
+
+
 class NlteError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libnlte error {code}: {msg}")
@@ -62,6 +74,15 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "or python paper_1912_08445_amd/build.py")
+    # torch's ROCm build carries its own HIP runtime with the same soname as the system's
+    # and asks for it by its unversioned name.  Loading torch first makes the library bind
+    # to that runtime instance; in the other order a second runtime would be loaded and
+    # torch would find no device.  Device tensors and streams are torch's, so there must
+    # be one runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.nlte_default_params.argtypes = [C.POINTER(Params)]
@@ -93,10 +114,30 @@ def load():
     L.nlte_autotune.argtypes = [vp, C.c_char_p, C.c_int, C.c_char_p, C.c_int]
     L.nlte_kernel_stats.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.nlte_reset_kernel_stats.argtypes = [vp]
+    L.nlte_default_train_params.argtypes = [C.POINTER(TrainParams)]
+    L.nlte_default_train_params.restype = None
+    L.nlte_mlp_param_count.argtypes = [C.c_int]
+    L.nlte_features.argtypes = [vp, vp]
+    L.nlte_features_dev.argtypes = [vp, vp, vp]
+    L.nlte_mlp_init.argtypes = [vp, C.c_int, C.c_uint64]
+    L.nlte_mlp_set_weights.argtypes = [vp, C.c_int, vp]
+    L.nlte_mlp_get_weights.argtypes = [vp, vp]
+    L.nlte_mlp_set_norm.argtypes = [vp, vp, vp]
+    L.nlte_mlp_forward.argtypes = [vp, vp, i64, vp]
+    L.nlte_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp, C.POINTER(dbl)]
+    L.nlte_mlp_train.argtypes = [vp, vp, vp, i64, C.POINTER(TrainParams), vp]
+    L.nlte_mlp_train_dev.argtypes = [vp, vp, vp, i64, C.POINTER(TrainParams), vp, vp]
+    L.nlte_mlp_predict.argtypes = [vp, vp, C.POINTER(i64)]
+    L.nlte_mlp_predict_dev.argtypes = [vp, vp, C.POINTER(i64), vp]
+    L.nlte_mlp_rows_dev.argtypes = [vp, vp, vp, vp, vp]
+    L.nlte_run_ali_warm.argtypes = [vp, vp, C.POINTER(AliReport), C.POINTER(C.c_int)]
+    L.nlte_run_ali_warm_dev.argtypes = [vp, vp, C.POINTER(AliReport), C.POINTER(C.c_int), vp]
     for name in EXPORTS:
         fn = getattr(L, name)   # AttributeError if the library lacks a declared entry point
-        if name not in ("nlte_destroy", "nlte_default_params", "nlte_last_error"):
+        if name not in ("nlte_destroy", "nlte_default_params", "nlte_last_error",
+                        "nlte_default_train_params"):
             fn.restype = C.c_int
+    L.nlte_mlp_param_count.restype = C.c_int64
     return L
 
 
@@ -306,6 +347,95 @@ class Solver:
         self.params.persistent = int(fields["persistent"])
         return choice
 
+    # ---------------------------------------------------------------- warm start
+    def features(self):
+        out = np.zeros((self.P, MLP_INPUTS))
+        self._chk(self.L.nlte_features(self.h, _p(out)))
+        return out
+
+    def features_dev(self, F, stream=None):
+        self._chk(self.L.nlte_features_dev(self.h, _tp(F), _stream(stream)))
+
+    def mlp_init(self, n_out, seed=0):
+        self.n_out = int(n_out)
+        self._chk(self.L.nlte_mlp_init(self.h, self.n_out, int(seed)))
+
+    def mlp_set_weights(self, theta, n_out):
+        t = _c(theta, np.float32)
+        if t.shape != (param_count(n_out),):
+            raise ValueError("parameter vector has the wrong length")
+        self.n_out = int(n_out)
+        self._chk(self.L.nlte_mlp_set_weights(self.h, self.n_out, _p(t)))
+
+    def mlp_get_weights(self):
+        out = np.zeros(param_count(self.n_out), dtype=np.float32)
+        self._chk(self.L.nlte_mlp_get_weights(self.h, _p(out)))
+        return out
+
+    def mlp_set_norm(self, mean, std):
+        m, s = _c(mean, np.float64), _c(std, np.float64)
+        if m.shape != (MLP_INPUTS,) or s.shape != (MLP_INPUTS,):
+            raise ValueError("mean and std need 8 entries")
+        self._chk(self.L.nlte_mlp_set_norm(self.h, _p(m), _p(s)))
+
+    def mlp_forward(self, X):
+        X = _c(X, np.float32)
+        Y = np.zeros((X.shape[0], self.n_out), dtype=np.float32)
+        self._chk(self.L.nlte_mlp_forward(self.h, _p(X), X.shape[0], _p(Y)))
+        return Y
+
+    def mlp_loss_grad(self, X, T):
+        X, T = _c(X, np.float32), _c(T, np.float32)
+        g = np.zeros(param_count(self.n_out), dtype=np.float32)
+        loss = C.c_double()
+        self._chk(self.L.nlte_mlp_loss_grad(self.h, _p(X), _p(T), X.shape[0], _p(g), C.byref(loss)))
+        return loss.value, g
+
+    def mlp_train(self, X, T, **kw):
+        X, T = _c(X, np.float32), _c(T, np.float32)
+        tp = train_params(**kw)
+        curve = np.zeros(max(tp.steps, 1), dtype=np.float32)
+        self._chk(self.L.nlte_mlp_train(self.h, _p(X), _p(T), X.shape[0], C.byref(tp), _p(curve)))
+        return curve[:tp.steps]
+
+    def mlp_train_dev(self, X, T, loss_curve=None, stream=None, **kw):
+        tp = train_params(**kw)
+        self._chk(self.L.nlte_mlp_train_dev(self.h, _tp(X), _tp(T), X.shape[0], C.byref(tp),
+                                            _tp(loss_curve), _stream(stream)))
+
+    def mlp_rows_dev(self, pops, X, T, stream=None):
+        """Standardised features X [P][8] and targets T [P][n_lev] (float32 GPU tensors)."""
+        self._chk(self.L.nlte_mlp_rows_dev(self.h, _tp(pops), _tp(X), _tp(T), _stream(stream)))
+
+    def mlp_predict(self):
+        out = np.zeros((self.P, self.n_lev))
+        nb = C.c_int64()
+        self._chk(self.L.nlte_mlp_predict(self.h, _p(out), C.byref(nb)))
+        return out, nb.value
+
+    def mlp_predict_dev(self, pops, stream=None):
+        nb = C.c_int64()
+        self._chk(self.L.nlte_mlp_predict_dev(self.h, _tp(pops), C.byref(nb), _stream(stream)))
+        return nb.value
+
+    def run_ali_warm(self):
+        out = np.zeros((self.P, self.n_lev))
+        rep = AliReport()
+        used = C.c_int()
+        rc = self._chk(self.L.nlte_run_ali_warm(self.h, _p(out), C.byref(rep), C.byref(used)), warn_ok=True)
+        d = report_dict(rep, rc)
+        d["used_network"] = bool(used.value)
+        return out, d
+
+    def run_ali_warm_dev(self, pops_out, stream=None):
+        rep = AliReport()
+        used = C.c_int()
+        rc = self._chk(self.L.nlte_run_ali_warm_dev(self.h, _tp(pops_out), C.byref(rep), C.byref(used),
+                                                    _stream(stream)), warn_ok=True)
+        d = report_dict(rep, rc)
+        d["used_network"] = bool(used.value)
+        return d
+
     # ---------------------------------------------------------------- profiling
     def kernel_stats(self, name):
         ms, n = C.c_double(), C.c_int64()
@@ -314,6 +444,18 @@ class Solver:
 
     def reset_kernel_stats(self):
         self._chk(self.L.nlte_reset_kernel_stats(self.h))
+
+
+def param_count(n_out):
+    return int(lib().nlte_mlp_param_count(int(n_out)))
+
+
+def train_params(**kw):
+    tp = TrainParams()
+    lib().nlte_default_train_params(C.byref(tp))
+    for k, v in kw.items():
+        setattr(tp, k, v)
+    return tp
 
 
 def report_dict(rep, rc):

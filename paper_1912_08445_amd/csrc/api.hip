@@ -244,6 +244,174 @@ nlte_status ensure_graph(nlte_ctx *c, int slot, const double *cur, double *nxt)
     return NLTE_OK;
 }
 
+
+// ------------------------------------------------------------------ warm start helpers
+
+// Largest batch of one gradient evaluation: its workgroup partials take
+// ceil(rows / 64) * n_params FP32 values (145 MB at the limit).
+constexpr int kMlpMaxRows = 1 << 16;
+
+MlpDims mlp_dims(int n_out)
+{
+    MlpDims d{};
+    const int ins[4] = {8, 128, 128, 128};
+    const int outs[4] = {128, 128, 128, n_out};
+    int64_t off = 0;
+    for (int l = 0; l < 4; ++l) {
+        d.in[l] = ins[l];
+        d.out[l] = outs[l];
+        d.w_off[l] = off;
+        off += (int64_t)ins[l] * outs[l];
+        d.b_off[l] = off;
+        off += outs[l];
+    }
+    d.n_params = off;
+    return d;
+}
+
+nlte_status need_mlp(nlte_ctx *c)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!c->mlp.ready) return fail(c, NLTE_E_STATE, "the warm-start network has no weights (nlte_mlp_init or nlte_mlp_set_weights)");
+    return NLTE_OK;
+}
+
+// Allocate the network state for n_out outputs and reset the optimiser.
+nlte_status mlp_alloc(nlte_ctx *c, int n_out)
+{
+    if (n_out < 1 || n_out > kMaxLev) return fail(c, NLTE_E_INVALID_ARG, "n_out must be in 1..16");
+    MlpState &m = c->mlp;
+    m.dims = mlp_dims(n_out);
+    const int64_t np = m.dims.n_params;
+    nlte_status st;
+    if ((st = dalloc(c, &m.d_theta, np))) return st;
+    if ((st = dalloc(c, &m.d_m, np))) return st;
+    if ((st = dalloc(c, &m.d_v, np))) return st;
+    if ((st = dalloc(c, &m.d_grad, np))) return st;
+    if ((st = dalloc(c, (char **)&m.d_frags, (size_t)mlp_frag_count() * 64 * 16))) return st;
+    if (!m.d_bad && (st = dalloc(c, &m.d_bad, 1))) return st;
+    HIPCHK(c, hipMemset(m.d_m, 0, sizeof(float) * np));
+    HIPCHK(c, hipMemset(m.d_v, 0, sizeof(float) * np));
+    m.wg_cap = 0;
+    dfree(m.d_gpart);
+    dfree(m.d_lpart);
+    m.rows_cap = 0;
+    dfree(m.d_x);
+    dfree(m.d_y);
+    m.step = 0;
+    return NLTE_OK;
+}
+
+nlte_status mlp_upload(nlte_ctx *c, const std::vector<float> &theta)
+{
+    MlpState &m = c->mlp;
+    HIPCHK(c, hipMemcpy(m.d_theta, theta.data(), sizeof(float) * theta.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, launch_mlp_pack(m.d_theta, m.dims, m.d_frags, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    m.ready = true;
+    return NLTE_OK;
+}
+
+nlte_status mlp_ensure_wg(nlte_ctx *c, int64_t n_wg)
+{
+    MlpState &m = c->mlp;
+    if (n_wg <= m.wg_cap) return NLTE_OK;
+    nlte_status st;
+    if ((st = dalloc(c, &m.d_gpart, (size_t)n_wg * m.dims.n_params))) return st;
+    if ((st = dalloc(c, &m.d_lpart, (size_t)n_wg))) return st;
+    m.wg_cap = n_wg;
+    return NLTE_OK;
+}
+
+nlte_status mlp_ensure_rows(nlte_ctx *c, int64_t rows)
+{
+    MlpState &m = c->mlp;
+    if (rows <= m.rows_cap) return NLTE_OK;
+    nlte_status st;
+    if ((st = dalloc(c, &m.d_x, (size_t)rows * 8))) return st;
+    if ((st = dalloc(c, &m.d_y, (size_t)rows * 16))) return st;
+    m.rows_cap = rows;
+    return NLTE_OK;
+}
+
+nlte_status mlp_ensure_points(nlte_ctx *c)
+{
+    MlpState &m = c->mlp;
+    if (c->P <= m.pred_cap) return NLTE_OK;
+    nlte_status st;
+    if ((st = dalloc(c, &m.d_feat, (size_t)c->P * 8))) return st;
+    if ((st = dalloc(c, &m.d_xp, (size_t)c->P * 8))) return st;
+    if ((st = dalloc(c, &m.d_yp, (size_t)c->P * 16))) return st;
+    if ((st = dalloc(c, &m.d_pred, (size_t)c->P * kMaxLev))) return st;
+    m.pred_cap = c->P;
+    return NLTE_OK;
+}
+
+nlte_status features_impl(nlte_ctx *c, double *d_F, hipStream_t s)
+{
+    HIPCHK(c, launch_features(c->d_cell, c->d_nh2, c->d_T, c->d_nbr, c->k, c->d_roff, c->d_rcells, c->d_dir,
+                              c->n_rays, c->P, d_F, s));
+    return NLTE_OK;
+}
+
+// Features -> standardised inputs -> network (departures from LTE) -> populations, over LTE populations for
+// points whose prediction is not finite.  The count of those lands in m.d_bad.
+nlte_status predict_impl(nlte_ctx *c, double *d_pops, hipStream_t s)
+{
+    MlpState &m = c->mlp;
+    nlte_status st;
+    if ((st = mlp_ensure_points(c))) return st;
+    if ((st = features_impl(c, m.d_feat, s))) return st;
+    HIPCHK(c, launch_mlp_standardise(m.d_feat, m.norm, c->P, m.d_xp, s));
+    HIPCHK(c, launch_mlp_forward(m.d_frags, m.d_theta, m.dims, m.d_xp, c->P, m.d_yp, s));
+    HIPCHK(c, launch_fill_u64(m.d_bad, 1, 0ull, s));
+    HIPCHK(c, launch_lte(c->sp, c->d_cell, c->d_T, c->P, d_pops, s));
+    HIPCHK(c, launch_mlp_populations(c->sp, m.d_yp, c->d_cell, c->d_T, c->P, d_pops, m.d_bad, s));
+    return NLTE_OK;
+}
+
+// Optimiser steps on device rows X [n][8], T [n][n_out].
+nlte_status train_impl(nlte_ctx *c, const float *d_X, const float *d_T, int64_t n, const nlte_train_params *tp,
+                       float *d_loss, hipStream_t s)
+{
+    MlpState &m = c->mlp;
+    const int n_wg = mlp_train_blocks(tp->batch);
+    nlte_status st;
+    if ((st = mlp_ensure_wg(c, n_wg))) return st;
+    const float inv_count = (float)(1.0 / ((double)tp->batch * m.dims.out[3]));
+    for (int64_t i = 0; i < tp->steps; ++i) {
+        const int64_t t = ++m.step;
+        const int64_t start = (int64_t)(((__int128)(t - 1) * tp->batch) % n);
+        HIPCHK(c, launch_mlp_train(m.d_frags, m.d_theta, m.dims, d_X, d_T, n, start, tp->batch, m.d_gpart,
+                                   m.d_lpart, s));
+        const float c1 = (float)(1.0 / (1.0 - pow(tp->beta1, (double)t)));
+        const float c2 = (float)(1.0 / (1.0 - pow(tp->beta2, (double)t)));
+        HIPCHK(c, launch_mlp_reduce_adam(m.d_theta, m.d_m, m.d_v, m.d_gpart, n_wg, m.dims.n_params, 1,
+                                         (float)tp->lr, (float)tp->beta1, (float)tp->beta2, (float)tp->eps, c1, c2,
+                                         m.d_lpart, inv_count, d_loss ? d_loss + i : nullptr, nullptr, s));
+        HIPCHK(c, launch_mlp_pack(m.d_theta, m.dims, m.d_frags, s));
+    }
+    return NLTE_OK;
+}
+
+nlte_status check_train_params(nlte_ctx *c, int64_t n, const nlte_train_params *tp)
+{
+    if (!tp || n < 1 || tp->steps < 0 || tp->batch < 1 || tp->batch > kMlpMaxRows || !(tp->lr >= 0.0) ||
+        !(tp->beta1 >= 0.0 && tp->beta1 < 1.0) || !(tp->beta2 >= 0.0 && tp->beta2 < 1.0) || !(tp->eps >= 0.0))
+        return fail(c, NLTE_E_INVALID_ARG, "invalid training parameters (n >= 1, batch 1..65536, 0 <= beta < 1, lr, eps >= 0)");
+    return NLTE_OK;
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014): the state advances by the golden-ratio
+// increment and each output is the state passed through two xor-shift-multiply rounds.
+uint64_t splitmix64(uint64_t &state)
+{
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 }  // namespace
 
 extern "C" {
@@ -334,6 +502,24 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_model_change);
     dfree(c->d_model_iters);
     dfree(c->d_model_last);
+    {
+        MlpState &m = c->mlp;
+        dfree(m.d_theta);
+        dfree(m.d_m);
+        dfree(m.d_v);
+        dfree(m.d_frags);
+        dfree(m.d_gpart);
+        dfree(m.d_lpart);
+        dfree(m.d_loss);
+        dfree(m.d_grad);
+        dfree(m.d_x);
+        dfree(m.d_y);
+        dfree(m.d_feat);
+        dfree(m.d_xp);
+        dfree(m.d_yp);
+        dfree(m.d_pred);
+        dfree(m.d_bad);
+    }
     drop_graphs(c);
     if (c->h_conv) (void)hipHostFree(c->h_conv);
     if (c->h_active) (void)hipHostFree(c->h_active);
@@ -1022,6 +1208,281 @@ nlte_status nlte_reset_kernel_stats(nlte_ctx *c)
     if (!c) return NLTE_E_INVALID_ARG;
     c->st_line_coef = c->st_formal = c->st_stateq = c->st_lte = c->st_trace = KernelStat{};
     return NLTE_OK;
+}
+
+
+// ------------------------------------------------------------------ warm start
+
+void nlte_default_train_params(nlte_train_params *p)
+{
+    if (!p) return;
+    p->steps = 1000;
+    p->batch = 4096;
+    p->lr = 1e-3;
+    p->beta1 = 0.9;
+    p->beta2 = 0.999;
+    p->eps = 1e-8;
+}
+
+int64_t nlte_mlp_param_count(int n_out)
+{
+    if (n_out < 1 || n_out > kMaxLev) return -1;
+    return mlp_dims(n_out).n_params;
+}
+
+nlte_status nlte_features_dev(nlte_ctx *c, double *d_F, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!d_F) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    return features_impl(c, d_F, pick(c, stream));
+}
+
+nlte_status nlte_features(nlte_ctx *c, double *F)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!F) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    double *d = nullptr;
+    if ((st = dalloc(c, &d, (size_t)c->P * 8))) return st;
+    st = features_impl(c, d, c->stream);
+    hipError_t e = hipSuccess;
+    if (!st) e = hipMemcpyAsync(F, d, sizeof(double) * c->P * 8, hipMemcpyDeviceToHost, c->stream);
+    if (!st && e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(d);
+    if (st) return st;
+    if (e != hipSuccess) return fail(c, NLTE_E_HIP, std::string("features copy: ") + hipGetErrorString(e));
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_init(nlte_ctx *c, int n_out, uint64_t seed)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    nlte_status st = mlp_alloc(c, n_out);
+    if (st) return st;
+    const MlpDims &d = c->mlp.dims;
+    std::vector<float> theta(d.n_params, 0.0f);
+    uint64_t state = seed;
+    for (int l = 0; l < 4; ++l) {
+        const double a = sqrt(6.0 / (double)(d.in[l] + d.out[l]));
+        for (int64_t i = 0; i < (int64_t)d.in[l] * d.out[l]; ++i) {
+            const double u = (double)(splitmix64(state) >> 11) * 0x1.0p-53;
+            theta[d.w_off[l] + i] = (float)(a * (2.0 * u - 1.0));
+        }
+    }
+    return mlp_upload(c, theta);
+}
+
+nlte_status nlte_mlp_set_weights(nlte_ctx *c, int n_out, const float *theta)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!theta) return fail(c, NLTE_E_INVALID_ARG, "null weights");
+    if (n_out < 1 || n_out > kMaxLev) return fail(c, NLTE_E_INVALID_ARG, "n_out must be in 1..16");
+    const int64_t np = mlp_dims(n_out).n_params;
+    std::vector<float> t(theta, theta + np);
+    for (int64_t i = 0; i < np; ++i)
+        if (!std::isfinite(t[i])) return fail(c, NLTE_E_INVALID_ARG, "non-finite weight");
+    HIPCHK(c, hipSetDevice(c->device));
+    nlte_status st = mlp_alloc(c, n_out);
+    if (st) return st;
+    return mlp_upload(c, t);
+}
+
+nlte_status nlte_mlp_get_weights(nlte_ctx *c, float *theta)
+{
+    nlte_status st = need_mlp(c);
+    if (st) return st;
+    if (!theta) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(theta, c->mlp.d_theta, sizeof(float) * c->mlp.dims.n_params, hipMemcpyDeviceToHost));
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_set_norm(nlte_ctx *c, const double *mean, const double *std)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!mean || !std) return fail(c, NLTE_E_INVALID_ARG, "null mean or std");
+    for (int f = 0; f < 8; ++f)
+        if (!std::isfinite(mean[f]) || !std::isfinite(std[f]) || !(std[f] > 0.0))
+            return fail(c, NLTE_E_INVALID_ARG, "mean must be finite and std finite and positive");
+    for (int f = 0; f < 8; ++f) {
+        c->mlp.norm.mean[f] = mean[f];
+        c->mlp.norm.std[f] = std[f];
+    }
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_forward(nlte_ctx *c, const float *X, int64_t n, float *Y)
+{
+    nlte_status st = need_mlp(c);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!X || !Y))) return fail(c, NLTE_E_INVALID_ARG, "invalid rows");
+    if (n == 0) return NLTE_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = mlp_ensure_rows(c, n))) return st;
+    MlpState &m = c->mlp;
+    const int no = m.dims.out[3];
+    HIPCHK(c, hipMemcpyAsync(m.d_x, X, sizeof(float) * n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_mlp_forward(m.d_frags, m.d_theta, m.dims, m.d_x, n, m.d_y, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Y, m.d_y, sizeof(float) * n * no, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_loss_grad(nlte_ctx *c, const float *X, const float *T, int64_t n, float *grad, double *loss)
+{
+    nlte_status st = need_mlp(c);
+    if (st) return st;
+    if (n < 1 || n > kMlpMaxRows || !X || !T) return fail(c, NLTE_E_INVALID_ARG, "invalid rows (1..65536)");
+    HIPCHK(c, hipSetDevice(c->device));
+    MlpState &m = c->mlp;
+    const int no = m.dims.out[3];
+    const int n_wg = mlp_train_blocks((int)n);
+    if ((st = mlp_ensure_rows(c, n))) return st;
+    if ((st = mlp_ensure_wg(c, n_wg))) return st;
+    if (!m.d_loss && (st = dalloc(c, &m.d_loss, 1))) return st;
+    if (m.loss_cap < 1) m.loss_cap = 1;
+    HIPCHK(c, hipMemcpyAsync(m.d_x, X, sizeof(float) * n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(m.d_y, T, sizeof(float) * n * no, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_mlp_train(m.d_frags, m.d_theta, m.dims, m.d_x, m.d_y, n, 0, (int)n, m.d_gpart, m.d_lpart,
+                               c->stream));
+    HIPCHK(c, launch_mlp_reduce_adam(m.d_theta, m.d_m, m.d_v, m.d_gpart, n_wg, m.dims.n_params, 0, 0.f, 0.f, 0.f,
+                                     0.f, 1.f, 1.f, m.d_lpart, (float)(1.0 / ((double)n * no)), m.d_loss, m.d_grad,
+                                     c->stream));
+    float lval = 0.f;
+    if (grad)
+        HIPCHK(c, hipMemcpyAsync(grad, m.d_grad, sizeof(float) * m.dims.n_params, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&lval, m.d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (loss) *loss = lval;
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_train_dev(nlte_ctx *c, const float *d_X, const float *d_T, int64_t n,
+                               const nlte_train_params *tp, float *d_loss_curve, void *stream)
+{
+    nlte_status st = need_mlp(c);
+    if (st) return st;
+    if ((st = check_train_params(c, n, tp))) return st;
+    if (!d_X || !d_T) return fail(c, NLTE_E_INVALID_ARG, "null rows");
+    HIPCHK(c, hipSetDevice(c->device));
+    return train_impl(c, d_X, d_T, n, tp, d_loss_curve, pick(c, stream));
+}
+
+nlte_status nlte_mlp_train(nlte_ctx *c, const float *X, const float *T, int64_t n, const nlte_train_params *tp,
+                           float *loss_curve)
+{
+    nlte_status st = need_mlp(c);
+    if (st) return st;
+    if ((st = check_train_params(c, n, tp))) return st;
+    if (!X || !T) return fail(c, NLTE_E_INVALID_ARG, "null rows");
+    HIPCHK(c, hipSetDevice(c->device));
+    MlpState &m = c->mlp;
+    const int no = m.dims.out[3];
+    if ((st = mlp_ensure_rows(c, n))) return st;
+    if (tp->steps > m.loss_cap) {
+        if ((st = dalloc(c, &m.d_loss, (size_t)tp->steps))) return st;
+        m.loss_cap = tp->steps;
+    }
+    HIPCHK(c, hipMemcpyAsync(m.d_x, X, sizeof(float) * n * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(m.d_y, T, sizeof(float) * n * no, hipMemcpyHostToDevice, c->stream));
+    if ((st = train_impl(c, m.d_x, m.d_y, n, tp, m.d_loss, c->stream))) return st;
+    if (loss_curve && tp->steps > 0)
+        HIPCHK(c, hipMemcpyAsync(loss_curve, m.d_loss, sizeof(float) * tp->steps, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_predict_dev(nlte_ctx *c, double *d_pops, int64_t *n_fallback, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if ((st = need_mlp(c))) return st;
+    if (c->mlp.dims.out[3] != c->n_lev) return fail(c, NLTE_E_STATE, "network outputs differ from the level count");
+    if (!d_pops) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick(c, stream);
+    if ((st = predict_impl(c, d_pops, s))) return st;
+    if (n_fallback) {
+        unsigned long long bad = 0;
+        HIPCHK(c, hipMemcpyAsync(&bad, c->mlp.d_bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        *n_fallback = (int64_t)bad;
+    }
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_predict(nlte_ctx *c, double *pops, int64_t *n_fallback)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!pops) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    if ((st = need_mlp(c))) return st;
+    if (c->mlp.dims.out[3] != c->n_lev) return fail(c, NLTE_E_STATE, "network outputs differ from the level count");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = mlp_ensure_points(c))) return st;
+    if ((st = predict_impl(c, c->mlp.d_pred, c->stream))) return st;
+    unsigned long long bad = 0;
+    HIPCHK(c, hipMemcpyAsync(pops, c->mlp.d_pred, sizeof(double) * c->P * c->n_lev, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&bad, c->mlp.d_bad, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (n_fallback) *n_fallback = (int64_t)bad;
+    return NLTE_OK;
+}
+
+nlte_status nlte_mlp_rows_dev(nlte_ctx *c, const double *d_pops, float *d_X, float *d_T, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!d_pops || !d_X || !d_T) return fail(c, NLTE_E_INVALID_ARG, "null pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = mlp_ensure_points(c))) return st;
+    hipStream_t s = pick(c, stream);
+    if ((st = features_impl(c, c->mlp.d_feat, s))) return st;
+    HIPCHK(c, launch_mlp_standardise(c->mlp.d_feat, c->mlp.norm, c->P, d_X, s));
+    HIPCHK(c, launch_mlp_targets(c->sp, d_pops, c->d_cell, c->d_T, c->P, d_T, s));
+    return NLTE_OK;
+}
+
+nlte_status nlte_run_ali_warm_dev(nlte_ctx *c, double *d_out, nlte_ali_report *rep, int *used_network, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if ((st = need_mlp(c))) return st;
+    if (c->mlp.dims.out[3] != c->n_lev) return fail(c, NLTE_E_STATE, "network outputs differ from the level count");
+    if (!d_out) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = mlp_ensure_points(c))) return st;
+    // the prediction runs on the caller's stream, which the ALI orders itself after
+    hipStream_t us = pick(c, stream);
+    if ((st = predict_impl(c, c->mlp.d_pred, us))) return st;
+    st = nlte_run_ali_dev(c, c->mlp.d_pred, d_out, rep, us);
+    if (used_network) *used_network = 1;
+    if (st == NLTE_W_NOT_CONVERGED) {
+        // the iteration did not settle from the predicted start: start again from LTE
+        if (used_network) *used_network = 0;
+        st = nlte_run_ali_dev(c, nullptr, d_out, rep, us);
+    }
+    return st;
+}
+
+nlte_status nlte_run_ali_warm(nlte_ctx *c, double *pops_out, nlte_ali_report *rep, int *used_network)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!pops_out) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    double *d_out = nullptr;
+    if ((st = dalloc(c, &d_out, (size_t)c->P * c->n_lev))) return st;
+    nlte_status rs = nlte_run_ali_warm_dev(c, d_out, rep, used_network, nullptr);
+    if (rs >= 0 && hipMemcpy(pops_out, d_out, sizeof(double) * c->P * c->n_lev, hipMemcpyDeviceToHost) != hipSuccess)
+        rs = fail(c, NLTE_E_HIP, "copy of the populations failed");
+    dfree(d_out);
+    return rs;
 }
 
 }  // extern "C"

@@ -100,6 +100,43 @@ struct KernelStat {
     int64_t launches = 0;
 };
 
+// Shapes of the warm-start network 8 -> 128 -> 128 -> 128 -> n_out and the offsets of
+// each layer's weights and biases in the flat parameter vector.
+struct MlpDims {
+    int in[4], out[4];
+    int64_t w_off[4], b_off[4];
+    int64_t n_params;
+};
+
+// Feature standardisation (x - mean) / std; identity until set.
+struct MlpNorm {
+    double mean[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double std[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+};
+
+// Parameters, optimiser state and work buffers of the warm-start network.
+struct MlpState {
+    bool ready = false;
+    MlpDims dims{};
+    MlpNorm norm{};
+    int64_t step = 0;                 // Adam steps since init / set_weights
+    float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr;  // [n_params]
+    void *d_frags = nullptr;          // bfloat16 A operands packed from d_theta
+    float *d_gpart = nullptr;         // [wg_cap][n_params]
+    float *d_lpart = nullptr;         // [wg_cap]
+    int64_t wg_cap = 0;
+    float *d_loss = nullptr;          // [loss_cap]
+    int64_t loss_cap = 0;
+    float *d_grad = nullptr;          // [n_params]
+    float *d_x = nullptr, *d_y = nullptr;  // host-call staging: [rows][8], [rows][n_out]
+    int64_t rows_cap = 0;
+    double *d_feat = nullptr;         // [P][8]
+    float *d_xp = nullptr, *d_yp = nullptr;  // [P][8], [P][n_out]
+    double *d_pred = nullptr;         // [P][n_lev]
+    int64_t pred_cap = 0;
+    unsigned long long *d_bad = nullptr;
+};
+
 }  // namespace nlte
 
 struct nlte_ctx {
@@ -176,6 +213,9 @@ struct nlte_ctx {
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     const double *graph_buf[2] = {nullptr, nullptr};
 
+    // warm-start network
+    nlte::MlpState mlp;
+
     // profiling
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     nlte::KernelStat st_line_coef, st_formal, st_stateq, st_lte, st_trace;
@@ -216,5 +256,26 @@ hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double
 int64_t stateq_blocks(int64_t P);
 hipError_t launch_conv_final(const ConvPartial *partials, int64_t n, ConvResult *out,
                              hipStream_t s);
+
+// warm start
+hipError_t launch_features(const CellRec *cell, const double *nh2, const double *T, const int32_t *nbr,
+                           int k, const int64_t *roff, const int32_t *rcells, const double *dir, int R,
+                           int64_t P, double *F, hipStream_t s);
+int mlp_frag_count();
+int mlp_train_blocks(int batch);
+hipError_t launch_mlp_pack(const float *theta, const MlpDims &d, void *frags, hipStream_t s);
+hipError_t launch_mlp_forward(const void *frags, const float *theta, const MlpDims &d, const float *X,
+                              int64_t n, float *Y, hipStream_t s);
+hipError_t launch_mlp_train(const void *frags, const float *theta, const MlpDims &d, const float *X, const float *T,
+                            int64_t n, int64_t start, int batch, float *gpart, float *lpart, hipStream_t s);
+hipError_t launch_mlp_reduce_adam(float *theta, float *m, float *v, const float *gpart, int n_wg, int64_t np,
+                                  int update, float lr, float b1, float b2, float eps, float c1, float c2,
+                                  const float *lpart, float inv_count, float *loss, float *grad_out,
+                                  hipStream_t s);
+hipError_t launch_mlp_standardise(const double *F, const MlpNorm &nm, int64_t P, float *X, hipStream_t s);
+hipError_t launch_mlp_targets(const SpeciesDev &sp, const double *pops, const CellRec *cell, const double *T,
+                              int64_t P, float *Tg, hipStream_t s);
+hipError_t launch_mlp_populations(const SpeciesDev &sp, const float *Y, const CellRec *cell, const double *T,
+                                  int64_t P, double *pops, unsigned long long *n_bad, hipStream_t s);
 
 }  // namespace nlte

@@ -1,0 +1,657 @@
+// Warm start of the accelerated Lambda iteration: per-point features of the local
+// conditions and a small multilayer perceptron that maps them to starting level
+// populations, predicted as departures from LTE.  This is not part of the paper's method, which only needs some initial
+// populations for its iteration (Sec. 2.2.1, 3.4); the iteration itself remains the
+// judge of the result.
+//
+// Network: 8 -> 128 -> 128 -> 128 -> n_out (n_out <= 16), erf GELU after each hidden
+// layer.  Parameters are one flat FP32 vector (master copy), matrices row-major
+// [out][in] in the order W1 b1 W2 b2 W3 b3 W4 b4.  Products run on the matrix cores
+// as v_mfma_f32_16x16x32_bf16: bfloat16 operands, FP32 accumulation.
+//
+// Operand layout used by every product (16x16 output tile, K = 32 per instruction):
+//   lane l = 16 g + i (g = 0..3, i = 0..15); the A operand holds row i of the tile, the
+//   B operand column i, and the four outputs of lane l are rows 4g .. 4g+3 of column i.
+//   The eight K slots of lane group g carry the reduction indices
+//       k(s, g, j) = 32 s + 16 (j / 4) + 4 g + (j % 4),   j = 0..7, K step s,
+//   on both operands.  With this choice an output tile pair (2s, 2s+1) of one layer,
+//   held as rows = features and columns = points, is exactly the B operand of K step s
+//   of the next layer, so activations pass from layer to layer in registers.
+#include "nlte_internal.h"
+
+namespace nlte {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kHid = 128;
+constexpr int kRowsWg = 64;   // rows per training workgroup (4 waves x 16)
+constexpr int kHS = 136;      // LDS row stride of bf16 activations (padding against bank conflicts)
+constexpr int kDS = 132;      // LDS row stride of FP32 output gradients
+
+// Round to the nearest bfloat16, ties to even (finite inputs).
+__device__ inline unsigned short bf16_bits(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+struct Frag {
+    unsigned short v[8];
+};
+
+__device__ inline bf16x8 as_bf16x8(const Frag &f) { return __builtin_bit_cast(bf16x8, f); }
+
+__device__ inline f32x4 mfma(const Frag &a, const Frag &b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
+}
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ inline float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Reduction index of K slot j of lane group g in K step s.
+__device__ inline int kslot(int s, int g, int j) { return 32 * s + 16 * (j >> 2) + 4 * g + (j & 3); }
+
+// B operand of K step s from output tiles 2s and 2s+1 (FP32 values -> bfloat16).
+__device__ inline Frag pack_pair(const f32x4 &lo, const f32x4 &hi)
+{
+    Frag f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        f.v[j] = bf16_bits(lo[j]);
+        f.v[4 + j] = bf16_bits(hi[j]);
+    }
+    return f;
+}
+
+__device__ inline Frag load_frag(const Frag *base, int idx, int lane) { return base[(int64_t)idx * 64 + lane]; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------- features
+
+// One wave per point.  F[p][0..7]: log10 n_H2, log10 T, log10 of the mean velocity
+// gradient to the neighbours (floored at 1e-30 s^-1), and log10 of the minimum, quartiles
+// and maximum over the rays of the H2 column along the cached walk (trapezoid in the
+// projected distance, floored at 1 cm^-2).  Quantiles interpolate linearly between order
+// statistics at position q (n_rays - 1).
+__global__ __launch_bounds__(64) void k_features(const CellRec *__restrict__ cell,
+                                                 const double *__restrict__ nh2,
+                                                 const double *__restrict__ T,
+                                                 const int32_t *__restrict__ nbr, int k,
+                                                 const int64_t *__restrict__ roff,
+                                                 const int32_t *__restrict__ rcells,
+                                                 const double *__restrict__ dir, int R, int64_t P,
+                                                 double *__restrict__ F)
+{
+    extern __shared__ double sh[];
+    double *col = sh;
+    double *srt = sh + R;
+    const int64_t p = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (p >= P) return;
+    const double ox = cell[p].px, oy = cell[p].py, oz = cell[p].pz;
+
+    for (int r = lane; r < R; r += 64) {
+        const double nx = dir[3 * r], ny = dir[3 * r + 1], nz = dir[3 * r + 2];
+        const int64_t b = roff[p * R + r], e = roff[p * R + r + 1];
+        double N = 0.0, n_prev = nh2[p], z_prev = 0.0;
+        for (int64_t i = b; i < e; ++i) {
+            const int32_t c = rcells[i];
+            const double dx = cell[c].px - ox, dy = cell[c].py - oy, dz = cell[c].pz - oz;
+            const double Z = (dx * nx + dy * ny) + dz * nz;
+            const double n_i = nh2[c];
+            N += 0.5 * (n_prev + n_i) * (Z - z_prev);
+            n_prev = n_i;
+            z_prev = Z;
+        }
+        col[r] = N;
+    }
+    __syncthreads();
+    // order statistics: rank by value, equal values by ray index
+    for (int r = lane; r < R; r += 64) {
+        const double v = col[r];
+        int rank = 0;
+        for (int s = 0; s < R; ++s) {
+            const double u = col[s];
+            rank += (u < v) || (u == v && s < r);
+        }
+        srt[rank] = v;
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    double *f = F + 8 * p;
+    f[0] = log10(nh2[p]);
+    f[1] = log10(T[p]);
+    double gsum = 0.0;
+    int gcount = 0;
+    for (int s = 0; s < k; ++s) {
+        const int32_t m = nbr[p * k + s];
+        if (m < 0) continue;
+        const double dvx = cell[m].vx - cell[p].vx, dvy = cell[m].vy - cell[p].vy, dvz = cell[m].vz - cell[p].vz;
+        const double dx = cell[m].px - ox, dy = cell[m].py - oy, dz = cell[m].pz - oz;
+        const double nv = sqrt((dvx * dvx + dvy * dvy) + dvz * dvz);
+        const double nx = sqrt((dx * dx + dy * dy) + dz * dz);
+        gsum += nv / nx;
+        ++gcount;
+    }
+    const double g = gcount > 0 ? gsum / gcount : 0.0;
+    f[2] = log10(g > 1e-30 ? g : 1e-30);
+    const double qs[5] = {0.0, 0.25, 0.5, 0.75, 1.0};
+    for (int j = 0; j < 5; ++j) {
+        const double h = qs[j] * (R - 1);
+        const int i = (int)floor(h);
+        double v = srt[i];
+        if (i + 1 < R) v = srt[i] + (h - i) * (srt[i + 1] - srt[i]);
+        f[3 + j] = log10(v > 1.0 ? v : 1.0);
+    }
+}
+
+hipError_t launch_features(const CellRec *cell, const double *nh2, const double *T, const int32_t *nbr,
+                           int k, const int64_t *roff, const int32_t *rcells, const double *dir, int R,
+                           int64_t P, double *F, hipStream_t s)
+{
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)P), dim3(64), sizeof(double) * 2 * R, s, cell, nh2, T, nbr, k, roff, rcells, dir, R, P, F);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------- MLP
+
+// Fragment counts: forward A operands (W, rows = outputs) per layer, then backward A
+// operands (W transposed, rows = inputs) of layers 2..4.
+//   forward:  L1 8 x 1, L2 8 x 4, L3 8 x 4, L4 1 x 4   (output tiles x K steps)
+//   backward: L2 8 x 4, L3 8 x 4, L4 8 x 1
+constexpr int kFwdBase[4] = {0, 8, 40, 72};
+constexpr int kFwdFrags = 76;
+constexpr int kBwdBase[4] = {0, 0, 32, 64};  // index by layer (1..3 used)
+constexpr int kBwdFrags = 72;
+
+int mlp_frag_count() { return kFwdFrags + kBwdFrags; }
+
+// Pack the bfloat16 A operands from the FP32 master parameters.  One thread per
+// (fragment, lane).
+__global__ void k_mlp_pack(const float *__restrict__ theta, MlpDims d, Frag *__restrict__ frags)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)(kFwdFrags + kBwdFrags) * 64) return;
+    const int fi = (int)(t / 64), lane = (int)(t % 64);
+    const int i = lane & 15, g = lane >> 4;
+    Frag out;
+    if (fi < kFwdFrags) {
+        const int L = fi < 8 ? 0 : fi < 40 ? 1 : fi < 72 ? 2 : 3;
+        const int KT = (L == 0) ? 1 : 4;
+        const int local = fi - kFwdBase[L];
+        const int mt = local / KT, s = local % KT;
+        const int row = 16 * mt + i;
+        for (int j = 0; j < 8; ++j) {
+            const int kk = kslot(s, g, j);
+            float w = 0.0f;
+            if (row < d.out[L] && kk < d.in[L]) w = theta[d.w_off[L] + (int64_t)row * d.in[L] + kk];
+            out.v[j] = bf16_bits(w);
+        }
+    } else {
+        const int bi = fi - kFwdFrags;
+        const int L = bi < 32 ? 1 : bi < 64 ? 2 : 3;
+        const int KT = (L == 3) ? 1 : 4;
+        const int local = bi - kBwdBase[L];
+        const int mt = local / KT, s = local % KT;
+        const int col = 16 * mt + i;  // input feature of layer L
+        for (int j = 0; j < 8; ++j) {
+            const int o = kslot(s, g, j);
+            float w = 0.0f;
+            if (o < d.out[L] && col < d.in[L]) w = theta[d.w_off[L] + (int64_t)o * d.in[L] + col];
+            out.v[j] = bf16_bits(w);
+        }
+    }
+    frags[t] = out;
+}
+
+hipError_t launch_mlp_pack(const float *theta, const MlpDims &d, void *frags, hipStream_t s)
+{
+    const int64_t n = (int64_t)(kFwdFrags + kBwdFrags) * 64;
+    hipLaunchKernelGGL(k_mlp_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, d, (Frag *)frags);
+    return hipGetLastError();
+}
+
+namespace {
+
+// B operand of the first layer: standardised inputs of row `row` (zero beyond 8 inputs
+// and for rows past the end).
+__device__ inline Frag input_frag(const float *__restrict__ X, int64_t row, bool valid, int g)
+{
+    Frag f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f.v[j] = 0;
+    if (valid && g < 2) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f.v[j] = bf16_bits(X[row * 8 + 4 * g + j]);
+    }
+    return f;
+}
+
+// Hidden layer L (1 or 2, 0-based index into the dims) from B operands hb[4] to new
+// pre-activations acc[8] (bias added).
+__device__ inline void hidden_layer(const Frag *__restrict__ fw, int L, const Frag (&hb)[4], const float *__restrict__ bias,
+                                    int lane, f32x4 (&acc)[8])
+{
+    const int g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) c = mfma(load_frag(fw, kFwdBase[L] + mt * 4 + s, lane), hb[s], c);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] += bias[16 * mt + 4 * g + j];
+        acc[mt] = c;
+    }
+}
+
+}  // namespace
+
+// Inference: each wave evaluates NT tiles of 16 rows.  X [n][8] standardised inputs,
+// Y [n][n_out] outputs (log10 fractional populations).
+template <int NT>
+__global__ __launch_bounds__(256) void k_mlp_forward(const Frag *__restrict__ fw, const float *__restrict__ theta,
+                                                     MlpDims d, const float *__restrict__ X, int64_t n,
+                                                     float *__restrict__ Y)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = blockIdx.x * (int64_t)(blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t row0 = wave * 16 * NT;
+    if (row0 >= n) return;
+    const int i = lane & 15, g = lane >> 4;
+    Frag hb[NT][4];
+    f32x4 acc[NT][8];
+    // layer 1
+    {
+        Frag xb[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t row = row0 + 16 * t + i;
+            xb[t] = input_frag(X, row, row < n, g);
+        }
+        const float *b1 = theta + d.b_off[0];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            const Frag a = load_frag(fw, kFwdBase[0] + mt, lane);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                f32x4 c = {0.f, 0.f, 0.f, 0.f};
+                c = mfma(a, xb[t], c);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) c[j] = gelu(c[j] + b1[16 * mt + 4 * g + j]);
+                acc[t][mt] = c;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) hb[t][s] = pack_pair(acc[t][2 * s], acc[t][2 * s + 1]);
+    }
+    // layers 2 and 3
+#pragma unroll
+    for (int L = 1; L <= 2; ++L) {
+        const float *bL = theta + d.b_off[L];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            f32x4 c[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const Frag a = load_frag(fw, kFwdBase[L] + mt * 4 + s, lane);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) c[t] = mfma(a, hb[t][s], c[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[t][mt][j] = gelu(c[t][j] + bL[16 * mt + 4 * g + j]);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) hb[t][s] = pack_pair(acc[t][2 * s], acc[t][2 * s + 1]);
+    }
+    // output layer
+    const float *b4 = theta + d.b_off[3];
+    f32x4 c[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const Frag a = load_frag(fw, kFwdBase[3] + s, lane);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[t] = mfma(a, hb[t][s], c[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int64_t row = row0 + 16 * t + i;
+        if (row >= n) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = 4 * g + j;
+            if (o < d.out[3]) Y[row * d.out[3] + o] = c[t][j] + b4[o];
+        }
+    }
+}
+
+hipError_t launch_mlp_forward(const void *frags, const float *theta, const MlpDims &d, const float *X,
+                              int64_t n, float *Y, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    constexpr int NT = 2;
+    const int64_t waves = (n + 16 * NT - 1) / (16 * NT);
+    const int64_t blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL(k_mlp_forward<NT>, dim3((unsigned)blocks), dim3(256), 0, s, (const Frag *)frags, theta, d,
+                       X, n, Y);
+    return hipGetLastError();
+}
+
+// One training pass over a batch: forward, loss, backward, and this workgroup's share
+// of the parameter gradient.  Workgroup w takes batch rows 64 w .. 64 w + 63; batch row
+// b reads data row (start + b) mod n.  gpart [n_wg][n_params]; lpart [n_wg] holds the
+// workgroup's sum of squared errors.  gscale = 2 / (batch n_out).
+__global__ __launch_bounds__(256) void k_mlp_train(const Frag *__restrict__ frags, const float *__restrict__ theta,
+                                                   MlpDims d, const float *__restrict__ X,
+                                                   const float *__restrict__ Tg, int64_t n, int64_t start,
+                                                   int batch, float gscale, float *__restrict__ gpart,
+                                                   float *__restrict__ lpart)
+{
+    __shared__ unsigned short H0[kRowsWg][16];
+    __shared__ unsigned short Hs[3][kRowsWg][kHS];
+    __shared__ float DZ[kRowsWg][kDS];
+    __shared__ float red[4];
+
+    const Frag *fw = frags;
+    const Frag *bw = frags + (int64_t)kFwdFrags * 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    const int rl = 16 * w + i;  // this lane's row within the workgroup (as an output column)
+    const int64_t b = (int64_t)blockIdx.x * kRowsWg + rl;
+    const bool valid = b < batch;
+    const int64_t row = valid ? (start + b) % n : 0;
+    float *gp = gpart + (int64_t)blockIdx.x * d.n_params;
+
+    // ---- forward, keeping pre-activations in registers and activations in LDS
+    f32x4 z[3][8];
+    Frag hb[4];
+    {
+        const Frag xb = input_frag(X, row, valid, g);
+        if (g < 2) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) H0[rl][4 * g + j] = xb.v[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) H0[rl][8 + 4 * (g - 2) + j] = 0;
+        }
+        const float *b1 = theta + d.b_off[0];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            c = mfma(load_frag(fw, kFwdBase[0] + mt, lane), xb, c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[j] += b1[16 * mt + 4 * g + j];
+            z[0][mt] = c;
+        }
+    }
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        f32x4 h[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const unsigned short hv = bf16_bits(gelu(z[L][mt][j]));
+                Hs[L][rl][16 * mt + 4 * g + j] = hv;
+                h[mt][j] = bf16_value(hv);
+            }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) hb[s] = pack_pair(h[2 * s], h[2 * s + 1]);
+        if (L < 2) hidden_layer(fw, L + 1, hb, theta + d.b_off[L + 1], lane, z[L + 1]);
+    }
+    // output layer and loss
+    f32x4 dz[8];
+    float sq = 0.0f;
+    {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) c = mfma(load_frag(fw, kFwdBase[3] + s, lane), hb[s], c);
+        const float *b4 = theta + d.b_off[3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = 4 * g + j;
+            float e = 0.0f;
+            if (valid && o < d.out[3]) e = (c[j] + b4[o]) - Tg[row * d.out[3] + o];
+            sq += e * e;
+            dz[0][j] = gscale * e;
+        }
+#pragma unroll
+        for (int mt = 1; mt < 8; ++mt) dz[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // loss partial: wave sum in a fixed tree, then the four waves in order
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
+    if (lane == 0) red[w] = sq;
+
+    // ---- backward, layer 4 down to 1
+#pragma unroll
+    for (int L = 3; L >= 0; --L) {
+        const int MT = (d.out[L] + 15) / 16;
+        // output gradient of this layer into LDS [row][out]
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+            if (mt < MT)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) DZ[rl][16 * mt + 4 * g + j] = dz[mt][j];
+        // gradient w.r.t. this layer's input (registers), through the previous GELU
+        f32x4 dzn[8];
+        if (L > 0) {
+            const int KT = (L == 3) ? 1 : 4;
+            Frag db[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (s < KT) db[s] = pack_pair(dz[2 * s], dz[2 * s + 1]);
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) {
+                f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    if (s < KT) c = mfma(load_frag(bw, kBwdBase[L] + mt * KT + s, lane), db[s], c);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dzn[mt][j] = c[j] * gelu_grad(z[L - 1][mt][j]);
+            }
+        }
+        __syncthreads();
+        // weight gradient over the workgroup's 64 rows: tiles (output mt, input nt)
+        {
+            const int NTi = (d.in[L] + 15) / 16;
+            const int tiles = MT * NTi;
+            for (int tIdx = w; tIdx < tiles; tIdx += 4) {
+                const int mt = tIdx / NTi, nt = tIdx % NTi;
+                f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    Frag a, bb;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int r = kslot(s, g, j);
+                        a.v[j] = bf16_bits(DZ[r][16 * mt + i]);
+                        bb.v[j] = (L == 0) ? H0[r][i] : Hs[L - 1][r][16 * nt + i];
+                    }
+                    c = mfma(a, bb, c);
+                }
+                const int kcol = 16 * nt + i;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = 16 * mt + 4 * g + j;
+                    if (o < d.out[L] && kcol < d.in[L]) gp[d.w_off[L] + (int64_t)o * d.in[L] + kcol] = c[j];
+                }
+            }
+            // bias gradient: unrounded output gradients summed over rows in order
+            for (int o = threadIdx.x; o < d.out[L]; o += blockDim.x) {
+                float sacc = 0.0f;
+                for (int r = 0; r < kRowsWg; ++r) sacc += DZ[r][o];
+                gp[d.b_off[L] + o] = sacc;
+            }
+        }
+        __syncthreads();
+        if (L > 0)
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) dz[mt] = dzn[mt];
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+int mlp_train_blocks(int batch) { return (batch + kRowsWg - 1) / kRowsWg; }
+
+hipError_t launch_mlp_train(const void *frags, const float *theta, const MlpDims &d, const float *X, const float *T,
+                            int64_t n, int64_t start, int batch, float *gpart, float *lpart, hipStream_t s)
+{
+    const int blocks = mlp_train_blocks(batch);
+    const float gscale = (float)(2.0 / ((double)batch * d.out[3]));
+    hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(256), 0, s, (const Frag *)frags, theta, d, X, T, n, start,
+                       batch, gscale, gpart, lpart);
+    return hipGetLastError();
+}
+
+// Sum the workgroup partials in a fixed order; optionally write the gradient and apply
+// one Adam step (c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t)).  The first thread also
+// writes the batch loss (mean squared error) to *loss.
+__global__ void k_mlp_reduce_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
+                                  const float *__restrict__ gpart, int n_wg, int64_t np, int update, float lr,
+                                  float b1, float b2, float eps, float c1, float c2,
+                                  const float *__restrict__ lpart, float inv_count, float *__restrict__ loss,
+                                  float *__restrict__ grad_out)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p == 0 && loss) {
+        float s = 0.0f;
+        for (int w = 0; w < n_wg; ++w) s += lpart[w];
+        *loss = s * inv_count;
+    }
+    if (p >= np) return;
+    float gsum = 0.0f;
+    for (int w = 0; w < n_wg; ++w) gsum += gpart[(int64_t)w * np + p];
+    if (grad_out) grad_out[p] = gsum;
+    if (!update) return;
+    const float mm = b1 * m[p] + (1.0f - b1) * gsum;
+    const float vv = b2 * v[p] + (1.0f - b2) * gsum * gsum;
+    m[p] = mm;
+    v[p] = vv;
+    theta[p] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+}
+
+hipError_t launch_mlp_reduce_adam(float *theta, float *m, float *v, const float *gpart, int n_wg, int64_t np,
+                                  int update, float lr, float b1, float b2, float eps, float c1, float c2,
+                                  const float *lpart, float inv_count, float *loss, float *grad_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, theta, m, v, gpart,
+                       n_wg, np, update, lr, b1, b2, eps, c1, c2, lpart, inv_count, loss, grad_out);
+    return hipGetLastError();
+}
+
+// Standardised FP32 inputs from FP64 features.
+__global__ void k_mlp_standardise(const double *__restrict__ F, MlpNorm nm, int64_t P, float *__restrict__ X)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= P * 8) return;
+    const int f = (int)(t % 8);
+    X[t] = (float)((F[t] - nm.mean[f]) / nm.std[f]);
+}
+
+hipError_t launch_mlp_standardise(const double *F, const MlpNorm &nm, int64_t P, float *X, hipStream_t s)
+{
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_standardise, dim3((unsigned)((P * 8 + 255) / 256)), dim3(256), 0, s, F, nm, P, X);
+    return hipGetLastError();
+}
+
+// Boltzmann fraction of level i at temperature T, floored at 1e-300.
+__device__ inline double lte_fraction(const SpeciesDev &sp, double T, int i)
+{
+    const double kT = kKB * T;
+    double Z = 0.0;
+    for (int j = 0; j < sp.n_lev; ++j) Z += sp.g[j] * exp(-(sp.E[j] - sp.E[0]) / kT);
+    const double f = sp.g[i] * exp(-(sp.E[i] - sp.E[0]) / kT) / Z;
+    return f > 1e-300 ? f : 1e-300;
+}
+
+// Training targets: log10 of the departure from LTE, log10 (f_i / f_i^LTE), with the
+// fractional population f_i = n_i / (abundance n_H2) floored at 1e-300.
+__global__ void k_mlp_targets(SpeciesDev sp, const double *__restrict__ pops, const CellRec *__restrict__ cell,
+                              const double *__restrict__ T, int64_t P, float *__restrict__ Tg)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int n_lev = sp.n_lev;
+    if (t >= P * n_lev) return;
+    const int64_t p = t / n_lev;
+    const int i = (int)(t % n_lev);
+    double f = pops[t] / cell[p].ntot;
+    f = f > 1e-300 ? f : 1e-300;
+    Tg[t] = (float)(log10(f) - log10(lte_fraction(sp, T[p], i)));
+}
+
+hipError_t launch_mlp_targets(const SpeciesDev &sp, const double *pops, const CellRec *cell, const double *T,
+                              int64_t P, float *Tg, hipStream_t s)
+{
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_targets, dim3((unsigned)((P * sp.n_lev + 255) / 256)), dim3(256), 0, s, sp, pops, cell,
+                       T, P, Tg);
+    return hipGetLastError();
+}
+
+// Populations from predicted departures y: n_i = ntot w_i / sum_j w_j with
+// w_i = f_i^LTE 10^y_i (evaluated relative to the largest log10 w).  A point with a
+// non-finite prediction keeps what pops already holds and is counted.
+__global__ void k_mlp_populations(SpeciesDev sp, const float *__restrict__ Y, const CellRec *__restrict__ cell,
+                                  const double *__restrict__ T, int64_t P, double *__restrict__ pops,
+                                  unsigned long long *__restrict__ n_bad)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int n_lev = sp.n_lev;
+    double a[kMaxLev];
+    double amax = -INFINITY;
+    bool ok = true;
+    for (int i = 0; i < n_lev; ++i) {
+        const double y = (double)Y[p * n_lev + i];
+        ok = ok && isfinite(y);
+        a[i] = log10(lte_fraction(sp, T[p], i)) + y;
+        amax = fmax(amax, a[i]);
+    }
+    if (!ok) {
+        atomicAdd(n_bad, 1ull);
+        return;
+    }
+    double sum = 0.0;
+    for (int i = 0; i < n_lev; ++i) {
+        a[i] = exp10(a[i] - amax);
+        sum += a[i];
+    }
+    const double nt = cell[p].ntot;
+    for (int i = 0; i < n_lev; ++i) pops[p * n_lev + i] = nt * a[i] / sum;
+}
+
+hipError_t launch_mlp_populations(const SpeciesDev &sp, const float *Y, const CellRec *cell, const double *T,
+                                  int64_t P, double *pops, unsigned long long *n_bad, hipStream_t s)
+{
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_populations, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, sp, Y, cell, T, P, pops,
+                       n_bad);
+    return hipGetLastError();
+}
+
+}  // namespace nlte

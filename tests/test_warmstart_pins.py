@@ -242,10 +242,21 @@ def test_training_fits_a_smooth_map():
     assert losses[-10:].mean() < 0.1 * losses[:5].mean()
 
 
-def test_populations_are_normalised_ratios():
-    y = np.array([[-0.5, -1.0, -3.0], [2.0, 2.0, 2.0]])
-    nt = np.array([1e-2, 5.0])
-    pops = mlp.populations(y, nt)
-    assert np.allclose(pops.sum(1), nt, rtol=1e-15)
-    assert abs(pops[0, 0] / pops[0, 1] - 10 ** 0.5) < 1e-14
-    assert np.allclose(pops[1], 5.0 / 3)
+def test_departure_targets_and_populations_invert_each_other():
+    rng = np.random.default_rng(31)
+    lte = rng.uniform(0.1, 1.0, (20, 5))
+    lte[:, 4] = 1e-12                                # a level far up the ladder
+    ntot = rng.uniform(1e-3, 1e3, 20)[:, None]
+    lte = ntot * lte / lte.sum(1, keepdims=True)
+    pops = lte * np.exp(rng.normal(0.0, 1.0, lte.shape))
+    pops = ntot * pops / pops.sum(1, keepdims=True)
+    y = mlp.targets(pops, lte)
+    assert np.allclose(mlp.populations(y, lte), pops, rtol=1e-12, atol=0)
+    # zero departure is the LTE start; equal departures cancel in the normalisation
+    assert np.allclose(mlp.populations(np.zeros_like(y), lte), lte, rtol=1e-13, atol=0)
+    assert np.allclose(mlp.populations(np.full_like(y, 3.7), lte), lte, rtol=1e-13, atol=0)
+    assert np.allclose(mlp.targets(lte, lte), 0.0, atol=1e-14)
+    # a departure of +1 on one level of two equal ones makes it ten times the other
+    two = np.full((1, 2), 0.5)
+    p2 = mlp.populations(np.array([[1.0, 0.0]]), two)
+    assert abs(p2[0, 0] / p2[0, 1] - 10.0) < 1e-13 and abs(p2.sum() - 1.0) < 1e-15
