@@ -91,6 +91,105 @@ def cpu_baseline(w, target_s=15.0):
                       f"populations, formal solve only, {dt:.1f} s wall"}
 
 
+def _rel_err(p, ref, ntot):
+    """Largest paper-metric difference 2|a-b|/(|a|+|b|) over levels with n_i/n_tot > 1e-10."""
+    import numpy as np
+    mask = ref / ntot[:, None] > 1e-10
+    a, b = p[mask], ref[mask]
+    return float(np.max(2 * np.abs(a - b) / (np.abs(a) + np.abs(b))))
+
+
+def train_warm_start(s, w, make, args, dev):
+    """Network for the warm start, trained on converged populations of other seeds of the
+    same workload family (never the measured model)."""
+    import numpy as np
+
+    from paper_1912_08445_amd import warmstart
+    from paper_1912_08445_amd.binding import Solver
+    t0 = time.perf_counter()
+    seeds = [101 + i for i in range(args.train_models)]
+
+    def model(sd):
+        wt = make(seed=sd) if args.points is None else make(n_points=args.points, seed=sd)
+        st = Solver(0)
+        st.setup(wt, precision="fp64")
+        return st
+
+    # one training model resident at a time: features first (for the standardisation),
+    # then the converged rows
+    feats = []
+    for sd in seeds:
+        st = model(sd)
+        feats.append(st.features())
+        st.close()
+    mean, std = warmstart.feature_norm(feats)
+    rows = []
+    for sd in seeds:
+        st = model(sd)
+        X, T, _ = warmstart.converged_rows(st, mean, std, tol=1e-6, sample=args.train_sample)
+        rows.append((X, T))
+        st.close()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    curve = warmstart.train(s, rows, mean, std, [(6000, 2e-3), (4000, 2e-4)], batch=4096, seed=1)
+    t_train = time.perf_counter() - t0
+    n_rows = sum(int(r[0].shape[0]) for r in rows)
+    log(f"warm start: {len(seeds)} training models, {n_rows} rows, data {t_data:.1f} s, "
+        f"training {t_train:.1f} s, loss {curve[:5].mean():.3e} -> {curve[-50:].mean():.3e}")
+    return {"train_models": len(seeds), "train_seeds": seeds, "rows": n_rows, "data_s": t_data,
+            "train_s": t_train, "steps": int(curve.shape[0]), "batch": 4096,
+            "loss_start": float(curve[:5].mean()), "loss_end": float(curve[-50:].mean())}
+
+
+def ali_forms(s, w, make, args, dev):
+    """ALI wall time and iterations to a maximum relative change of 1e-4 from LTE and from
+    the learned start, in FP64 and in the FP32 form, each against FP64 populations
+    converged to 1e-9."""
+    import numpy as np
+    import torch
+    ntot = w.model.abundance * w.model.n_h2
+    out = torch.empty((w.n_points, w.species.n_lev), dtype=torch.float64, device=dev)
+    s.set_params(precision="fp64", tol=1e-9, max_iter=500)
+    rep = s.run_ali_dev(None, out)
+    torch.cuda.synchronize()
+    ref = out.cpu().numpy()
+    res = {"tol": 1e-4, "reference": {"precision": "fp64", "tol": 1e-9, "iterations": rep["iterations"],
+                                      "converged": rep["converged"]},
+           "models": w.n_models, "graph": True}
+    warm = None
+    if w.n_models == 1 and args.train_models > 0:
+        res["warm_start"] = train_warm_start(s, w, make, args, dev)
+        warm = True
+    forms = [("fp64", "lte"), ("fp32", "lte")] + ([("fp64", "warm"), ("fp32", "warm")] if warm else [])
+    for prec, start in forms:
+        s.set_params(precision=prec, tol=1e-4, max_iter=200)
+        best = None
+        for _ in range(3):   # best of three: the first run of a form captures its graphs
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if start == "lte":
+                r = s.run_ali_dev(None, out)
+            else:
+                r = s.run_ali_warm_dev(out)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if best is None or wall < best[0]:
+                best = (wall, r)
+        wall, r = best
+        err = _rel_err(out.cpu().numpy(), ref, ntot)
+        key = f"{prec}_{start}"
+        res[key] = {"iterations": r["iterations"], "converged": r["converged"], "wall_s": wall,
+                    "max_rel_diff_vs_fp64_reference": err,
+                    "models_converged": r["n_models_converged"],
+                    "max_change": [float(c) for c in r["max_change"]]}
+        if start == "warm":
+            res[key]["used_network"] = r["used_network"]
+        log(f"ALI {key}: {r['iterations']} iterations, {wall * 1e3:.1f} ms, max rel diff vs FP64 "
+            f"reference {err:.2e}, changes {['%.2e' % c for c in r['max_change']]}")
+    s.set_params(precision=args.precision)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +202,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ali", action="store_true")
+    ap.add_argument("--train-models", type=int, default=8,
+                    help="other seeds of the workload whose converged populations train the warm start "
+                         "(0: no warm start)")
+    ap.add_argument("--train-sample", type=int, default=20000,
+                    help="rows taken from each training model")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (4 launches), "
                          "the calibration kernel for HBM byte counters")
@@ -212,18 +316,7 @@ def main():
 
     ali = None
     if not args.no_ali:
-        s.set_params(tol=1e-4, max_iter=200)
-        out = torch.empty_like(pops)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rep = s.run_ali_dev(None, out)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ali = {"iterations": rep["iterations"], "converged": rep["converged"], "wall_s": wall,
-               "final_max_change": rep["max_change"][-1] if rep["max_change"] else None,
-               "tol": 1e-4, "start": "LTE", "models": w.n_models,
-               "models_converged": rep["n_models_converged"], "graph": True}
-        log(f"ALI to 1e-4: {rep['iterations']} iterations, {wall:.2f} s")
+        ali = ali_forms(s, w, make, args, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

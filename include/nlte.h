@@ -61,7 +61,8 @@ typedef struct {
     int profile;      /* 1: time every kernel with HIP events (nlte_kernel_stats); the ALI
                          then launches kernels one by one instead of replaying a graph */
     int use_graph;    /* 1: capture one ALI iteration as a hipGraph and replay it.  1 */
-    int lines_per_lane; /* formal-solve lines per lane: 0 = by rule, 1 or 2.  0 */
+    int lines_per_lane; /* formal-solve lines per lane: 0 = by rule, 1 or 2 (or 3 in the FP32
+                           form); lines of a lane share its profile evaluations.  0 */
     int high_occupancy; /* 1: formal-solve kernels built for 3-4 waves per SIMD.  1 */
     int persistent;   /* 1: persistent formal solve taking points from a work queue in
                          decreasing order of their cached step counts.  0 */
@@ -227,9 +228,10 @@ nlte_status nlte_get_model_status(nlte_ctx *ctx, int32_t *iterations, uint8_t *c
                                   double *last_change);
 
 /*
- * Time the formal-solve launch variants (lines per lane 1/2, occupancy hint on/off, grid or
- * persistent work queue) on the current model with LTE populations, `trials` launches
- * each (after one warm-up), and keep the fastest (median) in the context's parameters.
+ * Time the formal-solve launch variants (lines per lane 1/2, or up to 3 in the FP32 form,
+ * occupancy hint on/off, grid or persistent work queue) on the current model with LTE
+ * populations, `trials` launches each (after one warm-up), and keep the fastest (median)
+ * in the context's parameters.
  * cache_path (nullable): text file of earlier choices keyed by device, model size, ray,
  * line and frequency counts, step count and precision; a hit skips the timing, a miss
  * appends the new choice.  choice (nullable, cap bytes) receives a description.

@@ -145,11 +145,25 @@ SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
     a.n_q = c->n_q;
     a.n_lines = c->n_lines;
     // A wave takes one or two groups of n_q lanes (one frequency each) and LPL lines per
-    // group (1 or 2; more lines per lane exceed the register budget of the sweep).
+    // group: 1 or 2, or 3 in the FP32 form (more exceed the register budget of the sweep).
+    // By rule LPL minimises an estimate of the work per point: 12 units per line slot
+    // (elimination) plus 18 per lane group (one shared profile evaluation), over the waves
+    // the point needs.
     const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
     a.fchunks = (c->n_q <= kWave) ? 1 : (c->n_q + kWave - 1) / kWave;
-    int lpl = std::min(2, (c->n_lines + ngrp - 1) / ngrp);
-    if (c->cfg.lpl == 1 || c->cfg.lpl == 2) lpl = std::min(lpl, c->cfg.lpl);
+    const int lpl_max = c->params.precision == NLTE_PREC_FP32_BULK ? 3 : 2;
+    int lpl = 1, best_cost = INT32_MAX;
+    for (int l = 1; l <= lpl_max; ++l) {
+        const int waves = (c->n_lines + ngrp * l - 1) / (ngrp * l);
+        const int cost = waves * ngrp * (12 * l + 18);
+        if (cost < best_cost) {
+            best_cost = cost;
+            lpl = l;
+        }
+        if (ngrp * l >= c->n_lines) break;   // one wave already holds every line
+    }
+    // an explicit choice, capped at the lines one lane group can need
+    if (c->cfg.lpl >= 1 && c->cfg.lpl <= lpl_max) lpl = std::min(c->cfg.lpl, (c->n_lines + ngrp - 1) / ngrp);
     a.lines_per_wave = ngrp * lpl;
     a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
     a.n_blocks = c->P * a.groups;
@@ -798,8 +812,8 @@ nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
     if (!c || !p) return NLTE_E_INVALID_ARG;
     if (!(p->t_cmb > 0.0) || !(p->f_sub > 0.0) || !(p->tol >= 0.0) || p->max_iter < 1 ||
         p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
-        p->lines_per_lane < 0 || p->lines_per_lane > 2)
-        return fail(c, NLTE_E_INVALID_ARG, "parameter out of range");
+        p->lines_per_lane < 0 || p->lines_per_lane > (p->precision == NLTE_PREC_FP32_BULK ? 3 : 2))
+        return fail(c, NLTE_E_INVALID_ARG, "parameter out of range (lines_per_lane: 0..2, 0..3 in the FP32 form)");
     c->params = *p;
     c->cfg.lpl = p->lines_per_lane;
     c->cfg.high_occupancy = p->high_occupancy ? 1 : 0;
@@ -1137,13 +1151,15 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
         const int saved_profile = c->params.profile;
         c->params.profile = 0;
         const SolveConfig saved = c->cfg;
-        for (int lpl = 1; lpl <= 2; ++lpl)
+        const int lpl_max = c->params.precision == NLTE_PREC_FP32_BULK ? 3 : 2;
+        const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
+        for (int lpl = 1; lpl <= lpl_max; ++lpl)
             for (int hi = 0; hi <= 1; ++hi)
                 for (int pe = 0; pe <= 1; ++pe) {
                     c->cfg.lpl = lpl;
                     c->cfg.high_occupancy = hi;
                     c->cfg.persistent = pe;
-                    if (lpl == 2 && solve_args(c, nullptr, nullptr, nullptr).lines_per_wave / 2 < 1) continue;
+                    if (lpl > (c->n_lines + ngrp - 1) / ngrp) continue;   // same as a smaller lpl
                     std::vector<float> t;
                     for (int k = 0; k <= trials; ++k) {
                         HIPCHK(c, hipEventRecord(c->ev0, s));

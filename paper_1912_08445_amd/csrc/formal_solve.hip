@@ -591,6 +591,11 @@ hipError_t launch_fs(const SolveArgs &a, const SolveConfig &cfg, hipStream_t s)
     if (lpl == 2)
         return cfg.high_occupancy ? launch_variant<F32, 2, true>(a, cfg.persistent, cfg.n_wg, s)
                                   : launch_variant<F32, 2, false>(a, cfg.persistent, cfg.n_wg, s);
+    // three lines per lane only in the FP32 form: its state fits 3 waves per SIMD without
+    // spills, where the FP64 one would not
+    if (F32 && lpl == 3)
+        return cfg.high_occupancy ? launch_variant<true, 3, true>(a, cfg.persistent, cfg.n_wg, s)
+                                  : launch_variant<true, 3, false>(a, cfg.persistent, cfg.n_wg, s);
     return hipErrorInvalidValue;
 }
 
