@@ -66,9 +66,15 @@ typedef struct {
     int high_occupancy; /* 1: formal-solve kernels built for 3-4 waves per SIMD.  1 */
     int persistent;   /* 1: persistent formal solve taking points from a work queue in
                          decreasing order of their cached step counts.  0 */
+    int ng_every;     /* Ng acceleration (Sec. 3.4): after every ng_every regular ALI
+                         iterations each model still iterating takes the combination of its
+                         last ng_every - 1 iterates, summing to one, that minimises the same
+                         combination of successive changes in the fractional populations
+                         (uniform weights); points where it is not positive keep the newest
+                         iterate.  0 = off, else 3..8 (the paper's default is 4).  0 */
 } nlte_params;
 
-/* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0. */
+/* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0, ng_every 0. */
 void nlte_default_params(nlte_params *p);
 
 typedef struct {
@@ -82,6 +88,8 @@ typedef struct {
     int64_t n_kept;          /* points that kept their previous populations (last iteration) */
     int64_t n_maser;         /* (point, line) pairs with non-positive opacity (last iteration) */
     double ms_total;         /* wall time of the iteration loop [ms] */
+    int n_ng_steps;          /* Ng extrapolations applied (ng_every > 0) */
+    int64_t n_ng_rejected;   /* points that kept the newest iterate in those steps */
 } nlte_ali_report;
 
 /* ---------------------------------------------------------------- context */

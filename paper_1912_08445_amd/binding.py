@@ -48,7 +48,7 @@ class Params(C.Structure):
     _fields_ = [("t_cmb", C.c_double), ("f_sub", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("use_alo", C.c_int), ("precision", C.c_int),
                 ("profile", C.c_int), ("use_graph", C.c_int), ("lines_per_lane", C.c_int),
-                ("high_occupancy", C.c_int), ("persistent", C.c_int)]
+                ("high_occupancy", C.c_int), ("persistent", C.c_int), ("ng_every", C.c_int)]
 
 
 class AliReport(C.Structure):
@@ -56,7 +56,7 @@ class AliReport(C.Structure):
                 ("max_change", C.c_double * 1024), ("mean_change", C.c_double * 1024),
                 ("n_models_converged", C.c_int64),
                 ("n_fallback", C.c_int64), ("n_kept", C.c_int64), ("n_maser", C.c_int64),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("n_ng_steps", C.c_int), ("n_ng_rejected", C.c_int64)]
 
 
 class TrainParams(C.Structure):
@@ -465,4 +465,4 @@ def report_dict(rep, rc):
                 max_change=list(rep.max_change[:min(it, 1024)]),
                 mean_change=list(rep.mean_change[:min(it, 1024)]),
                 n_fallback=rep.n_fallback, n_kept=rep.n_kept, n_maser=rep.n_maser,
-                ms_total=rep.ms_total)
+                ms_total=rep.ms_total, n_ng_steps=rep.n_ng_steps, n_ng_rejected=rep.n_ng_rejected)

@@ -426,6 +426,28 @@ uint64_t splitmix64(uint64_t &state)
     return z ^ (z >> 31);
 }
 
+
+// Ng work arrays for the current model(s) and ng_every.
+nlte_status ensure_ng(nlte_ctx *c)
+{
+    const int M = c->params.ng_every;
+    const int64_t need = (int64_t)M * c->P * c->n_lev;
+    nlte_status st;
+    if (need > c->ng_hist_elems) {
+        if ((st = dalloc(c, &c->d_ng_hist, (size_t)need))) return st;
+        c->ng_hist_elems = need;
+    }
+    if (c->n_models > c->ng_models_cap || !c->d_ng_rej) {
+        const int K = kNgMaxM - 2;
+        if ((st = dalloc(c, &c->d_ng_part, (size_t)c->n_models * ng_chunks() * (K * (K + 1) / 2 + K)))) return st;
+        if ((st = dalloc(c, &c->d_ng_coef, (size_t)c->n_models * (kNgMaxM - 1)))) return st;
+        if ((st = dalloc(c, &c->d_ng_ok, (size_t)c->n_models))) return st;
+        if ((st = dalloc(c, &c->d_ng_rej, 1))) return st;
+        c->ng_models_cap = c->n_models;
+    }
+    return NLTE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -444,6 +466,7 @@ void nlte_default_params(nlte_params *p)
     p->lines_per_lane = 0;
     p->high_occupancy = 1;
     p->persistent = 0;
+    p->ng_every = 0;
 }
 
 nlte_status nlte_create(nlte_ctx **out, int hip_device)
@@ -512,6 +535,12 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_work_counter);
     dfree(c->d_order);
     dfree(c->d_model_of);
+    dfree(c->d_model_off);
+    dfree(c->d_ng_hist);
+    dfree(c->d_ng_part);
+    dfree(c->d_ng_coef);
+    dfree(c->d_ng_ok);
+    dfree(c->d_ng_rej);
     dfree(c->d_model_done);
     dfree(c->d_model_change);
     dfree(c->d_model_iters);
@@ -734,9 +763,10 @@ nlte_status nlte_set_models(nlte_ctx *c, int n_models, const int64_t *offsets, c
     nlte_status st2;
     if ((st2 = dalloc(c, &c->d_model_of, P)) || (st2 = dalloc(c, &c->d_model_done, n_models)) ||
         (st2 = dalloc(c, &c->d_model_change, n_models)) || (st2 = dalloc(c, &c->d_model_iters, n_models)) ||
-        (st2 = dalloc(c, &c->d_model_last, n_models)))
+        (st2 = dalloc(c, &c->d_model_last, n_models)) || (st2 = dalloc(c, &c->d_model_off, n_models + 1)))
         return st2;
     HIPCHK(c, hipMemcpy(c->d_model_of, mo.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_model_off, off.data(), sizeof(int64_t) * (n_models + 1), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemset(c->d_model_done, 0, n_models));
     HIPCHK(c, hipMemset(c->d_model_iters, 0, sizeof(int32_t) * n_models));
     HIPCHK(c, hipMemset(c->d_model_last, 0, sizeof(double) * n_models));
@@ -812,8 +842,10 @@ nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
     if (!c || !p) return NLTE_E_INVALID_ARG;
     if (!(p->t_cmb > 0.0) || !(p->f_sub > 0.0) || !(p->tol >= 0.0) || p->max_iter < 1 ||
         p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
-        p->lines_per_lane < 0 || p->lines_per_lane > (p->precision == NLTE_PREC_FP32_BULK ? 3 : 2))
-        return fail(c, NLTE_E_INVALID_ARG, "parameter out of range (lines_per_lane: 0..2, 0..3 in the FP32 form)");
+        p->lines_per_lane < 0 || p->lines_per_lane > (p->precision == NLTE_PREC_FP32_BULK ? 3 : 2) ||
+        !(p->ng_every == 0 || (p->ng_every >= 3 && p->ng_every <= kNgMaxM)))
+        return fail(c, NLTE_E_INVALID_ARG,
+                    "parameter out of range (lines_per_lane: 0..2, 0..3 in the FP32 form; ng_every: 0 or 3..8)");
     c->params = *p;
     c->cfg.lpl = p->lines_per_lane;
     c->cfg.high_occupancy = p->high_occupancy ? 1 : 0;
@@ -1028,7 +1060,11 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
         if ((st = ensure_graph(c, 1, buf[1], buf[0]))) return st;
     }
     if (rep) memset(rep, 0, sizeof(*rep));
-    int it = 0, active = c->n_models;
+    const int M = c->params.ng_every;
+    if (M > 0 && (st = ensure_ng(c))) return st;
+    if (M > 0) HIPCHK(c, launch_fill_u64(c->d_ng_rej, 1, 0ull, s));
+    const size_t nel = (size_t)c->P * c->n_lev;
+    int it = 0, active = c->n_models, n_ng = 0;
     ConvResult last{};
     while (it < c->params.max_iter) {
         const int slot = it & 1;
@@ -1045,6 +1081,20 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
         }
         ++it;
         if (active == 0) break;
+        if (M > 0) {
+            // keep this iterate; after every M of them extrapolate (Sec. 3.4)
+            double *newest = buf[it & 1];
+            HIPCHK(c, hipMemcpyAsync(c->d_ng_hist + (size_t)((it - 1) % M) * nel, newest, sizeof(double) * nel,
+                                     hipMemcpyDeviceToDevice, s));
+            if (it % M == 0) {
+                NgHist h{};
+                h.M = M;
+                for (int j = 0; j < M; ++j) h.x[j] = c->d_ng_hist + (size_t)((it - 1 - j) % M) * nel;
+                HIPCHK(c, launch_ng(h, c->d_cell, c->d_model_off, c->d_model_done, c->d_model_of, c->n_models,
+                                    c->n_lev, c->P, c->d_ng_part, c->d_ng_coef, c->d_ng_ok, newest, c->d_ng_rej, s));
+                ++n_ng;
+            }
+        }
     }
     const double *cur = buf[it & 1];
     HIPCHK(c, hipMemcpyAsync(d_out, cur, np, hipMemcpyDeviceToDevice, s));
@@ -1053,6 +1103,12 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
     HIPCHK(c, hipStreamSynchronize(s));
     auto t1 = std::chrono::steady_clock::now();
     if (rep) {
+        if (M > 0) {
+            unsigned long long rej = 0;
+            HIPCHK(c, hipMemcpy(&rej, c->d_ng_rej, sizeof(rej), hipMemcpyDeviceToHost));
+            rep->n_ng_rejected = (int64_t)rej;
+        }
+        rep->n_ng_steps = n_ng;
         rep->iterations = it;
         rep->converged = active == 0 ? 1 : 0;
         rep->n_models_converged = c->n_models - active;

@@ -87,6 +87,14 @@ struct SolveArgs {
     unsigned long long *work_counter;
 };
 
+// Ng acceleration: the last M iterates, newest first.
+constexpr int kNgMaxM = 8;
+constexpr int kNgMaxSums = (kNgMaxM - 2) * (kNgMaxM - 1) / 2 + (kNgMaxM - 2);
+struct NgHist {
+    const double *x[kNgMaxM];
+    int M;
+};
+
 // Launch choices of the formal solve (picked by rule or by the autotuner).
 struct SolveConfig {
     int lpl = 0;              // lines per lane (1 or 2; 0 = by rule)
@@ -160,6 +168,7 @@ struct nlte_ctx {
     int n_models = 0;
     std::vector<int64_t> offsets;   // [n_models + 1]
     int32_t *d_model_of = nullptr;  // [P]
+    int64_t *d_model_off = nullptr; // [n_models + 1]
     uint8_t *d_model_done = nullptr;            // [n_models]
     unsigned long long *d_model_change = nullptr;  // [n_models] max change as FP64 bits
     int32_t *d_model_iters = nullptr;           // [n_models]
@@ -205,6 +214,14 @@ struct nlte_ctx {
     int32_t *d_active = nullptr;         // models still iterating
     int32_t *h_active = nullptr;         // pinned
     int64_t *d_maser = nullptr;
+
+    // Ng acceleration: ring of the last M iterates and per-model work arrays
+    double *d_ng_hist = nullptr;     // [M][P][n_lev]
+    int64_t ng_hist_elems = 0;       // capacity in doubles
+    double *d_ng_part = nullptr, *d_ng_coef = nullptr;
+    uint8_t *d_ng_ok = nullptr;
+    unsigned long long *d_ng_rej = nullptr;
+    int ng_models_cap = 0;
 
     // launch choices and the captured ALI iterations (cur -> next, next -> cur)
     nlte::SolveConfig cfg;
@@ -256,6 +273,12 @@ hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double
 int64_t stateq_blocks(int64_t P);
 hipError_t launch_conv_final(const ConvPartial *partials, int64_t n, ConvResult *out,
                              hipStream_t s);
+
+// Ng acceleration
+int ng_chunks();
+hipError_t launch_ng(const NgHist &h, const CellRec *cell, const int64_t *off, const uint8_t *done,
+                     const int32_t *model_of, int n_models, int n_lev, int64_t P, double *part, double *coef,
+                     uint8_t *ok, double *out, unsigned long long *rejected, hipStream_t s);
 
 // warm start
 hipError_t launch_features(const CellRec *cell, const double *nh2, const double *T, const int32_t *nbr,
