@@ -168,6 +168,15 @@ nlte_status nlte_trace(nlte_ctx *ctx);
 nlte_status nlte_get_ray(nlte_ctx *ctx, int64_t point, int ray, int32_t *cells, int cap,
                          int *len);
 
+/* Processing order of the points (set by nlte_set_models): within each model, by the
+ * Morton code of the coordinates quantised to 21 bits over the model's bounding box,
+ * q = floor((x - min) / (max - min) * (2^21 - 1)) (0 for a flat extent), bits interleaved
+ * x, y, z from the most significant; equal codes in index order.  perm [P]: the global
+ * index of the point at each position: the order in which points would be split into
+ * contiguous shards across devices.  (The formal solve on one device keeps index order,
+ * which measured as fast or faster; results do not depend on the order.) */
+nlte_status nlte_get_order(nlte_ctx *ctx, int64_t *perm);
+
 /* Total cached cells over all (point, ray), the longest ray, and the number of
  * elimination steps one frequency of one line takes over all half rays (cells plus
  * velocity sub-steps); any output pointer may be NULL. */

@@ -227,3 +227,29 @@ class Oracle:
 
 def from_workload(w, **kw) -> Oracle:
     return Oracle(w.model, w.species, w.rays, w.quad_x, w.quad_w, t_cmb=w.t_cmb, f_sub=w.f_sub, **kw)
+
+
+def morton_order(pos, offsets=None):
+    """Processing order of the points: within each model (offsets, default one model), by
+    the Morton code of coordinates quantised to 21 bits over the model's bounding box,
+    q = floor((x - min) / (max - min) * (2^21 - 1)) (0 for a flat extent), bits
+    interleaved x, y, z from the most significant; equal codes keep index order."""
+    pos = np.asarray(pos, dtype=np.float64)
+    P = pos.shape[0]
+    offsets = [0, P] if offsets is None else list(offsets)
+    order = np.empty(P, dtype=np.int64)
+    for m in range(len(offsets) - 1):
+        a, b = int(offsets[m]), int(offsets[m + 1])
+        x = pos[a:b]
+        lo, hi = x.min(axis=0), x.max(axis=0)
+        q = np.zeros((b - a, 3), dtype=np.uint64)
+        for d in range(3):
+            ext = hi[d] - lo[d]
+            if ext > 0:
+                q[:, d] = np.floor((x[:, d] - lo[d]) / ext * 2097151.0).astype(np.uint64)
+        code = np.zeros(b - a, dtype=np.uint64)
+        for bit in range(21):
+            for d in range(3):
+                code |= ((q[:, d] >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + 2 - d)
+        order[a:b] = a + np.argsort(code, kind="stable")
+    return order

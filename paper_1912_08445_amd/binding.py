@@ -30,7 +30,7 @@ PREC_FP32_BULK = 1
 EXPORTS = (
     "nlte_default_params", "nlte_create", "nlte_destroy", "nlte_last_error", "nlte_set_species",
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
-    "nlte_get_ray", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
+    "nlte_get_ray", "nlte_get_order", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_stateq", "nlte_stateq_dev",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
     "nlte_kernel_stats", "nlte_reset_kernel_stats",
@@ -100,6 +100,7 @@ def load():
     L.nlte_set_params.argtypes = [vp, C.POINTER(Params)]
     L.nlte_trace.argtypes = [vp]
     L.nlte_get_ray.argtypes = [vp, i64, C.c_int, vp, C.c_int, C.POINTER(C.c_int)]
+    L.nlte_get_order.argtypes = [vp, vp]
     L.nlte_trace_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int), C.POINTER(i64)]
     L.nlte_get_line_width_speed.argtypes = [vp, vp]
     L.nlte_lte.argtypes = [vp, vp]
@@ -270,6 +271,12 @@ class Solver:
         out = np.zeros(max(n.value, 1), dtype=np.int32)
         self._chk(self.L.nlte_get_ray(self.h, int(point), int(ray), _p(out), n.value, C.byref(n)))
         return out[:n.value].copy()
+
+    def order(self):
+        """Morton processing order of the points (global indices)."""
+        out = np.zeros(self.P, dtype=np.int64)
+        self._chk(self.L.nlte_get_order(self.h, _p(out)))
+        return out
 
     def trace_stats(self):
         """(total cached cells, longest ray, elimination steps per frequency per sweep)"""

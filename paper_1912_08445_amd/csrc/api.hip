@@ -536,6 +536,7 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_order);
     dfree(c->d_model_of);
     dfree(c->d_model_off);
+    dfree(c->d_morton);
     dfree(c->d_ng_hist);
     dfree(c->d_ng_part);
     dfree(c->d_ng_coef);
@@ -767,6 +768,34 @@ nlte_status nlte_set_models(nlte_ctx *c, int n_models, const int64_t *offsets, c
         return st2;
     HIPCHK(c, hipMemcpy(c->d_model_of, mo.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_model_off, off.data(), sizeof(int64_t) * (n_models + 1), hipMemcpyHostToDevice));
+    // Morton processing order within each model (bounding box per model)
+    {
+        std::vector<double> box(6 * (size_t)n_models);
+        for (int m = 0; m < n_models; ++m) {
+            double lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) lo[d] = hi[d] = off[m] < off[m + 1] ? pos[3 * off[m] + d] : 0.0;
+            for (int64_t p = off[m]; p < off[m + 1]; ++p)
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = std::min(lo[d], pos[3 * p + d]);
+                    hi[d] = std::max(hi[d], pos[3 * p + d]);
+                }
+            for (int d = 0; d < 3; ++d) {
+                box[6 * m + d] = lo[d];
+                box[6 * m + 3 + d] = hi[d] - lo[d];
+            }
+        }
+        double *d_box = nullptr;
+        if ((st2 = dalloc(c, &d_box, box.size()))) return st2;
+        if ((st2 = dalloc(c, &c->d_morton, P))) {
+            dfree(d_box);
+            return st2;
+        }
+        hipError_t e = hipMemcpy(d_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = morton_order(c->d_cell, c->d_model_of, d_box, c->d_model_off, n_models, P, c->d_morton, c->stream);
+        dfree(d_box);
+        if (e != hipSuccess) return fail(c, NLTE_E_HIP, std::string("Morton order: ") + hipGetErrorString(e));
+    }
     HIPCHK(c, hipMemset(c->d_model_done, 0, n_models));
     HIPCHK(c, hipMemset(c->d_model_iters, 0, sizeof(int32_t) * n_models));
     HIPCHK(c, hipMemset(c->d_model_last, 0, sizeof(double) * n_models));
@@ -928,6 +957,18 @@ nlte_status nlte_get_ray(nlte_ctx *c, int64_t point, int ray, int32_t *cells, in
         int m = (int)(std::upper_bound(c->offsets.begin(), c->offsets.end(), point) - c->offsets.begin()) - 1;
         for (int i = 0; i < ncopy; ++i) cells[i] -= (int32_t)c->offsets[m];
     }
+    return NLTE_OK;
+}
+
+nlte_status nlte_get_order(nlte_ctx *c, int64_t *perm)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!c->have_model) return fail(c, NLTE_E_STATE, "nlte_set_models has not been called");
+    if (!perm) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<int32_t> o(c->P);
+    HIPCHK(c, hipMemcpy(o.data(), c->d_morton, sizeof(int32_t) * c->P, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < c->P; ++i) perm[i] = o[i];
     return NLTE_OK;
 }
 

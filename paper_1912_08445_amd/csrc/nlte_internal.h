@@ -169,6 +169,7 @@ struct nlte_ctx {
     std::vector<int64_t> offsets;   // [n_models + 1]
     int32_t *d_model_of = nullptr;  // [P]
     int64_t *d_model_off = nullptr; // [n_models + 1]
+    int32_t *d_morton = nullptr;    // [P] points in Morton order within each model
     uint8_t *d_model_done = nullptr;            // [n_models]
     unsigned long long *d_model_change = nullptr;  // [n_models] max change as FP64 bits
     int32_t *d_model_iters = nullptr;           // [n_models]
@@ -260,6 +261,8 @@ hipError_t launch_formal_solve(const SolveArgs &a, const SolveConfig &cfg, int f
 hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, unsigned long long *point_cost,
                               hipStream_t s);
 hipError_t sort_by_cost(unsigned long long *cost, int32_t *order, int64_t P, hipStream_t s);
+hipError_t morton_order(const CellRec *cell, const int32_t *model_of, const double *box, const int64_t *off,
+                        int n_models, int64_t P, int32_t *order, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_model_update(int n_models, unsigned long long *change, uint8_t *done, int32_t *iters,

@@ -171,4 +171,64 @@ hipError_t sort_by_cost(unsigned long long *cost, int32_t *order, int64_t P, hip
     return e;
 }
 
+// Morton code of a point within its model's bounding box (box[m] = min x, y, z and
+// extents): each coordinate quantised to q = floor((x - min) / extent * (2^21 - 1)) (0 for
+// a flat extent), bits interleaved x, y, z from the most significant.
+__global__ void k_morton(const CellRec *__restrict__ cell, const int32_t *__restrict__ model_of,
+                         const double *__restrict__ box, int64_t P, unsigned long long *__restrict__ code)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double *b = box + 6 * model_of[p];
+    const double x[3] = {cell[p].px, cell[p].py, cell[p].pz};
+    unsigned long long q[3];
+    for (int d = 0; d < 3; ++d) {
+        const double ext = b[3 + d];
+        q[d] = ext > 0.0 ? (unsigned long long)floor((x[d] - b[d]) / ext * 2097151.0) : 0ull;
+    }
+    unsigned long long c = 0;
+    for (int bit = 0; bit < 21; ++bit)
+        for (int d = 0; d < 3; ++d) c |= ((q[d] >> bit) & 1ull) << (3 * bit + 2 - d);
+    code[p] = c;
+}
+
+__global__ void k_iota(int32_t *__restrict__ v, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+
+// Points of each model (offsets on the device) in Morton order, equal codes by index
+// (the radix sort is stable).  Synchronises the stream.
+hipError_t morton_order(const CellRec *cell, const int32_t *model_of, const double *box, const int64_t *off,
+                        int n_models, int64_t P, int32_t *order, hipStream_t s)
+{
+    if (P == 0) return hipSuccess;
+    unsigned long long *codes = nullptr, *codes_out = nullptr;
+    int32_t *idx = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    hipError_t e = hipMalloc((void **)&codes, sizeof(unsigned long long) * P);
+    if (e == hipSuccess) e = hipMalloc((void **)&codes_out, sizeof(unsigned long long) * P);
+    if (e == hipSuccess) e = hipMalloc((void **)&idx, sizeof(int32_t) * P);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_morton, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, cell, model_of, box, P, codes);
+        hipLaunchKernelGGL(k_iota, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, idx, P);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tmp_bytes, codes, codes_out, idx, order, (int)P,
+                                                         n_models, off, off + 1, 0, 63, s);
+    if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes ? tmp_bytes : 1);
+    if (e == hipSuccess)
+        e = hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tmp_bytes, codes, codes_out, idx, order, (int)P,
+                                                         n_models, off, off + 1, 0, 63, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (tmp) (void)hipFree(tmp);
+    if (codes) (void)hipFree(codes);
+    if (codes_out) (void)hipFree(codes_out);
+    if (idx) (void)hipFree(idx);
+    return e;
+}
+
 }  // namespace nlte

@@ -294,3 +294,20 @@ def test_error_codes():
     s.set_rays(w.rays)
     with pytest.raises(binding.NlteError):
         s.set_quadrature(np.array([-1.0, 0.5]), np.array([0.5, 0.5]))
+
+
+# ---------------------------------------------------------------- point order
+
+def test_morton_order_bit_exact():
+    import oracle
+    from synth.models import chain_1d, concat_models
+    cases = [configs.sphere2(500), configs.outflow5(n_points=5000, seed=3)]
+    x = np.linspace(0.0, 1e16, 50)
+    chain = configs.sphere2(10)
+    chain.model = chain_1d(x, np.zeros(50), 1e4, 20.0, 1.5e4, 1e-8)     # flat y and z extents
+    cases.append(chain)
+    b = configs.batch256(n_models=4, n_min=200, n_max=800, seed0=40)
+    cases.append(b)
+    for w in cases:
+        s = solver_for(w, trace=False)
+        assert np.array_equal(s.order(), oracle.morton_order(w.model.pos, w.offsets))

@@ -462,3 +462,34 @@ def test_alo_does_not_change_fixed_point(oracle_lib):
     assert cha[-1] < 1e-12 and chb[-1] < 1e-12
     assert np.abs(rel(pa, pb)).max() < 1e-9
     assert len(cha) <= len(chb)
+
+
+# ---------------------------------------------------------------- Morton order
+
+def test_morton_order_reference():
+    import oracle
+    from synth.models import lattice_3d
+    # 2x2x2 lattice: one bit per axis, x most significant, so index order (i, j, k)
+    m = lattice_3d(2, 1e15)
+    assert np.array_equal(oracle.morton_order(m.pos), np.arange(8))
+    # brute force on random points: codes from the definition with Python integers
+    rng = np.random.default_rng(0)
+    pos = rng.uniform(-1, 1, (300, 3))
+    pos[:5] = pos[5]                        # equal codes keep index order
+    order = oracle.morton_order(pos)
+    lo, hi = pos.min(0), pos.max(0)
+
+    def code(p):
+        q = [int(np.floor((p[d] - lo[d]) / (hi[d] - lo[d]) * 2097151.0)) for d in range(3)]
+        c = 0
+        for b in range(21):
+            for d in range(3):
+                c |= ((q[d] >> b) & 1) << (3 * b + 2 - d)
+        return c
+
+    keys = [(code(pos[i]), i) for i in range(300)]
+    assert np.array_equal(order, [i for _, i in sorted(keys)])
+    # models are ordered separately
+    offs = [0, 100, 300]
+    o2 = oracle.morton_order(pos, offs)
+    assert np.array_equal(np.sort(o2[:100]), np.arange(100)) and np.array_equal(o2[:100], oracle.morton_order(pos[:100]))
