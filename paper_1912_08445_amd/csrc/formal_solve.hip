@@ -340,7 +340,9 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                 const T im = rec[i].inv_m;
                 const T dx = rec[i].da * xq - rec[i].db;
                 const int K = rec[i].K;
-                if (F32 || K == 0) {
+                // direct evaluation where the recurrence would not pay for its two
+                // exponentials (one sub-step node) or cannot be used (K == 0)
+                if (F32 || K == 0 || m == 2) {
                     T S0[LPL], dk[LPL], dS[LPL];
 #pragma unroll
                     for (int l = 0; l < LPL; ++l) {
@@ -397,7 +399,15 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                             recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
                             recur_step<F32, LPL, true>(g, r, c, kq, dkq, St, dS, a_prev, ls);
                         }
-                        for (; jj < jint; ++jj) recur_step<F32, LPL, true>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                        // the last 0-3 steps in straight-line code; the elimination step
+                        // that follows renormalises, so at most seven steps pass between
+                        // renormalisations
+                        const int rem = jint - jj;
+                        if (rem >= 2) {
+                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                        }
+                        if (rem & 1) recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
                         travel += mdx * (double)(jint - j);
                         j = jint;
                         if (jend == m) {
