@@ -15,8 +15,9 @@
 //   T = h_i + Q_{i-1};  F_i = D_+ T;  E = 1/(1 + F_i);  Q_i = T E;  y_i = (S_i h_i + y_{i-1}) E
 // with Q = 1, y = I_boundary, D_- = 0 before the first node, which is exactly the Auer
 // boundary row.  No step divides by an optical depth.  The sweep carries Q and y as
-// fractions N/D and Y/D, which turns each step into three multiply-adds of non-negative
-// numbers with no division (see elim_step).  At O the two halves combine into
+// fractions N/D and Y/D (scaled by sqrt 2, which cancels at O), which turns each step
+// into three multiply-adds of non-negative numbers with no division (see elim_step).
+// At O the two halves combine into
 //   u_O = (h_O S_O + y_f + y_b) / (h_O + Q_f + Q_b),   Lambda_OO = h_O / (h_O + Q_f + Q_b),
 // and u_O - Lambda_OO S_O = (y_f + y_b) / (h_O + Q_f + Q_b) without cancellation.
 //
@@ -29,6 +30,9 @@
 #include "nlte_internal.h"
 
 namespace nlte {
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr double kInv2Sqrt2 = 0.35355339059327376220;  // 1 / (2 sqrt 2)
 
 // ---------------------------------------------------------------- line coefficients
 
@@ -100,7 +104,7 @@ struct Bulk<true> {
 
 // One staged node of a half ray.  (a, b) give the Doppler offset of a lane's frequency
 // x_q at this node as x = a x_q - b.  The segment to the next node toward O has m
-// sub-intervals of length 4 dzq; per sub-interval x changes by da x_q - db.  maxdx bounds
+// sub-intervals of length 2 sqrt(2) dzq; per sub-interval x changes by da x_q - db.  maxdx bounds
 // |dx| over all frequencies, K is the restart interval of the profile recurrence (0:
 // evaluate every profile directly).  kap, S: line-centre opacity and source function of
 // the wave's lines.
@@ -112,8 +116,8 @@ struct NodeRec {
 };
 
 // Elimination state of a half sweep in homogeneous form: the Rybicki-Hummer quantities
-// Q = N / D and y = Y / D (see the file comment), and Hm, half the previous
-// optical-depth step.
+// Q = N / (sqrt 2 D) and y = Y / (sqrt 2 D), and Hm = D_- / sqrt 2, the previous
+// optical-depth step (see elim_step).
 struct HalfState {
     double N, D, Y, Hm;
 };
@@ -169,24 +173,29 @@ __device__ __forceinline__ float profile(float x)
     return __builtin_amdgcn_exp2f(-(x * x) * 1.44269504088896340736f);
 }
 
-// One elimination step.  a_prev, a_t are chi dz/4 at the two ends of the step, so
-// Hp = a_prev + a_t is half its trapezoid optical depth D_+, and h = Hm + Hp.  The
-// Rybicki-Hummer update  T = h + Q, E = 1/(1 + D_+ T), Q' = T E, y' = (S h + y) E
+// One elimination step.  The Rybicki-Hummer update with h = (D_- + D_+)/2 (mean of the
+// trapezoid optical depths D_-, D_+ on either side of the node)
+//   T = h + Q,  E = 1/(1 + D_+ T),  Q' = T E,  y' = (S h + y) E
 // becomes, for Q = N/D and y = Y/D,
 //   N' = N + h D,  Y' = Y + S h D,  D' = D + D_+ N'
-// (products and sums of non-negative numbers only).  RENORM rescales N, D, Y by the
-// power of two that brings D into [0.5, 1), which is exact.
+// (products and sums of non-negative numbers only).  The node coefficients a are
+// chi dz / (2 sqrt 2), so P = a_prev + a_t = D_+ / sqrt 2, and the state is carried as
+// n = sqrt 2 N, y~ = sqrt 2 Y, d = D, which turns the update into
+//   n' = n + (P_- + P) d,  y~' = y~ + S (P_- + P) d,  d' = d + P n'
+// with no constant factors; Q = n/(sqrt 2 d), y = y~/(sqrt 2 d), and the factor sqrt 2
+// cancels in every quantity formed at the origin.  RENORM rescales n, d, y~ by the power
+// of two that brings d into [0.5, 1), which is exact.
 template <bool F32, bool RENORM>
 __device__ __forceinline__ void elim_step(typename Bulk<F32>::T a_t, typename Bulk<F32>::T S_t,
                                           typename Bulk<F32>::T &a_prev, typename Bulk<F32>::T &S_e,
                                           HalfState &st)
 {
-    const double Hp = (double)(a_prev + a_t);
-    const double hD = (st.Hm + Hp) * st.D;
-    st.N = st.N + hD;
-    st.Y = fma((double)S_e, hD, st.Y);
-    st.D = fma(Hp + Hp, st.N, st.D);
-    st.Hm = Hp;
+    const double Pp = (double)(a_prev + a_t);
+    const double hd = (st.Hm + Pp) * st.D;
+    st.N = st.N + hd;
+    st.Y = fma((double)S_e, hd, st.Y);
+    st.D = fma(Pp, st.N, st.D);
+    st.Hm = Pp;
     a_prev = a_t;
     S_e = S_t;
     if (RENORM) {
@@ -236,9 +245,10 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
     const int lane = threadIdx.x;
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
-        ls.st[l].N = 1.0;
+        // Q = 1, y = I_in at the far boundary (in the scaled state of elim_step)
+        ls.st[l].N = kSqrt2;
         ls.st[l].D = 1.0;
-        ls.st[l].Y = ib[l];
+        ls.st[l].Y = kSqrt2 * ib[l];
         ls.st[l].Hm = 0.0;
     }
     const int64_t base = O * a.n_rays + ray;
@@ -297,7 +307,7 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                 const double im = 1.0 / (double)m;
                 r.m = m;
                 r.inv_m = (T)im;
-                r.dzq = (T)(0.25 * (Zs - Zn) * im);
+                r.dzq = (T)(kInv2Sqrt2 * (Zs - Zn) * im);
                 r.da = (T)((an1 - an) * im);
                 r.db = (T)((bn1 - bn) * im);
                 // bound on |dx| over every frequency of the quadrature; the recurrence of
