@@ -31,6 +31,14 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_STEP = 17
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0   # dense
+
+
+def mlp_flops_per_row(n_out):
+    """Algorithmic flops of the 8-128-128-128-n_out network: forward, and one training
+    pass (forward, weight gradients of every layer, input gradients of layers 2-4)."""
+    fwd = 2 * (8 * 128 + 2 * 128 * 128 + 128 * n_out)
+    return fwd, 3 * fwd - 2 * 8 * 128
 
 
 def log(*a):
@@ -134,6 +142,7 @@ def train_warm_start(s, w, make, args, dev):
     curve = warmstart.train(s, rows, mean, std, [(6000, 2e-3), (4000, 2e-4)], batch=4096, seed=1)
     t_train = time.perf_counter() - t0
     n_rows = sum(int(r[0].shape[0]) for r in rows)
+    s._bench_rows = rows   # kept for the kernel timing of training steps
     log(f"warm start: {len(seeds)} training models, {n_rows} rows, data {t_data:.1f} s, "
         f"training {t_train:.1f} s, loss {curve[:5].mean():.3e} -> {curve[-50:].mean():.3e}")
     return {"train_models": len(seeds), "train_seeds": seeds, "rows": n_rows, "data_s": t_data,
@@ -186,8 +195,44 @@ def ali_forms(s, w, make, args, dev):
             res[key]["used_network"] = r["used_network"]
         log(f"ALI {key}: {r['iterations']} iterations, {wall * 1e3:.1f} ms, max rel diff vs FP64 "
             f"reference {err:.2e}, changes {['%.2e' % c for c in r['max_change']]}")
+    if warm:
+        res["mlp"] = mlp_timing(s, w, dev)
     s.set_params(precision=args.precision)
     return res
+
+
+def mlp_timing(s, w, dev, steps=50):
+    """Per-kernel HIP-event times of prediction (features, network forward over every
+    point) and of training steps, with algorithmic throughput against the dense BF16
+    matrix-core peak."""
+    import torch
+    n_out = w.species.n_lev
+    fwd_f, train_f = mlp_flops_per_row(n_out)
+    out = torch.empty((w.n_points, n_out), dtype=torch.float64, device=dev)
+    X = torch.cat([r[0] for r in s._bench_rows]).contiguous()
+    T = torch.cat([r[1] for r in s._bench_rows]).contiguous()
+    s.set_params(profile=1)
+    s.reset_kernel_stats()
+    for _ in range(3):
+        s.mlp_predict_dev(out)
+    s.mlp_train_dev(X, T, steps=steps, batch=4096, lr=2e-4)
+    torch.cuda.synchronize()
+    s.set_params(profile=0)
+    f_ms, f_n = s.kernel_stats("mlp_forward")
+    ft_ms, _ = s.kernel_stats("features")
+    t_ms, t_n = s.kernel_stats("mlp_train")
+    u_ms, _ = s.kernel_stats("mlp_update")
+    fwd_ms, tr_ms, up_ms = f_ms / f_n, t_ms / t_n, u_ms / t_n
+    fwd_tf = fwd_f * w.n_points / (fwd_ms * 1e-3) / 1e12
+    tr_tf = train_f * 4096 / (tr_ms * 1e-3) / 1e12
+    r = {"rows_forward": w.n_points, "forward_ms": fwd_ms, "features_ms": ft_ms / f_n,
+         "forward_tflops": fwd_tf, "forward_mfma_frac": fwd_tf / PEAK_BF16_MFMA_TFLOPS,
+         "train_batch": 4096, "train_kernel_ms": tr_ms, "update_ms": up_ms,
+         "train_tflops": tr_tf, "train_mfma_frac": tr_tf / PEAK_BF16_MFMA_TFLOPS,
+         "flops_per_row": {"forward": fwd_f, "train": train_f}, "peak_tflops": PEAK_BF16_MFMA_TFLOPS}
+    log(f"mlp: forward {fwd_ms:.3f} ms for {w.n_points} rows ({fwd_tf:.1f} TFLOP/s), features "
+        f"{ft_ms / f_n:.3f} ms; train step {tr_ms:.3f} + {up_ms:.3f} ms ({tr_tf:.1f} TFLOP/s)")
+    return r
 
 
 def main():

@@ -363,8 +363,10 @@ nlte_status mlp_ensure_points(nlte_ctx *c)
 
 nlte_status features_impl(nlte_ctx *c, double *d_F, hipStream_t s)
 {
-    HIPCHK(c, launch_features(c->d_cell, c->d_nh2, c->d_T, c->d_nbr, c->k, c->d_roff, c->d_rcells, c->d_dir,
-                              c->n_rays, c->P, d_F, s));
+    HIPCHK(c, timed(c, c->st_features, s, [&] {
+        return launch_features(c->d_cell, c->d_nh2, c->d_T, c->d_nbr, c->k, c->d_roff, c->d_rcells, c->d_dir,
+                               c->n_rays, c->P, d_F, s);
+    }));
     return NLTE_OK;
 }
 
@@ -377,7 +379,8 @@ nlte_status predict_impl(nlte_ctx *c, double *d_pops, hipStream_t s)
     if ((st = mlp_ensure_points(c))) return st;
     if ((st = features_impl(c, m.d_feat, s))) return st;
     HIPCHK(c, launch_mlp_standardise(m.d_feat, m.norm, c->P, m.d_xp, s));
-    HIPCHK(c, launch_mlp_forward(m.d_frags, m.d_theta, m.dims, m.d_xp, c->P, m.d_yp, s));
+    HIPCHK(c, timed(c, c->st_mlp_forward, s,
+                    [&] { return launch_mlp_forward(m.d_frags, m.d_theta, m.dims, m.d_xp, c->P, m.d_yp, s); }));
     HIPCHK(c, launch_fill_u64(m.d_bad, 1, 0ull, s));
     HIPCHK(c, launch_lte(c->sp, c->d_cell, c->d_T, c->P, d_pops, s));
     HIPCHK(c, launch_mlp_populations(c->sp, m.d_yp, c->d_cell, c->d_T, c->P, d_pops, m.d_bad, s));
@@ -396,14 +399,19 @@ nlte_status train_impl(nlte_ctx *c, const float *d_X, const float *d_T, int64_t 
     for (int64_t i = 0; i < tp->steps; ++i) {
         const int64_t t = ++m.step;
         const int64_t start = (int64_t)(((__int128)(t - 1) * tp->batch) % n);
-        HIPCHK(c, launch_mlp_train(m.d_frags, m.d_theta, m.dims, d_X, d_T, n, start, tp->batch, m.d_gpart,
-                                   m.d_lpart, s));
+        HIPCHK(c, timed(c, c->st_mlp_train, s, [&] {
+            return launch_mlp_train(m.d_frags, m.d_theta, m.dims, d_X, d_T, n, start, tp->batch, m.d_gpart,
+                                    m.d_lpart, s);
+        }));
         const float c1 = (float)(1.0 / (1.0 - pow(tp->beta1, (double)t)));
         const float c2 = (float)(1.0 / (1.0 - pow(tp->beta2, (double)t)));
-        HIPCHK(c, launch_mlp_reduce_adam(m.d_theta, m.d_m, m.d_v, m.d_gpart, n_wg, m.dims.n_params, 1,
-                                         (float)tp->lr, (float)tp->beta1, (float)tp->beta2, (float)tp->eps, c1, c2,
-                                         m.d_lpart, inv_count, d_loss ? d_loss + i : nullptr, nullptr, s));
-        HIPCHK(c, launch_mlp_pack(m.d_theta, m.dims, m.d_frags, s));
+        HIPCHK(c, timed(c, c->st_mlp_update, s, [&] {
+            hipError_t e = launch_mlp_reduce_adam(m.d_theta, m.d_m, m.d_v, m.d_gpart, n_wg, m.dims.n_params, 1,
+                                                  (float)tp->lr, (float)tp->beta1, (float)tp->beta2,
+                                                  (float)tp->eps, c1, c2, m.d_lpart, inv_count,
+                                                  d_loss ? d_loss + i : nullptr, nullptr, s);
+            return e == hipSuccess ? launch_mlp_pack(m.d_theta, m.dims, m.d_frags, s) : e;
+        }));
     }
     return NLTE_OK;
 }
@@ -1310,6 +1318,10 @@ nlte_status nlte_kernel_stats(nlte_ctx *c, const char *name, double *ms, int64_t
     else if (!strcmp(name, "stateq")) k = &c->st_stateq;
     else if (!strcmp(name, "lte")) k = &c->st_lte;
     else if (!strcmp(name, "trace")) k = &c->st_trace;
+    else if (!strcmp(name, "features")) k = &c->st_features;
+    else if (!strcmp(name, "mlp_forward")) k = &c->st_mlp_forward;
+    else if (!strcmp(name, "mlp_train")) k = &c->st_mlp_train;
+    else if (!strcmp(name, "mlp_update")) k = &c->st_mlp_update;
     if (!k) return fail(c, NLTE_E_INVALID_ARG, "unknown kernel name");
     if (ms) *ms = k->ms;
     if (launches) *launches = k->launches;
@@ -1320,6 +1332,7 @@ nlte_status nlte_reset_kernel_stats(nlte_ctx *c)
 {
     if (!c) return NLTE_E_INVALID_ARG;
     c->st_line_coef = c->st_formal = c->st_stateq = c->st_lte = c->st_trace = KernelStat{};
+    c->st_features = c->st_mlp_forward = c->st_mlp_train = c->st_mlp_update = KernelStat{};
     return NLTE_OK;
 }
 

@@ -237,6 +237,7 @@ struct nlte_ctx {
     // profiling
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     nlte::KernelStat st_line_coef, st_formal, st_stateq, st_lte, st_trace;
+    nlte::KernelStat st_features, st_mlp_forward, st_mlp_train, st_mlp_update;
 };
 
 namespace nlte {
