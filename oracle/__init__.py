@@ -130,6 +130,10 @@ class Oracle:
             raise ValueError("ray set is not point-symmetric")
         self.n_rays = int(rays.shape[0])
         self.n_pairs = npairs
+        self.rays = np.array(rays, dtype=np.float64)
+        self.model = model
+        self.t_cmb = t_cmb
+        self.tau_floor = tau_floor
         L.or_set_quadrature(self.c, int(quad_x.shape[0]), _f64(quad_x), _f64(quad_w))
         L.or_set_params(self.c, t_cmb, f_sub, tau_floor, 1 if use_alo else 0)
 
@@ -210,6 +214,52 @@ class Oracle:
                           flags.ctypes.data)
         return out, flags
 
+    def image(self, pops, ray, line, v_ch):
+        """Sec. 3.5: intensity leaving the model along direction `ray` at the far end of the
+        ray pair through every point, at observer-frame channel velocities v_ch [cm/s] of
+        line `line` (profile offset x = (v - n.v_k)/v_w,k at node k), with CMB intensity
+        entering at both ends: I_out = 2 u_end - I_in from the pair's second-order
+        solution.  Returns I [P][n_ch] and the image-plane coordinates [P][2]."""
+        pops = _f64(pops)
+        v_ch = np.atleast_1d(np.asarray(v_ch, dtype=np.float64))
+        dirs = self.rays
+        n = dirs[ray]
+        # the pair holding this ray, and whether it is the pair's representative
+        pair, forward = None, None
+        for p in range(self.n_pairs):
+            r = self._pair_rep(p)
+            if r == ray:
+                pair, forward = p, True
+            elif np.allclose(dirs[r], -n, atol=1e-12):
+                pair, forward = p, False
+        sp = self.species
+        nu = (sp.energy[sp.line_up[line]] - sp.energy[sp.line_lo[line]]) / 6.62607015e-27
+        I_in = planck(nu, self.t_cmb)
+        vw = self.line_width_speed()
+        vel = self.model.vel
+        out = np.zeros((self.P, v_ch.shape[0]))
+        for O in range(self.P):
+            nd = self.pair_nodes(pops, O, pair)
+            z, a, b = nd["z"], nd["a"], nd["b"]
+            kap, S = nd["kappa"][:, line], nd["S"][:, line]
+            # frame of O: x_k = a_k x_O - b_k along the representative's direction m;
+            # for the antipode the propagation direction is -m and x_k = a_k x_O + b_k
+            nvO = float(np.dot(n, vel[O]))
+            for c, v in enumerate(v_ch):
+                xO = (v - nvO) / vw[O]
+                x = a * xO - b if forward else a * xO + b
+                chi = kap * np.exp(-x * x)
+                _, _, _, u = solve_ray(z, chi, S, I_in, I_in, nd["o"], tau_floor=self.tau_floor, want_all=True)
+                u_end = u[-1] if forward else u[0]
+                out[O, c] = 2.0 * u_end - I_in
+        return out, image_plane(self.model.pos, n)
+
+    def _pair_rep(self, p):
+        """Representative ray of pair p (the lower index of the two antipodes)."""
+        reps = [r for r in range(self.n_rays)
+                if r == min(r, int(np.argmin(np.linalg.norm(self.rays + self.rays[r], axis=1))))]
+        return reps[p]
+
     def rel_change(self, old, new):
         mean = C.c_double()
         mx = self._L.or_rel_change(self.c, _f64(old), _f64(new), C.byref(mean))
@@ -227,6 +277,18 @@ class Oracle:
 
 def from_workload(w, **kw) -> Oracle:
     return Oracle(w.model, w.species, w.rays, w.quad_x, w.quad_w, t_cmb=w.t_cmb, f_sub=w.f_sub, **kw)
+
+
+def image_plane(pos, n):
+    """Coordinates of points on the plane orthogonal to direction n: (x . e1, x . e2) with
+    e1 = (z x n)/|z x n| (x-axis instead of z when |n_z| > 0.9) and e2 = n x e1."""
+    n = np.asarray(n, dtype=np.float64)
+    ref = np.array([0.0, 0.0, 1.0]) if abs(n[2]) <= 0.9 else np.array([1.0, 0.0, 0.0])
+    e1 = np.cross(ref, n)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(n, e1)
+    pos = np.asarray(pos, dtype=np.float64)
+    return np.stack([pos @ e1, pos @ e2], axis=1)
 
 
 def morton_order(pos, offsets=None):
