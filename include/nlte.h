@@ -255,6 +255,24 @@ nlte_status nlte_get_model_status(nlte_ctx *ctx, int32_t *iterations, uint8_t *c
  */
 nlte_status nlte_autotune(nlte_ctx *ctx, const char *cache_path, int trials, char *choice, int cap);
 
+/* ---------------------------------------------------------------- imaging */
+
+/*
+ * Image of the model (Sec. 3.5) along direction `ray` (the direction of propagation,
+ * toward the observer) in line `line` at n_ch (1..1024) observer-frame channel velocities
+ * v_ch [cm/s] (host array; channel frequency nu_l (1 + v/c), profile offset
+ * x = (v - n.v_k)/v_w,k at node k): I [P][n_ch] is the intensity leaving the model at the
+ * far end of the ray pair through each point, 2 u_E - I_in from the pair's second-order
+ * solution with CMB intensity (line centre, t_cmb) entering at both ends; xy [P][2]
+ * (nullable) the point's image-plane coordinates (x . e1, x . e2), e1 = (z x n)/|z x n|
+ * (the x axis in place of z when |n_z| > 0.9), e2 = n x e1.  Populations pops [P][n_lev]
+ * give the line coefficients (FP64 whatever the precision setting).  Needs nlte_trace.
+ */
+nlte_status nlte_image(nlte_ctx *ctx, const double *pops, int ray, int line, int n_ch, const double *v_ch,
+                       double *I, double *xy);
+nlte_status nlte_image_dev(nlte_ctx *ctx, const double *d_pops, int ray, int line, int n_ch,
+                           const double *v_ch, double *d_I, double *d_xy, void *stream);
+
 /* ---------------------------------------------------------------- warm start */
 
 /*

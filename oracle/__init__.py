@@ -214,12 +214,13 @@ class Oracle:
                           flags.ctypes.data)
         return out, flags
 
-    def image(self, pops, ray, line, v_ch):
+    def image(self, pops, ray, line, v_ch, points=None):
         """Sec. 3.5: intensity leaving the model along direction `ray` at the far end of the
         ray pair through every point, at observer-frame channel velocities v_ch [cm/s] of
         line `line` (profile offset x = (v - n.v_k)/v_w,k at node k), with CMB intensity
         entering at both ends: I_out = 2 u_end - I_in from the pair's second-order
-        solution.  Returns I [P][n_ch] and the image-plane coordinates [P][2]."""
+        solution.  Returns I [P][n_ch] (rows of `points` only, if given) and the
+        image-plane coordinates [P][2]."""
         pops = _f64(pops)
         v_ch = np.atleast_1d(np.asarray(v_ch, dtype=np.float64))
         dirs = self.rays
@@ -237,8 +238,9 @@ class Oracle:
         I_in = planck(nu, self.t_cmb)
         vw = self.line_width_speed()
         vel = self.model.vel
-        out = np.zeros((self.P, v_ch.shape[0]))
-        for O in range(self.P):
+        pts = range(self.P) if points is None else [int(p) for p in points]
+        out = np.zeros((len(pts), v_ch.shape[0]))
+        for row, O in enumerate(pts):
             nd = self.pair_nodes(pops, O, pair)
             z, a, b = nd["z"], nd["a"], nd["b"]
             kap, S = nd["kappa"][:, line], nd["S"][:, line]
@@ -251,7 +253,7 @@ class Oracle:
                 chi = kap * np.exp(-x * x)
                 _, _, _, u = solve_ray(z, chi, S, I_in, I_in, nd["o"], tau_floor=self.tau_floor, want_all=True)
                 u_end = u[-1] if forward else u[0]
-                out[O, c] = 2.0 * u_end - I_in
+                out[row, c] = 2.0 * u_end - I_in
         return out, image_plane(self.model.pos, n)
 
     def _pair_rep(self, p):

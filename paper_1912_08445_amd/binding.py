@@ -37,7 +37,7 @@ EXPORTS = (
     "nlte_default_train_params", "nlte_mlp_param_count", "nlte_features", "nlte_features_dev",
     "nlte_mlp_init", "nlte_mlp_set_weights", "nlte_mlp_get_weights", "nlte_mlp_set_norm",
     "nlte_mlp_forward", "nlte_mlp_loss_grad", "nlte_mlp_train", "nlte_mlp_train_dev",
-    "nlte_mlp_predict", "nlte_mlp_predict_dev", "nlte_mlp_rows_dev", "nlte_run_ali_warm", "nlte_run_ali_warm_dev",
+    "nlte_mlp_predict", "nlte_mlp_predict_dev", "nlte_mlp_rows_dev", "nlte_run_ali_warm", "nlte_run_ali_warm_dev", "nlte_image", "nlte_image_dev",
 )
 
 MLP_INPUTS = 8
@@ -131,6 +131,8 @@ def load():
     L.nlte_mlp_predict.argtypes = [vp, vp, C.POINTER(i64)]
     L.nlte_mlp_predict_dev.argtypes = [vp, vp, C.POINTER(i64), vp]
     L.nlte_mlp_rows_dev.argtypes = [vp, vp, vp, vp, vp]
+    L.nlte_image.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
+    L.nlte_image_dev.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp]
     L.nlte_run_ali_warm.argtypes = [vp, vp, C.POINTER(AliReport), C.POINTER(C.c_int)]
     L.nlte_run_ali_warm_dev.argtypes = [vp, vp, C.POINTER(AliReport), C.POINTER(C.c_int), vp]
     for name in EXPORTS:
@@ -353,6 +355,21 @@ class Solver:
         self.params.high_occupancy = int(fields["high"])
         self.params.persistent = int(fields["persistent"])
         return choice
+
+    # ---------------------------------------------------------------- imaging
+    def image(self, pops, ray, line, v_ch):
+        """Emergent intensities I [P][n_ch] along `ray` and image-plane coordinates [P][2]."""
+        pops = _c(pops, np.float64)
+        v = _c(np.atleast_1d(v_ch), np.float64)
+        I = np.zeros((self.P, v.shape[0]))
+        xy = np.zeros((self.P, 2))
+        self._chk(self.L.nlte_image(self.h, _p(pops), int(ray), int(line), v.shape[0], _p(v), _p(I), _p(xy)))
+        return I, xy
+
+    def image_dev(self, pops, ray, line, v_ch, I, xy=None, stream=None):
+        v = _c(np.atleast_1d(v_ch), np.float64)
+        self._chk(self.L.nlte_image_dev(self.h, _tp(pops), int(ray), int(line), v.shape[0], _p(v), _tp(I),
+                                        _tp(xy), _stream(stream)))
 
     # ---------------------------------------------------------------- warm start
     def features(self):

@@ -545,6 +545,7 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_model_of);
     dfree(c->d_model_off);
     dfree(c->d_morton);
+    dfree(c->d_vch);
     dfree(c->d_ng_hist);
     dfree(c->d_ng_part);
     dfree(c->d_ng_coef);
@@ -1609,6 +1610,94 @@ nlte_status nlte_run_ali_warm(nlte_ctx *c, double *pops_out, nlte_ali_report *re
         rs = fail(c, NLTE_E_HIP, "copy of the populations failed");
     dfree(d_out);
     return rs;
+}
+
+// ------------------------------------------------------------------ imaging
+
+nlte_status nlte_image_dev(nlte_ctx *c, const double *d_pops, int ray, int line, int n_ch, const double *v_ch,
+                           double *d_I, double *d_xy, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!d_pops || !d_I || !v_ch) return fail(c, NLTE_E_INVALID_ARG, "null pointer");
+    if (ray < 0 || ray >= c->n_rays) return fail(c, NLTE_E_INVALID_ARG, "ray out of range");
+    if (line < 0 || line >= c->n_lines) return fail(c, NLTE_E_INVALID_ARG, "line out of range");
+    if (n_ch < 1 || n_ch > 1024) return fail(c, NLTE_E_INVALID_ARG, "n_ch must be in 1..1024");
+    for (int i = 0; i < n_ch; ++i)
+        if (!std::isfinite(v_ch[i])) return fail(c, NLTE_E_INVALID_ARG, "non-finite channel velocity");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = pick(c, stream);
+    if (n_ch > c->vch_cap) {
+        if ((st = dalloc(c, &c->d_vch, (size_t)n_ch))) return st;
+        c->vch_cap = n_ch;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_vch, v_ch, sizeof(double) * n_ch, hipMemcpyHostToDevice, s));
+    // FP64 line coefficients of these populations
+    HIPCHK(c, launch_line_coef(c->sp, c->d_cell, d_pops, c->P, 0, c->d_lc, c->d_maser, s));
+    const double nu = c->nu[line];
+    ImageArgs a{};
+    a.cell = c->d_cell;
+    a.lc = c->d_lc;
+    a.roff = c->d_roff;
+    a.rcells = c->d_rcells;
+    a.dir = c->d_dir;
+    a.anti = c->d_anti;
+    a.v_ch = c->d_vch;
+    a.I = d_I;
+    a.f_sub = c->params.f_sub;
+    a.I_in = 2.0 * kH * nu * nu * nu / (kC * kC) / expm1(kH * nu / (kKB * c->params.t_cmb));
+    a.P = c->P;
+    a.n_rays = c->n_rays;
+    a.n_lines = c->n_lines;
+    a.line = line;
+    a.ray = ray;
+    a.n_ch = n_ch;
+    // image-plane basis: e1 = (z x n)/|z x n| (x-axis instead of z when |n_z| > 0.9), e2 = n x e1
+    std::vector<double> dir(3 * (size_t)c->n_rays);
+    HIPCHK(c, hipMemcpy(dir.data(), c->d_dir, sizeof(double) * dir.size(), hipMemcpyDeviceToHost));
+    const double n0 = dir[3 * ray], n1 = dir[3 * ray + 1], n2 = dir[3 * ray + 2];
+    double r0 = 0.0, r1 = 0.0, r2 = 1.0;
+    if (fabs(n2) > 0.9) {
+        r0 = 1.0;
+        r2 = 0.0;
+    }
+    double e1x = r1 * n2 - r2 * n1, e1y = r2 * n0 - r0 * n2, e1z = r0 * n1 - r1 * n0;
+    const double en = sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
+    e1x /= en;
+    e1y /= en;
+    e1z /= en;
+    const double3 e1 = make_double3(e1x, e1y, e1z);
+    const double3 e2 = make_double3(n1 * e1z - n2 * e1y, n2 * e1x - n0 * e1z, n0 * e1y - n1 * e1x);
+    HIPCHK(c, launch_image(a, e1, e2, d_xy, s));
+    return NLTE_OK;
+}
+
+nlte_status nlte_image(nlte_ctx *c, const double *pops, int ray, int line, int n_ch, const double *v_ch, double *I,
+                       double *xy)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!pops || !I) return fail(c, NLTE_E_INVALID_ARG, "null pointer");
+    if (n_ch < 1 || n_ch > 1024) return fail(c, NLTE_E_INVALID_ARG, "n_ch must be in 1..1024");
+    HIPCHK(c, hipSetDevice(c->device));
+    double *d_I = nullptr, *d_xy = nullptr;
+    if ((st = dalloc(c, &d_I, (size_t)c->P * n_ch))) return st;
+    if (xy && (st = dalloc(c, &d_xy, (size_t)c->P * 2))) {
+        dfree(d_I);
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(c->d_pops_a, pops, sizeof(double) * c->P * c->n_lev, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) st = nlte_image_dev(c, c->d_pops_a, ray, line, n_ch, v_ch, d_I, d_xy, c->stream);
+    if (e == hipSuccess && st == NLTE_OK)
+        e = hipMemcpyAsync(I, d_I, sizeof(double) * c->P * n_ch, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && st == NLTE_OK && xy)
+        e = hipMemcpyAsync(xy, d_xy, sizeof(double) * c->P * 2, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(d_I);
+    dfree(d_xy);
+    if (st) return st;
+    if (e != hipSuccess) return fail(c, NLTE_E_HIP, std::string("image: ") + hipGetErrorString(e));
+    return NLTE_OK;
 }
 
 }  // extern "C"

@@ -87,6 +87,22 @@ struct SolveArgs {
     unsigned long long *work_counter;
 };
 
+// Image of the model along one ray direction (see image.hip).
+struct ImageArgs {
+    const CellRec *cell;
+    const void *lc;          // [P][n_lines] double2 (kappa, S), FP64
+    const int64_t *roff;
+    const int32_t *rcells;
+    const double *dir;
+    const int32_t *anti;
+    const double *v_ch;      // [n_ch] channel velocities [cm/s]
+    double *I;               // [P][n_ch]
+    double f_sub;
+    double I_in;             // CMB intensity at the line centre
+    int64_t P;
+    int n_rays, n_lines, line, ray, n_ch;
+};
+
 // Ng acceleration: the last M iterates, newest first.
 constexpr int kNgMaxM = 8;
 constexpr int kNgMaxSums = (kNgMaxM - 2) * (kNgMaxM - 1) / 2 + (kNgMaxM - 2);
@@ -216,6 +232,10 @@ struct nlte_ctx {
     int32_t *h_active = nullptr;         // pinned
     int64_t *d_maser = nullptr;
 
+    // imaging: channel velocities
+    double *d_vch = nullptr;
+    int vch_cap = 0;
+
     // Ng acceleration: ring of the last M iterates and per-model work arrays
     double *d_ng_hist = nullptr;     // [M][P][n_lev]
     int64_t ng_hist_elems = 0;       // capacity in doubles
@@ -277,6 +297,9 @@ hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double
 int64_t stateq_blocks(int64_t P);
 hipError_t launch_conv_final(const ConvPartial *partials, int64_t n, ConvResult *out,
                              hipStream_t s);
+
+// imaging
+hipError_t launch_image(const ImageArgs &a, double3 e1, double3 e2, double *xy, hipStream_t s);
 
 // Ng acceleration
 int ng_chunks();
