@@ -107,6 +107,19 @@ def _rel_err(p, ref, ntot):
     return float(np.max(2 * np.abs(a - b) / (np.abs(a) + np.abs(b))))
 
 
+def training_factory(args, make):
+    """Single training models of the measured workload's family, by seed (None: no warm
+    start for this workload)."""
+    from synth import configs
+    if args.workload == "discs":
+        return (lambda sd: configs.disc_model(sd)), 100
+    if args.workload == "batch256":
+        return None, 0
+    if args.points is None:
+        return (lambda sd: make(seed=sd)), 101
+    return (lambda sd: make(n_points=args.points, seed=sd)), 101
+
+
 def train_warm_start(s, w, make, args, dev):
     """Network for the warm start, trained on converged populations of other seeds of the
     same workload family (never the measured model)."""
@@ -115,12 +128,12 @@ def train_warm_start(s, w, make, args, dev):
     from paper_1912_08445_amd import warmstart
     from paper_1912_08445_amd.binding import Solver
     t0 = time.perf_counter()
-    seeds = [101 + i for i in range(args.train_models)]
+    factory, seed0 = training_factory(args, make)
+    seeds = [seed0 + i for i in range(args.train_models)]
 
     def model(sd):
-        wt = make(seed=sd) if args.points is None else make(n_points=args.points, seed=sd)
         st = Solver(0)
-        st.setup(wt, precision="fp64")
+        st.setup(factory(sd), precision="fp64")
         return st
 
     # one training model resident at a time: features first (for the standardisation),
@@ -139,7 +152,7 @@ def train_warm_start(s, w, make, args, dev):
         st.close()
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
-    curve = warmstart.train(s, rows, mean, std, [(6000, 2e-3), (4000, 2e-4)], batch=4096, seed=1)
+    curve = warmstart.train(s, rows, mean, std, [(6000, 2e-3), (4000, 2e-4), (4000, 5e-5)], batch=4096, seed=1)
     t_train = time.perf_counter() - t0
     n_rows = sum(int(r[0].shape[0]) for r in rows)
     s._bench_rows = rows   # kept for the kernel timing of training steps
@@ -166,7 +179,7 @@ def ali_forms(s, w, make, args, dev):
                                       "converged": rep["converged"]},
            "models": w.n_models, "graph": True}
     warm = None
-    if w.n_models == 1 and args.train_models > 0:
+    if training_factory(args, make)[0] is not None and args.train_models > 0:
         res["warm_start"] = train_warm_start(s, w, make, args, dev)
         warm = True
     forms = [("fp64", "lte"), ("fp32", "lte")] + ([("fp64", "warm"), ("fp32", "warm")] if warm else [])
@@ -187,15 +200,24 @@ def ali_forms(s, w, make, args, dev):
         wall, r = best
         err = _rel_err(out.cpu().numpy(), ref, ntot)
         key = f"{prec}_{start}"
+        its = s.model_status()[0]
         res[key] = {"iterations": r["iterations"], "converged": r["converged"], "wall_s": wall,
+                    "model_iterations": {int(k): int(v) for k, v in zip(*np.unique(its, return_counts=True))},
                     "max_rel_diff_vs_fp64_reference": err,
                     "models_converged": r["n_models_converged"],
                     "max_change": [float(c) for c in r["max_change"]]}
         if start == "warm":
             res[key]["used_network"] = r["used_network"]
-        log(f"ALI {key}: {r['iterations']} iterations, {wall * 1e3:.1f} ms, max rel diff vs FP64 "
-            f"reference {err:.2e}, changes {['%.2e' % c for c in r['max_change']]}")
+        log(f"ALI {key}: {r['iterations']} iterations (models: {res[key]['model_iterations']}), "
+            f"{wall * 1e3:.1f} ms, max rel diff vs FP64 reference {err:.2e}, "
+            f"changes {['%.2e' % c for c in r['max_change']]}")
     if warm:
+        # the combination the method is aimed at: FP32 bulk from the learned start against
+        # plain FP64 from LTE, on the same model(s)
+        a, b = res["fp32_warm"], res["fp64_lte"]
+        res["fp32_warm_vs_fp64_lte"] = {"iterations": [a["iterations"], b["iterations"]],
+                                        "wall_ratio": a["wall_s"] / b["wall_s"],
+                                        "max_rel_diff_vs_fp64_reference": a["max_rel_diff_vs_fp64_reference"]}
         res["mlp"] = mlp_timing(s, w, dev)
     s.set_params(precision=args.precision)
     return res
@@ -240,22 +262,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="outflow5", choices=["outflow5", "sphere2", "disc10", "batch256"])
+    ap.add_argument("--workload", default="outflow5", choices=["outflow5", "sphere2", "disc10", "batch256", "discs"])
     ap.add_argument("--autotune", default=None, metavar="CACHE",
                     help="pick the formal-solve launch variant by timing (cache file path)")
     ap.add_argument("--points", type=int, default=None, help="override the point count")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ali", action="store_true")
-    ap.add_argument("--train-models", type=int, default=8,
+    ap.add_argument("--train-models", type=int, default=None,
                     help="other seeds of the workload whose converged populations train the warm start "
-                         "(0: no warm start)")
+                         "(0: no warm start; default 48 for discs, else 8)")
     ap.add_argument("--train-sample", type=int, default=20000,
                     help="rows taken from each training model")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (4 launches), "
                          "the calibration kernel for HBM byte counters")
     args = ap.parse_args()
+    if args.train_models is None:
+        args.train_models = 48 if args.workload == "discs" else 8
 
     if args.copy_probe_mib > 0:
         import torch
@@ -281,7 +305,7 @@ def main():
     from synth import configs
 
     make = {"outflow5": configs.outflow5, "sphere2": configs.sphere2, "disc10": configs.disc10,
-            "batch256": configs.batch256}[args.workload]
+            "batch256": configs.batch256, "discs": configs.discs}[args.workload]
     t0 = time.perf_counter()
     if args.points is None:
         w = make()

@@ -12,6 +12,8 @@ batch256    256 models with the physics of outflow5, point counts log-uniform in
             [500, 20000], temperature and density scales log-uniform in [0.3, 3].
 disc10      1,000,000 points in a flared Keplerian disc (R 10..500 AU, H/R = 0.1),
             10-level rotor (9 lines), 192 HEALPix rays (Nside 4).
+discs       16 discs of the disc10 family (seeds 200..215), 8,000 points each, batched,
+            12 HEALPix rays (Nside 1).
 
 Species mass 28 amu and turbulent speed 150 m/s for all of them.
 """
@@ -94,3 +96,18 @@ def disc10(n_points: int = 1_000_000, seed: int = 3) -> Workload:
     m = keplerian_disc(seed, n_points)
     x, w = directions.uniform_grid(31, 4.0)
     return Workload("disc10", m, species.linear_rotor(10), directions.healpix_ring(4), x, w)
+
+
+def discs(n_models: int = 16, n_points: int = 8000, seed0: int = 200, nside: int = 1) -> Workload:
+    models = [keplerian_disc(seed0 + i, n_points) for i in range(n_models)]
+    offs, merged = concat_models(models)
+    x, w = directions.uniform_grid(31, 4.0)
+    return Workload("discs", merged, species.linear_rotor(10), directions.healpix_ring(nside), x, w,
+                    offsets=offs)
+
+
+def disc_model(seed: int, n_points: int = 8000, nside: int = 1) -> Workload:
+    """One disc of the `discs` family (for training the warm start on other seeds)."""
+    m = keplerian_disc(seed, n_points)
+    x, w = directions.uniform_grid(31, 4.0)
+    return Workload("disc", m, species.linear_rotor(10), directions.healpix_ring(nside), x, w)
