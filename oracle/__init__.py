@@ -70,6 +70,7 @@ def lib():
         L.or_walk_all.argtypes = [C.c_void_p, _lp, C.c_void_p]
         L.or_walk_all.restype = C.c_int64
         L.or_features.argtypes = [C.c_void_p, _dp]
+        L.or_formal_solve_band.argtypes = [C.c_void_p, _dp, C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -206,6 +207,21 @@ class Oracle:
         Ls = np.zeros((n, self.n_lines))
         self._L.or_formal_solve(self.c, pops, n, selp, J, Je, Ls)
         return J, Je, Ls
+
+    def formal_solve_band(self, pops, sel=None):
+        """Band ALO of width one node: J, Jeff, L as formal_solve, plus Jb (J without the
+        band's share), Ld (diagonal with the neighbours' interpolated part) and Ln
+        [n][n_lines][n_rays] (coupling to the first cell of the walk along each ray)."""
+        pops = _f64(pops)
+        if sel is None:
+            n, selp = self.P, None
+        else:
+            sel_arr = np.ascontiguousarray(sel, dtype=np.int64)
+            n, selp = sel_arr.shape[0], sel_arr.ctypes.data
+        out = [np.zeros((n, self.n_lines)) for _ in range(5)]
+        Ln = np.zeros((n, self.n_lines, self.n_rays))
+        self._L.or_formal_solve_band(self.c, pops, n, selp, *out, Ln)
+        return (*out, Ln)
 
     def stateq(self, pops_old, J, Jeff, L):
         out = np.zeros((self.P, self.n_lev))

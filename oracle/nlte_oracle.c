@@ -810,3 +810,106 @@ void or_features(const or_ctx *c, double *F)
         free(col);
     }
 }
+
+/* ------------------------------------------------------------------ band ALO */
+
+/* or_solve_ray plus the entries (T^-1)_{o,o-1} and (T^-1)_{o,o+1} of the inverse system
+ * matrix (0 where the neighbour node does not exist), from solves with unit right-hand
+ * sides at o-1 and o+1. */
+static void solve_ray_band(int N, const double *z, const double *chi, const double *S, double I_lo,
+                           double I_hi, int o, double tau_floor, double *u_o, double *lam_o,
+                           double *ueff_o, double *tm, double *tp)
+{
+    or_solve_ray(N, z, chi, S, I_lo, I_hi, o, tau_floor, u_o, lam_o, ueff_o, NULL);
+    *tm = *tp = 0.0;
+    if (N == 1) return;
+    double *u = malloc(sizeof(double) * N), *zero = calloc(N, sizeof(double));
+    for (int side = -1; side <= 1; side += 2) {
+        int j = o + side;
+        if (j < 0 || j >= N) continue;
+        /* T u = e_j with no incoming intensity: the source-free system with S = e_j */
+        double *e = calloc(N, sizeof(double));
+        e[j] = 1.0;
+        double uo, lo_, ue_;
+        or_solve_ray(N, z, chi, e, 0.0, 0.0, o, tau_floor, &uo, &lo_, &ue_, u);
+        if (side < 0) *tm = uo; else *tp = uo;
+        free(e);
+    }
+    free(u);
+    free(zero);
+}
+
+/* Band ALO of width one node (Sec. 3.4: the diagonal band of the matrix representation
+ * of the Lambda operator; here the origin node and its neighbour on each side of every
+ * ray pair).  Per selected point and line, besides J, Jeff and L of or_formal_solve:
+ *   Ld     L plus the average of (1 - t)(T^-1)_{o,o+-1}: a neighbour node at fraction t of
+ *          the first segment toward the first cell c of the walk carries the source
+ *          function (1 - t) S_O + t S_c (t = 1 when the neighbour is the cell itself),
+ *   Ln[r]  the average of t (T^-1)_{o,o+-1} for the neighbour node along ray r: the
+ *          coupling to the first cell of the walk along r (0 without one),
+ *   Jb     Jeff minus the average of (T^-1)_{o,o+-1} S_{o+-1}: J without the band's share.
+ * Averages are (2/N_rays) sum over pairs and frequencies with the weights w_n, as for L.
+ * Ln is [n_sel][n_lines][n_rays]. */
+void or_formal_solve_band(const or_ctx *c, const double *pops, int64_t n_sel, const int64_t *sel,
+                          double *J, double *Jeff, double *L, double *Jb, double *Ld, double *Ln)
+{
+    int nl = c->n_lines, nq = c->nq, R = c->n_rays;
+    double norm = 2.0 / (double)R;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_sel; ++s) {
+        int64_t O = sel ? sel[s] : s;
+        double *Js = calloc(nl, sizeof(double)), *Ls = calloc(nl, sizeof(double));
+        double *Es = calloc(nl, sizeof(double)), *Bs = calloc(nl, sizeof(double));
+        double *Ds = calloc(nl, sizeof(double)), *Ns = calloc((size_t)nl * R, sizeof(double));
+        for (int p = 0; p < c->n_pairs; ++p) {
+            int r = c->pair_r[p], rb = c->anti[r];
+            int io;
+            int N = or_pair_nodes(c, pops, O, p, 0, NULL, NULL, NULL, NULL, NULL, &io);
+            double *z = malloc(sizeof(double) * N), *a = malloc(sizeof(double) * N);
+            double *b = malloc(sizeof(double) * N);
+            double *kap = malloc(sizeof(double) * N * nl), *S = malloc(sizeof(double) * N * nl);
+            or_pair_nodes(c, pops, O, p, N, z, a, b, kap, S, &io);
+            /* fractions of the first segments at which the neighbour nodes lie */
+            double tf = 1.0, tb = 1.0;
+            int32_t c1;
+            if (or_walk(c, O, r, &c1, NULL, 1) > 0)
+                tf = 1.0 / n_sub(c->f_sub, 0.0, vproj(c, O, c1, c->dir + 3 * r), c->vw[O], c->vw[c1]);
+            if (or_walk(c, O, rb, &c1, NULL, 1) > 0)
+                tb = 1.0 / n_sub(c->f_sub, 0.0, vproj(c, O, c1, c->dir + 3 * rb), c->vw[O], c->vw[c1]);
+            double *chi = malloc(sizeof(double) * N), *Sl = malloc(sizeof(double) * N);
+            for (int l = 0; l < nl; ++l) {
+                double Ib = or_planck(c->nu[l], c->t_cmb);
+                for (int i = 0; i < N; ++i) Sl[i] = S[i * nl + l];
+                for (int n = 0; n < nq; ++n) {
+                    for (int i = 0; i < N; ++i) {
+                        double x = a[i] * c->qx[n] - b[i];
+                        chi[i] = kap[i * nl + l] * exp(-x * x);
+                    }
+                    double u, lam, ue, tm, tp;
+                    solve_ray_band(N, z, chi, Sl, Ib, Ib, io, c->tau_floor, &u, &lam, &ue, &tm, &tp);
+                    double w = c->qw[n];
+                    Js[l] += w * u;
+                    Ls[l] += w * lam;
+                    Es[l] += w * ue;
+                    double band = 0.0;
+                    if (io > 0) band += tm * Sl[io - 1];
+                    if (io + 1 < N) band += tp * Sl[io + 1];
+                    Bs[l] += w * (ue - band);
+                    Ds[l] += w * (lam + (1.0 - tb) * tm + (1.0 - tf) * tp);
+                    Ns[(size_t)l * R + r] += w * tf * tp;
+                    Ns[(size_t)l * R + rb] += w * tb * tm;
+                }
+            }
+            free(z); free(a); free(b); free(kap); free(S); free(chi); free(Sl);
+        }
+        for (int l = 0; l < nl; ++l) {
+            J[s * nl + l] = norm * Js[l];
+            L[s * nl + l] = norm * Ls[l];
+            Jeff[s * nl + l] = norm * Es[l];
+            Jb[s * nl + l] = norm * Bs[l];
+            Ld[s * nl + l] = norm * Ds[l];
+            for (int q = 0; q < R; ++q) Ln[((size_t)s * nl + l) * R + q] = norm * Ns[(size_t)l * R + q];
+        }
+        free(Js); free(Ls); free(Es); free(Bs); free(Ds); free(Ns);
+    }
+}

@@ -38,4 +38,6 @@ int or_run_ali(const or_ctx *c, const double *pops_init, double *pops_out, int m
 int64_t or_walk_all(const or_ctx *c, int64_t *off, int32_t *cells);
 
 void or_features(const or_ctx *c, double *F);
+void or_formal_solve_band(const or_ctx *c, const double *pops, int64_t n_sel, const int64_t *sel,
+                          double *J, double *Jeff, double *L, double *Jb, double *Ld, double *Ln);
 #endif
