@@ -72,9 +72,16 @@ typedef struct {
                          combination of successive changes in the fractional populations
                          (uniform weights); points where it is not positive keep the newest
                          iterate.  0 = off, else 3..8 (the paper's default is 4).  0 */
+    int alo_band;     /* 1: band ALO of one node on each side of the origin (Sec. 3.4; see
+                         nlte_formal_solve_band), the coupled rate equations of all points
+                         solved together each iteration, with the local (diagonal) solve
+                         whenever the band's populations are not all positive (Sec. 6.1).
+                         FP64 formal solve whatever the precision; no graph replay.  Needs
+                         use_alo.  0 */
 } nlte_params;
 
-/* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0, ng_every 0. */
+/* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0, ng_every 0,
+ * alo_band 0. */
 void nlte_default_params(nlte_params *p);
 
 typedef struct {
@@ -90,6 +97,7 @@ typedef struct {
     double ms_total;         /* wall time of the iteration loop [ms] */
     int n_ng_steps;          /* Ng extrapolations applied (ng_every > 0) */
     int64_t n_ng_rejected;   /* points that kept the newest iterate in those steps */
+    int n_band;              /* iterations whose populations came from the band ALO (alo_band) */
 } nlte_ali_report;
 
 /* ---------------------------------------------------------------- context */
@@ -221,6 +229,40 @@ nlte_status nlte_stateq(nlte_ctx *ctx, const double *pops_old, const double *J,
 nlte_status nlte_stateq_dev(nlte_ctx *ctx, const double *d_pops_old, const double *d_J,
                             const double *d_Jeff, const double *d_Lstar, double *d_pops_new,
                             uint8_t *d_flags, void *stream);
+
+/*
+ * Band ALO (Sec. 3.4: the diagonal band of the matrix representation of the Lambda
+ * operator), one node on each side of the origin of every ray pair.  With T the pair's
+ * system matrix, (T^-1)_{O,O+-1} is the weight of the neighbour node's source function in
+ * u_O.  A neighbour node at fraction t of the first segment toward the first cell c of the
+ * walk (t = 1 when it is c) carries (1 - t) S_O + t S_c.  Per point and line, averaged over
+ * rays and frequencies like L*:
+ *   Ld [P][n_lines]          L* plus the (1 - t) shares,
+ *   Ln [P][n_lines][n_rays]  the t shares, coupling to the first cell of the walk along
+ *                            each ray (0 without one),
+ *   Jb [P][n_lines]          Jeff minus the band's contribution of the current source
+ *                            functions.
+ * J, Jeff, Lstar as nlte_formal_solve.  All arrays host memory of the caller.  FP64
+ * whatever the precision setting; lines_per_lane above 2 is taken as 2.
+ */
+nlte_status nlte_formal_solve_band(nlte_ctx *ctx, const double *pops, double *J, double *Jeff,
+                                   double *Lstar, double *Jb, double *Ld, double *Ln);
+
+/*
+ * Statistical equilibrium with the band ALO: the rate equations of all points together,
+ * per point as nlte_stateq with L* := Ld and Jeff := Jb, plus for every line (u -> l) and
+ * ray the coupling -A (k_O / k_c) Ln n_u,c of the first cell c in the net downward rate
+ * (k = h nu/4pi (n_l B_lu - n_u B_ul) with pops_old; no coupling where either k is not
+ * positive).  Solved by BiCGSTAB preconditioned with the points' own rate matrices, from
+ * their uncoupled solution, to a weighted relative residual of 1e-13.  If that fails or some
+ * population is not positive and finite, pops_new is the local solve of nlte_stateq with J,
+ * Jeff, Lstar.  *band_used and *solver_iterations (nullable) say which and how many solver
+ * steps ran.  Host arrays; needs use_alo.
+ */
+nlte_status nlte_stateq_band(nlte_ctx *ctx, const double *pops_old, const double *J,
+                             const double *Jeff, const double *Lstar, const double *Jb,
+                             const double *Ld, const double *Ln, double *pops_new, int *band_used,
+                             int *solver_iterations);
 
 /* ---------------------------------------------------------------- ALI */
 

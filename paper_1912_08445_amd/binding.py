@@ -32,6 +32,7 @@ EXPORTS = (
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
     "nlte_get_ray", "nlte_get_order", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_stateq", "nlte_stateq_dev",
+    "nlte_formal_solve_band", "nlte_stateq_band",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
     "nlte_kernel_stats", "nlte_reset_kernel_stats",
     "nlte_default_train_params", "nlte_mlp_param_count", "nlte_features", "nlte_features_dev",
@@ -48,7 +49,8 @@ class Params(C.Structure):
     _fields_ = [("t_cmb", C.c_double), ("f_sub", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("use_alo", C.c_int), ("precision", C.c_int),
                 ("profile", C.c_int), ("use_graph", C.c_int), ("lines_per_lane", C.c_int),
-                ("high_occupancy", C.c_int), ("persistent", C.c_int), ("ng_every", C.c_int)]
+                ("high_occupancy", C.c_int), ("persistent", C.c_int), ("ng_every", C.c_int),
+                ("alo_band", C.c_int)]
 
 
 class AliReport(C.Structure):
@@ -56,7 +58,8 @@ class AliReport(C.Structure):
                 ("max_change", C.c_double * 1024), ("mean_change", C.c_double * 1024),
                 ("n_models_converged", C.c_int64),
                 ("n_fallback", C.c_int64), ("n_kept", C.c_int64), ("n_maser", C.c_int64),
-                ("ms_total", C.c_double), ("n_ng_steps", C.c_int), ("n_ng_rejected", C.c_int64)]
+                ("ms_total", C.c_double), ("n_ng_steps", C.c_int), ("n_ng_rejected", C.c_int64),
+                ("n_band", C.c_int)]
 
 
 class TrainParams(C.Structure):
@@ -109,6 +112,8 @@ def load():
     L.nlte_formal_solve_dev.argtypes = [vp, vp, vp, vp, vp, vp]
     L.nlte_stateq.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.nlte_stateq_dev.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.nlte_formal_solve_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.nlte_stateq_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.nlte_run_ali.argtypes = [vp, vp, vp, C.POINTER(AliReport)]
     L.nlte_run_ali_dev.argtypes = [vp, vp, vp, C.POINTER(AliReport), vp]
     L.nlte_get_model_status.argtypes = [vp, vp, vp, vp]
@@ -311,6 +316,22 @@ class Solver:
         self._chk(self.L.nlte_stateq(self.h, *[_p(a) for a in args], _p(out), _p(flags)))
         return out, flags
 
+    def formal_solve_band(self, pops):
+        """(J, Jeff, L*, Jb, Ld, Ln) of the band ALO (nlte_formal_solve_band)."""
+        pops = _c(pops, np.float64)
+        out = [np.zeros((self.P, self.n_lines)) for _ in range(5)]
+        Ln = np.zeros((self.P, self.n_lines, self.n_rays))
+        self._chk(self.L.nlte_formal_solve_band(self.h, _p(pops), *[_p(a) for a in out], _p(Ln)))
+        return (*out, Ln)
+
+    def stateq_band(self, pops_old, J, Jeff, L, Jb, Ld, Ln):
+        """(populations, band used, solver iterations) of the coupled band-ALO solve."""
+        args = [_c(a, np.float64) for a in (pops_old, J, Jeff, L, Jb, Ld, Ln)]
+        out = np.zeros((self.P, self.n_lev))
+        used, its = C.c_int(), C.c_int()
+        self._chk(self.L.nlte_stateq_band(self.h, *[_p(a) for a in args], _p(out), C.byref(used), C.byref(its)))
+        return out, bool(used.value), its.value
+
     def run_ali(self, pops_init=None):
         out = np.zeros((self.P, self.n_lev))
         rep = AliReport()
@@ -489,4 +510,5 @@ def report_dict(rep, rc):
                 max_change=list(rep.max_change[:min(it, 1024)]),
                 mean_change=list(rep.mean_change[:min(it, 1024)]),
                 n_fallback=rep.n_fallback, n_kept=rep.n_kept, n_maser=rep.n_maser,
-                ms_total=rep.ms_total, n_ng_steps=rep.n_ng_steps, n_ng_rejected=rep.n_ng_rejected)
+                ms_total=rep.ms_total, n_ng_steps=rep.n_ng_steps, n_ng_rejected=rep.n_ng_rejected,
+                n_band=rep.n_band)

@@ -456,6 +456,207 @@ nlte_status ensure_ng(nlte_ctx *c)
     return NLTE_OK;
 }
 
+// ------------------------------------------------------------------ band ALO helpers
+
+// Buffers of the band formal solve and the coupled solve for the current model, rays
+// and species, and the first cells of the walks.
+nlte_status ensure_band(nlte_ctx *c)
+{
+    const int64_t P = c->P;
+    const int n = c->n_lev, nl = c->n_lines, R = c->n_rays;
+    const int64_t key = P * 1000003 + (int64_t)n * 1009 + nl * 31 + R;
+    nlte_status st;
+    if (key != c->band_cap_P) {
+        if ((st = dalloc(c, &c->d_first, (size_t)P * R))) return st;
+        if ((st = dalloc(c, &c->d_Jb, (size_t)P * nl))) return st;
+        if ((st = dalloc(c, &c->d_Ld, (size_t)P * nl))) return st;
+        if ((st = dalloc(c, &c->d_Ln, (size_t)P * nl * R))) return st;
+        if ((st = dalloc(c, &c->d_bLU, (size_t)P * n * n))) return st;
+        if ((st = dalloc(c, &c->d_bcpl, (size_t)P * nl * R))) return st;
+        if ((st = dalloc(c, &c->d_bx0, (size_t)P * n))) return st;
+        if ((st = dalloc(c, &c->d_bpiv, (size_t)P * n))) return st;
+        if ((st = dalloc(c, &c->d_bvec, (size_t)P * n * 8))) return st;
+        if ((st = dalloc(c, &c->d_bpart, (size_t)band_dot_blocks(P) * 3))) return st;
+        if ((st = dalloc(c, &c->d_bdot, 3))) return st;
+        if ((st = dalloc(c, &c->d_bbad, 1))) return st;
+        if (!c->h_bdot) HIPCHK(c, hipHostMalloc((void **)&c->h_bdot, sizeof(double) * 3, hipHostMallocDefault));
+        if (!c->h_bbad)
+            HIPCHK(c, hipHostMalloc((void **)&c->h_bbad, sizeof(unsigned long long), hipHostMallocDefault));
+        c->band_cap_P = key;
+        c->first_valid = false;
+    }
+    if (!c->first_valid) {
+        HIPCHK(c, launch_first_cells(c->d_roff, c->d_rcells, P * R, c->d_first, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->first_valid = true;
+    }
+    return NLTE_OK;
+}
+
+// Band formal solve (FP64 whatever the precision setting): J, Jeff, L as the local one plus
+// Jb, Ld, Ln into the context's band buffers.
+nlte_status formal_solve_band_impl(nlte_ctx *c, const double *d_pops, double *d_J, double *d_Jeff, double *d_L,
+                                   hipStream_t s, bool ali)
+{
+    HIPCHK(c, launch_line_coef(c->sp, c->d_cell, d_pops, c->P, 0, c->d_lc, c->d_maser, s));
+    SolveArgs a = solve_args(c, d_J, d_Jeff, d_L);
+    const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
+    if (a.lines_per_wave / ngrp > 2) {   // the band kernel takes one or two lines per lane
+        a.lines_per_wave = ngrp * 2;
+        a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
+        a.n_blocks = c->P * a.groups;
+    }
+    if (ali) a.model_done = c->d_model_done;
+    a.Jb = c->d_Jb;
+    a.Ld = c->d_Ld;
+    a.Ln = c->d_Ln;
+    HIPCHK(c, timed(c, c->st_formal, s, [&] { return launch_formal_solve_band(a, s); }));
+    return NLTE_OK;
+}
+
+// Weighted inner products (a_k, b_k), k < nd, into c->h_bdot (synchronises s).
+nlte_status band_dots(nlte_ctx *c, int nd, const double *a0, const double *b0, const double *a1, const double *b1,
+                      const double *a2, const double *b2, hipStream_t s)
+{
+    DotArgs d{};
+    d.a[0] = a0;
+    d.b[0] = b0;
+    d.a[1] = a1 ? a1 : a0;
+    d.b[1] = b1 ? b1 : b0;
+    d.a[2] = a2 ? a2 : a0;
+    d.b[2] = b2 ? b2 : b0;
+    d.nd = nd;
+    HIPCHK(c, launch_band_dots(d, c->d_cell, c->n_lev, c->P, c->d_bpart, c->d_bdot, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_bdot, c->d_bdot, sizeof(double) * 3, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return NLTE_OK;
+}
+
+// Coupled statistical equilibrium of the band ALO by preconditioned BiCGSTAB (see
+// band.hip); when the local matrices are singular, the solver breaks down or does not
+// converge, or a population is not positive and finite, the band is dropped and the local
+// solve (diagonal ALO) gives the populations (Sec. 6.1).  Leaves the change partials for
+// launch_conv_final.  *used: 1 if the band's populations were taken; *iters: solver steps.
+nlte_status stateq_band_impl(nlte_ctx *c, const double *d_old, const double *d_J, const double *d_Jeff,
+                             const double *d_L, double *d_new, uint8_t *d_flags, hipStream_t s, bool ali, int *used,
+                             int *iters)
+{
+    const int n = c->n_lev;
+    const int64_t N = c->P * n;
+    const double tol = 1e-13;
+    *used = 0;
+    *iters = 0;
+    BandArgs b{};
+    b.Jb = c->d_Jb;
+    b.Ld = c->d_Ld;
+    b.Ln = c->d_Ln;
+    b.first = c->d_first;
+    b.done = ali ? c->d_model_done : nullptr;
+    b.model_of = c->d_model_of;
+    b.LU = c->d_bLU;
+    b.piv = c->d_bpiv;
+    b.cpl = c->d_bcpl;
+    b.x0 = c->d_bx0;
+    b.bad = c->d_bbad;
+    b.P = c->P;
+    b.R = c->n_rays;
+    double *x = c->d_bvec, *r = x + N, *r0 = r + N, *p = r0 + N, *v = p + N, *sv = v + N, *t = sv + N, *w = t + N;
+    HIPCHK(c, launch_fill_u64(c->d_bbad, 1, 0ull, s));
+    HIPCHK(c, launch_band_setup(b, c->sp, c->d_cell, c->d_nh2, c->d_T, d_old, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_bbad, c->d_bbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    bool ok = *c->h_bbad == 0;
+    nlte_status st;
+    if (ok) {
+        // x = K^-1 b; r = K^-1 b - (I + K^-1 C) x = -(K^-1 C) x
+        HIPCHK(c, launch_band_lin(x, 1.0, c->d_bx0, 0.0, c->d_bx0, 0.0, nullptr, N, s));
+        HIPCHK(c, launch_band_apply(b, c->sp, x, w, s));
+        HIPCHK(c, launch_band_lin(r, 1.0, x, -1.0, w, 0.0, nullptr, N, s));
+        HIPCHK(c, launch_band_lin(r0, 1.0, r, 0.0, r, 0.0, nullptr, N, s));
+        HIPCHK(c, launch_band_lin(p, 0.0, r, 0.0, r, 0.0, nullptr, N, s));
+        HIPCHK(c, launch_band_lin(v, 0.0, r, 0.0, r, 0.0, nullptr, N, s));
+        if ((st = band_dots(c, 3, r0, r, r, r, x, x, s))) return st;
+        double rho = 1.0, alpha = 1.0, omega = 1.0, rho1 = c->h_bdot[0];
+        bool conv = !(c->h_bdot[2] > 0.0) || c->h_bdot[1] <= tol * tol * c->h_bdot[2];
+        for (int it = 0; it < 200 && !conv && ok; ++it) {
+            *iters = it + 1;
+            if (!(rho1 != 0.0) || !std::isfinite(rho1)) {
+                ok = false;
+                break;
+            }
+            const double beta = (rho1 / rho) * (alpha / omega);
+            HIPCHK(c, launch_band_lin(p, 1.0, r, beta, p, -beta * omega, v, N, s));
+            HIPCHK(c, launch_band_apply(b, c->sp, p, v, s));
+            if ((st = band_dots(c, 1, r0, v, nullptr, nullptr, nullptr, nullptr, s))) return st;
+            const double sigma = c->h_bdot[0];
+            if (!(sigma != 0.0) || !std::isfinite(sigma)) {
+                ok = false;
+                break;
+            }
+            alpha = rho1 / sigma;
+            HIPCHK(c, launch_band_lin(sv, 1.0, r, -alpha, v, 0.0, nullptr, N, s));
+            if ((st = band_dots(c, 2, sv, sv, x, x, nullptr, nullptr, s))) return st;
+            if (c->h_bdot[0] <= tol * tol * c->h_bdot[1]) {
+                HIPCHK(c, launch_band_lin(x, 1.0, x, alpha, p, 0.0, nullptr, N, s));
+                conv = true;
+                break;
+            }
+            HIPCHK(c, launch_band_apply(b, c->sp, sv, t, s));
+            if ((st = band_dots(c, 2, t, sv, t, t, nullptr, nullptr, s))) return st;
+            if (!(c->h_bdot[1] > 0.0)) {
+                ok = false;
+                break;
+            }
+            omega = c->h_bdot[0] / c->h_bdot[1];
+            HIPCHK(c, launch_band_lin(x, 1.0, x, alpha, p, omega, sv, N, s));
+            HIPCHK(c, launch_band_lin(r, 1.0, sv, -omega, t, 0.0, nullptr, N, s));
+            if ((st = band_dots(c, 3, r0, r, r, r, x, x, s))) return st;
+            rho = rho1;
+            rho1 = c->h_bdot[0];
+            conv = c->h_bdot[1] <= tol * tol * c->h_bdot[2];
+            if (!(omega != 0.0)) ok = false;
+        }
+        ok = ok && conv;
+    }
+    if (ok) {
+        HIPCHK(c, launch_fill_u64(c->d_bbad, 1, 0ull, s));
+        HIPCHK(c, launch_band_check(x, N, c->d_bbad, s));
+        HIPCHK(c, hipMemcpyAsync(c->h_bbad, c->d_bbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        ok = *c->h_bbad == 0;
+    }
+    if (ok) {
+        *used = 1;
+        HIPCHK(c, launch_band_finish(x, d_old, c->d_cell, n, c->P, d_new, d_flags, c->d_partials,
+                                     ali ? c->d_model_done : nullptr, c->d_model_of,
+                                     ali ? c->d_model_change : nullptr, s));
+        return NLTE_OK;
+    }
+    // the band gave no physical populations: the local solve
+    HIPCHK(c, launch_stateq(c->sp, c->d_cell, c->d_nh2, c->d_T, c->P, c->params.use_alo, d_old, d_J, d_Jeff, d_L,
+                            d_new, d_flags, c->d_partials, stateq_blocks(c->P), ali ? c->d_model_done : nullptr,
+                            c->d_model_of, ali ? c->d_model_change : nullptr, s));
+    return NLTE_OK;
+}
+
+// One band-ALO iteration cur -> nxt (not captured: the solver reads scalars back).
+nlte_status iteration_band(nlte_ctx *c, const double *cur, double *nxt, hipStream_t s, int *used)
+{
+    nlte_status st;
+    int iters = 0;
+    HIPCHK(c, launch_fill_u64(c->d_model_change, c->n_models, 0ull, s));
+    HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->d_maser), 1, 0ull, s));
+    HIPCHK(c, launch_fill_u8(reinterpret_cast<uint8_t *>(c->d_active), sizeof(int32_t), 0, s));
+    if ((st = formal_solve_band_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, s, true))) return st;
+    if ((st = stateq_band_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, nxt, c->d_flags, s, true, used, &iters))) return st;
+    HIPCHK(c, launch_conv_final(c->d_partials, stateq_blocks(c->P), c->d_conv, s));
+    HIPCHK(c, launch_model_update(c->n_models, c->d_model_change, c->d_model_done, c->d_model_iters,
+                                  c->d_model_last, c->params.tol, c->d_active, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_conv, c->d_conv, sizeof(ConvResult), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    return NLTE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -475,6 +676,7 @@ void nlte_default_params(nlte_params *p)
     p->high_occupancy = 1;
     p->persistent = 0;
     p->ng_every = 0;
+    p->alo_band = 0;
 }
 
 nlte_status nlte_create(nlte_ctx **out, int hip_device)
@@ -546,6 +748,20 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_model_off);
     dfree(c->d_morton);
     dfree(c->d_vch);
+    dfree(c->d_first);
+    dfree(c->d_Jb);
+    dfree(c->d_Ld);
+    dfree(c->d_Ln);
+    dfree(c->d_bLU);
+    dfree(c->d_bcpl);
+    dfree(c->d_bx0);
+    dfree(c->d_bpiv);
+    dfree(c->d_bvec);
+    dfree(c->d_bpart);
+    dfree(c->d_bdot);
+    dfree(c->d_bbad);
+    if (c->h_bdot) (void)hipHostFree(c->h_bdot);
+    if (c->h_bbad) (void)hipHostFree(c->h_bbad);
     dfree(c->d_ng_hist);
     dfree(c->d_ng_part);
     dfree(c->d_ng_coef);
@@ -881,9 +1097,11 @@ nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
     if (!(p->t_cmb > 0.0) || !(p->f_sub > 0.0) || !(p->tol >= 0.0) || p->max_iter < 1 ||
         p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
         p->lines_per_lane < 0 || p->lines_per_lane > (p->precision == NLTE_PREC_FP32_BULK ? 3 : 2) ||
-        !(p->ng_every == 0 || (p->ng_every >= 3 && p->ng_every <= kNgMaxM)))
+        !(p->ng_every == 0 || (p->ng_every >= 3 && p->ng_every <= kNgMaxM)) ||
+        !(p->alo_band == 0 || (p->alo_band == 1 && p->use_alo)))
         return fail(c, NLTE_E_INVALID_ARG,
-                    "parameter out of range (lines_per_lane: 0..2, 0..3 in the FP32 form; ng_every: 0 or 3..8)");
+                    "parameter out of range (lines_per_lane: 0..2, 0..3 in the FP32 form; ng_every: 0 or 3..8; "
+                    "alo_band: 0, or 1 with use_alo)");
     c->params = *p;
     c->cfg.lpl = p->lines_per_lane;
     c->cfg.high_occupancy = p->high_occupancy ? 1 : 0;
@@ -946,6 +1164,7 @@ nlte_status nlte_trace(nlte_ctx *c)
     if (e2 != hipSuccess) return fail(c, NLTE_E_HIP, std::string("step count: ") + hipGetErrorString(e2));
     drop_graphs(c);
     c->traced = true;
+    c->first_valid = false;
     return NLTE_OK;
 }
 
@@ -1104,7 +1323,9 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
     HIPCHK(c, launch_fill_u8(c->d_model_done, c->n_models, 0, s));
     HIPCHK(c, hipMemsetAsync(c->d_model_iters, 0, sizeof(int32_t) * c->n_models, s));
     double *buf[2] = {c->d_pops_a, c->d_pops_b};
-    const bool graph = c->params.use_graph != 0 && !c->params.profile;
+    const bool band = c->params.alo_band != 0;
+    if (band && (st = ensure_band(c))) return st;
+    const bool graph = c->params.use_graph != 0 && !c->params.profile && !band;
     if (graph) {
         if ((st = ensure_graph(c, 0, buf[0], buf[1]))) return st;
         if ((st = ensure_graph(c, 1, buf[1], buf[0]))) return st;
@@ -1114,11 +1335,15 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
     if (M > 0 && (st = ensure_ng(c))) return st;
     if (M > 0) HIPCHK(c, launch_fill_u64(c->d_ng_rej, 1, 0ull, s));
     const size_t nel = (size_t)c->P * c->n_lev;
-    int it = 0, active = c->n_models, n_ng = 0;
+    int it = 0, active = c->n_models, n_ng = 0, n_band = 0;
     ConvResult last{};
     while (it < c->params.max_iter) {
         const int slot = it & 1;
-        if (graph)
+        if (band) {
+            int used = 0;
+            if ((st = iteration_band(c, buf[slot], buf[slot ^ 1], s, &used))) return st;
+            n_band += used;
+        } else if (graph)
             HIPCHK(c, hipGraphLaunch(c->graph_exec[slot], s));
         else if ((st = enqueue_iteration(c, buf[slot], buf[slot ^ 1], s, false)))
             return st;
@@ -1159,6 +1384,7 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
             rep->n_ng_rejected = (int64_t)rej;
         }
         rep->n_ng_steps = n_ng;
+        rep->n_band = n_band;
         rep->iterations = it;
         rep->converged = active == 0 ? 1 : 0;
         rep->n_models_converged = c->n_models - active;
@@ -1610,6 +1836,59 @@ nlte_status nlte_run_ali_warm(nlte_ctx *c, double *pops_out, nlte_ali_report *re
         rs = fail(c, NLTE_E_HIP, "copy of the populations failed");
     dfree(d_out);
     return rs;
+}
+
+// ------------------------------------------------------------------ band ALO
+
+nlte_status nlte_formal_solve_band(nlte_ctx *c, const double *pops, double *J, double *Jeff, double *Lstar,
+                                   double *Jb, double *Ld, double *Ln)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!pops || !J || !Jeff || !Lstar || !Jb || !Ld || !Ln) return fail(c, NLTE_E_INVALID_ARG, "null pointer");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = ensure_band(c))) return st;
+    const size_t np = sizeof(double) * c->P * c->n_lev, nq = sizeof(double) * c->P * c->n_lines;
+    HIPCHK(c, hipMemcpyAsync(c->d_pops_a, pops, np, hipMemcpyHostToDevice, c->stream));
+    if ((st = formal_solve_band_impl(c, c->d_pops_a, c->d_J, c->d_Jeff, c->d_L, c->stream, false))) return st;
+    HIPCHK(c, hipMemcpyAsync(J, c->d_J, nq, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Jeff, c->d_Jeff, nq, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Lstar, c->d_L, nq, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Jb, c->d_Jb, nq, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Ld, c->d_Ld, nq, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Ln, c->d_Ln, nq * c->n_rays, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NLTE_OK;
+}
+
+nlte_status nlte_stateq_band(nlte_ctx *c, const double *pops_old, const double *J, const double *Jeff,
+                             const double *Lstar, const double *Jb, const double *Ld, const double *Ln,
+                             double *pops_new, int *band_used, int *solver_iterations)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!pops_old || !J || !Jeff || !Lstar || !Jb || !Ld || !Ln || !pops_new)
+        return fail(c, NLTE_E_INVALID_ARG, "null pointer");
+    if (!c->params.use_alo) return fail(c, NLTE_E_STATE, "the band ALO needs use_alo = 1");
+    HIPCHK(c, hipSetDevice(c->device));
+    if ((st = ensure_band(c))) return st;
+    const size_t np = sizeof(double) * c->P * c->n_lev, nq = sizeof(double) * c->P * c->n_lines;
+    HIPCHK(c, hipMemcpyAsync(c->d_pops_a, pops_old, np, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_J, J, nq, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_Jeff, Jeff, nq, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_L, Lstar, nq, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_Jb, Jb, nq, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_Ld, Ld, nq, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_Ln, Ln, nq * c->n_rays, hipMemcpyHostToDevice, c->stream));
+    int used = 0, iters = 0;
+    if ((st = stateq_band_impl(c, c->d_pops_a, c->d_J, c->d_Jeff, c->d_L, c->d_pops_b, c->d_flags, c->stream, false,
+                               &used, &iters)))
+        return st;
+    HIPCHK(c, hipMemcpyAsync(pops_new, c->d_pops_b, np, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (band_used) *band_used = used;
+    if (solver_iterations) *solver_iterations = iters;
+    return NLTE_OK;
 }
 
 // ------------------------------------------------------------------ imaging

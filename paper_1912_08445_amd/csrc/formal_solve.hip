@@ -120,6 +120,8 @@ struct NodeRec {
 // optical-depth step (see elim_step).
 struct HalfState {
     double N, D, Y, Hm;
+    double hd;   // weight h d of the last step (renormalised with the state): the share of the
+    double Sl;   // last eliminated node's source Sl in Y (read by the band operator only)
 };
 
 // e^y for y <= 700 in FP64: y = n ln2 + r with |r| <= ln2/2 (two-part ln2), e^r by its
@@ -185,7 +187,7 @@ __device__ __forceinline__ float profile(float x)
 // with no constant factors; Q = n/(sqrt 2 d), y = y~/(sqrt 2 d), and the factor sqrt 2
 // cancels in every quantity formed at the origin.  RENORM rescales n, d, y~ by the power
 // of two that brings d into [0.5, 1), which is exact.
-template <bool F32, bool RENORM>
+template <bool F32, bool RENORM, bool TRACK = false>
 __device__ __forceinline__ void elim_step(typename Bulk<F32>::T a_t, typename Bulk<F32>::T S_t,
                                           typename Bulk<F32>::T &a_prev, typename Bulk<F32>::T &S_e,
                                           HalfState &st)
@@ -196,6 +198,10 @@ __device__ __forceinline__ void elim_step(typename Bulk<F32>::T a_t, typename Bu
     st.Y = fma((double)S_e, hd, st.Y);
     st.D = fma(Pp, st.N, st.D);
     st.Hm = Pp;
+    if (TRACK) {
+        st.hd = hd;
+        st.Sl = (double)S_e;
+    }
     a_prev = a_t;
     S_e = S_t;
     if (RENORM) {
@@ -203,6 +209,7 @@ __device__ __forceinline__ void elim_step(typename Bulk<F32>::T a_t, typename Bu
         st.N = ldexp(st.N, -e);
         st.D = ldexp(st.D, -e);
         st.Y = ldexp(st.Y, -e);
+        if (TRACK) st.hd = ldexp(st.hd, -e);
     }
 }
 
@@ -211,11 +218,12 @@ template <typename T, int LPL>
 struct LineState {
     HalfState st[LPL];
     T k_cur[LPL], S_e[LPL], chi_cur[LPL];
+    int m_last;   // sub-intervals of the last segment (the one ending at O)
 };
 
 // One recurrence step of all LPL lines: g <- g r, r <- r c (shared), then the linear
 // kappa dz/4 and S of each line and its elimination step.
-template <bool F32, int LPL, bool RENORM>
+template <bool F32, int LPL, bool RENORM, bool TRACK = false>
 __device__ __forceinline__ void recur_step(double &g, double &r, double c, double (&kq)[LPL],
                                            const double (&dkq)[LPL], double (&St)[LPL],
                                            const double (&dS)[LPL], typename Bulk<F32>::T (&a_prev)[LPL],
@@ -227,13 +235,13 @@ __device__ __forceinline__ void recur_step(double &g, double &r, double c, doubl
     for (int l = 0; l < LPL; ++l) {
         kq[l] += dkq[l];
         St[l] += dS[l];
-        elim_step<F32, RENORM>(kq[l] * g, St[l], a_prev[l], ls.S_e[l], ls.st[l]);
+        elim_step<F32, RENORM, TRACK>(kq[l] * g, St[l], a_prev[l], ls.S_e[l], ls.st[l]);
     }
 }
 
 // Half-sweep along ray `ray` from its far end to O for Doppler offset xq of this lane.
 // The result is left in ls.st (one HalfState per line of the lane).
-template <bool F32, int LPL>
+template <bool F32, int LPL, bool TRACK = false>
 __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 * LPL> *rec, int64_t O,
                            const CellRec &cO, int ray, typename Bulk<F32>::T xq, int grp, int line0,
                            int nlw, const double (&ib)[LPL], LineState<typename Bulk<F32>::T, LPL> &ls)
@@ -250,7 +258,12 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
         ls.st[l].D = 1.0;
         ls.st[l].Y = kSqrt2 * ib[l];
         ls.st[l].Hm = 0.0;
+        if (TRACK) {
+            ls.st[l].hd = 0.0;
+            ls.st[l].Sl = 0.0;
+        }
     }
+    if (TRACK) ls.m_last = 1;
     const int64_t base = O * a.n_rays + ray;
     const int64_t beg = a.roff[base];
     const int L = (int)(a.roff[base + 1] - beg);
@@ -365,7 +378,7 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                         const T gq = profile(x_cur + tj * dx) * dzq;
 #pragma unroll
                         for (int l = 0; l < LPL; ++l)
-                            elim_step<F32, true>((ls.k_cur[l] + tj * dk[l]) * gq, S0[l] + tj * dS[l], a_prev[l],
+                            elim_step<F32, true, TRACK>((ls.k_cur[l] + tj * dk[l]) * gq, S0[l] + tj * dS[l], a_prev[l],
                                                  ls.S_e[l], ls.st[l]);
                     }
                     gn = profile(xn);
@@ -404,20 +417,20 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                         const int jint = min(jend, m - 1);
                         int jj = j;
                         for (; jj + 3 < jint; jj += 4) {
-                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
-                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
-                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
-                            recur_step<F32, LPL, true>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false, TRACK>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false, TRACK>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false, TRACK>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, true, TRACK>(g, r, c, kq, dkq, St, dS, a_prev, ls);
                         }
                         // the last 0-3 steps in straight-line code; the elimination step
                         // that follows renormalises, so at most seven steps pass between
                         // renormalisations
                         const int rem = jint - jj;
                         if (rem >= 2) {
-                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
-                            recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false, TRACK>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                            recur_step<F32, LPL, false, TRACK>(g, r, c, kq, dkq, St, dS, a_prev, ls);
                         }
-                        if (rem & 1) recur_step<F32, LPL, false>(g, r, c, kq, dkq, St, dS, a_prev, ls);
+                        if (rem & 1) recur_step<F32, LPL, false, TRACK>(g, r, c, kq, dkq, St, dS, a_prev, ls);
                         travel += mdx * (double)(jint - j);
                         j = jint;
                         if (jend == m) {
@@ -442,12 +455,13 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
 #pragma unroll
             for (int l = 0; l < LPL; ++l) {
                 const T chi_n = kn[l] * gn;
-                elim_step<F32, true>(chi_n * dzq, Sn[l], a_prev[l], ls.S_e[l], ls.st[l]);
+                elim_step<F32, true, TRACK>(chi_n * dzq, Sn[l], a_prev[l], ls.S_e[l], ls.st[l]);
                 ls.k_cur[l] = kn[l];
                 ls.chi_cur[l] = chi_n;
             }
             x_cur = xn;
             g_cur = gn;
+            if (TRACK) ls.m_last = m;
         }
     }
 }
@@ -455,7 +469,7 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
 // All (line, frequency) work of one wave for origin point O and line block w, accumulated
 // over every ray pair and written to J, L*, Jeff.  Points of models that already
 // converged are skipped (their outputs are not needed).
-template <bool F32, int LPL>
+template <bool F32, int LPL, bool BAND = false>
 __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
                                            NodeRec<typename Bulk<F32>::T, 2 * LPL> *rec,
                                            double (*red)[LPL][kWave])
@@ -492,8 +506,12 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
         ib[l] = a.ibdy[line];
     }
     Acc accJ[LPL], accL[LPL], accE[LPL];
+    double accB[LPL], accD[LPL];   // band operator (BAND only): Jb and Ld
 #pragma unroll
-    for (int l = 0; l < LPL; ++l) accJ[l] = accL[l] = accE[l] = 0;
+    for (int l = 0; l < LPL; ++l) {
+        accJ[l] = accL[l] = accE[l] = 0;
+        accB[l] = accD[l] = 0.0;
+    }
     LineState<T, LPL> ls;
     for (int p = 0; p < a.n_pairs; ++p) {
         const int r = a.pair_r[p], rb = a.anti[r];
@@ -503,16 +521,20 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
             const double xq = act ? a.qx[nidx] : 0.0;
             const double wq = act ? a.qw[nidx] : 0.0;
             // u pairs I(n, x) with I(-n, -x): the antipode sweeps at the mirrored offset
-            half_sweep<F32, LPL>(a, rec, O, cO, r, (T)xq, grp, line0, nlw, ib, ls);
-            double Qf[LPL], yf[LPL], Hf[LPL];
+            half_sweep<F32, LPL, BAND>(a, rec, O, cO, r, (T)xq, grp, line0, nlw, ib, ls);
+            double Qf[LPL], yf[LPL], Hf[LPL], hdf[LPL], Sf[LPL];
+            const int mf = BAND ? ls.m_last : 1;
 #pragma unroll
             for (int l = 0; l < LPL; ++l) {
                 const double id = 1.0 / ls.st[l].D;
                 Qf[l] = ls.st[l].N * id;
                 yf[l] = ls.st[l].Y * id;
                 Hf[l] = ls.st[l].Hm;
+                hdf[l] = ls.st[l].hd * id;
+                Sf[l] = ls.st[l].Sl;
             }
-            half_sweep<F32, LPL>(a, rec, O, cO, rb, (T)(-xq), grp, line0, nlw, ib, ls);
+            half_sweep<F32, LPL, BAND>(a, rec, O, cO, rb, (T)(-xq), grp, line0, nlw, ib, ls);
+            double nbf[LPL], nbb[LPL];
 #pragma unroll
             for (int l = 0; l < LPL; ++l) {
                 const double id = 1.0 / ls.st[l].D;
@@ -522,6 +544,46 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
                 accJ[l] += (Acc)(wq * (fma(h, S_O[l], yy) * inv));
                 accL[l] += (Acc)(wq * (h * inv));
                 accE[l] += (Acc)(wq * (yy * inv));
+                if (BAND) {
+                    // (T^-1)_{O, neighbour} on either side: the neighbour's share of y
+                    // over the combine's denominator; a neighbour at fraction 1/m of the
+                    // segment toward the first cell interpolates O's own source by 1 - 1/m
+                    const double tf = hdf[l] * inv, tb = ls.st[l].hd * id * inv;
+                    const double imf = 1.0 / (double)mf, imb = 1.0 / (double)ls.m_last;
+                    accB[l] += wq * (yy * inv - tf * Sf[l] - tb * ls.st[l].Sl);
+                    accD[l] += wq * (h * inv + (1.0 - imf) * tf + (1.0 - imb) * tb);
+                    nbf[l] = wq * tf * imf;
+                    nbb[l] = wq * tb * imb;
+                }
+            }
+            if (BAND) {
+                // couplings to the first cells along r and rb, summed over this wave's
+                // frequencies in a fixed order
+#pragma unroll
+                for (int l = 0; l < LPL; ++l) {
+                    red[0][l][lane] = lact[l] && act ? nbf[l] : 0.0;
+                    red[1][l][lane] = lact[l] && act ? nbb[l] : 0.0;
+                }
+                __syncthreads();
+                if (lane < nlw) {
+                    const int g = lane / LPL, l = lane - g * LPL;
+                    const int n0 = (a.fchunks == 1) ? g * a.n_q : 0;
+                    const int n1 = (a.fchunks == 1) ? n0 + a.n_q : kWave;
+                    double sf = 0.0, sb = 0.0;
+                    for (int i = n0; i < n1; ++i) {
+                        sf += red[0][l][i];
+                        sb += red[1][l][i];
+                    }
+                    const int64_t o = (O * a.n_lines + line0 + lane) * a.n_rays;
+                    if (c == 0) {
+                        a.Ln[o + r] = a.norm * sf;
+                        a.Ln[o + rb] = a.norm * sb;
+                    } else {
+                        a.Ln[o + r] += a.norm * sf;
+                        a.Ln[o + rb] += a.norm * sb;
+                    }
+                }
+                __syncthreads();
             }
         }
     }
@@ -547,6 +609,28 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
         a.J[o] = a.norm * (double)sJ;
         a.L[o] = a.norm * (double)sL;
         a.Jeff[o] = a.norm * (double)sE;
+    }
+    if (BAND) {
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < LPL; ++l) {
+            red[0][l][lane] = lact[l] ? accB[l] : 0.0;
+            red[1][l][lane] = lact[l] ? accD[l] : 0.0;
+        }
+        __syncthreads();
+        if (lane < nlw) {
+            const int g = lane / LPL, l = lane - g * LPL;
+            const int n0 = (a.fchunks == 1) ? g * a.n_q : 0;
+            const int n1 = (a.fchunks == 1) ? n0 + a.n_q : kWave;
+            double sB = 0.0, sD = 0.0;
+            for (int i = n0; i < n1; ++i) {
+                sB += red[0][l][i];
+                sD += red[1][l][i];
+            }
+            const int64_t o = O * a.n_lines + line0 + lane;
+            a.Jb[o] = a.norm * sB;
+            a.Ld[o] = a.norm * sD;
+        }
     }
 }
 
@@ -587,6 +671,34 @@ __global__ __launch_bounds__(64, HIGH ? (LPL == 1 ? 4 : 3) : 1) void k_formal_so
         const int64_t rank = item / a.groups;
         solve_item<F32, LPL>(a, (int64_t)a.order[rank], (int)(item - rank * a.groups), rec, red);
     }
+}
+
+// Band-operator variant of the FP64 grid kernel: also the entries of the inverse system
+// matrix between O and its neighbour nodes (Jb, Ld, Ln of SolveArgs).
+template <int LPL>
+__global__ __launch_bounds__(64, 1) void k_formal_solve_band(SolveArgs a)
+{
+    __shared__ NodeRec<double, 2 * LPL> rec[kWave];
+    __shared__ double red[3][LPL][kWave];
+    const int64_t nb8 = (a.n_blocks + 7) / 8;
+    const int64_t lb = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
+    if (lb >= a.n_blocks) return;
+    const int64_t O = lb / a.groups;
+    solve_item<false, LPL, true>(a, O, (int)(lb - O * a.groups), rec, red);
+}
+
+hipError_t launch_formal_solve_band(const SolveArgs &a, hipStream_t s)
+{
+    if (a.n_blocks == 0) return hipSuccess;
+    const int lpl = a.lines_per_wave / ((a.fchunks == 1 && 2 * a.n_q <= kWave) ? 2 : 1);
+    const int64_t nb8 = (a.n_blocks + 7) / 8;
+    if (lpl == 1)
+        hipLaunchKernelGGL(k_formal_solve_band<1>, dim3((unsigned)(nb8 * 8)), dim3(kWave), 0, s, a);
+    else if (lpl == 2)
+        hipLaunchKernelGGL(k_formal_solve_band<2>, dim3((unsigned)(nb8 * 8)), dim3(kWave), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 template <bool F32, int LPL, bool HIGH>

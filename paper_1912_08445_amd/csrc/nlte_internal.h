@@ -79,12 +79,35 @@ struct SolveArgs {
     int fchunks;             // frequency chunks per wave (n_q > 64), else 1
     int64_t n_blocks;        // work items (P * groups)
     double *J, *Jeff, *L;    // [P][n_lines]
+    double *Jb, *Ld;         // band operator: J without the band's share, its diagonal [P][n_lines]
+    double *Ln;              // band operator: coupling to the first cell per ray [P][n_lines][n_rays]
     // ALI only: points of converged models are skipped (null: solve every point)
     const uint8_t *model_done;
     const int32_t *model_of;
     // persistent form: item order (points by decreasing cost) and the work counter
     const int32_t *order;
     unsigned long long *work_counter;
+};
+
+// Coupled statistical equilibrium of the band ALO (see band.hip).
+struct BandArgs {
+    const double *Jb, *Ld, *Ln;   // band formal-solve outputs
+    const int32_t *first;         // [P][n_rays] first cell of each walk (-1: none)
+    const uint8_t *done;          // converged models (held fixed; null: none)
+    const int32_t *model_of;
+    double *LU;                   // [P][n_lev][n_lev] factors of the points' own rate matrices
+    int32_t *piv;                 // [P][n_lev]
+    double *cpl;                  // [P][n_lines][n_rays] coupling coefficients
+    double *x0;                   // [P][n_lev] uncoupled solution
+    unsigned long long *bad;      // singular local matrices
+    int64_t P;
+    int R;
+};
+
+struct DotArgs {
+    const double *a[3];
+    const double *b[3];
+    int nd;
 };
 
 // Image of the model along one ray direction (see image.hip).
@@ -232,6 +255,17 @@ struct nlte_ctx {
     int32_t *h_active = nullptr;         // pinned
     int64_t *d_maser = nullptr;
 
+    // band ALO: outputs of the band formal solve and the coupled solve's work arrays
+    int32_t *d_first = nullptr;          // [P][n_rays]
+    bool first_valid = false;
+    double *d_Jb = nullptr, *d_Ld = nullptr, *d_Ln = nullptr;
+    double *d_bLU = nullptr, *d_bcpl = nullptr, *d_bx0 = nullptr;
+    int32_t *d_bpiv = nullptr;
+    double *d_bvec = nullptr;            // 8 vectors of [P][n_lev]
+    double *d_bpart = nullptr, *d_bdot = nullptr, *h_bdot = nullptr;
+    unsigned long long *d_bbad = nullptr, *h_bbad = nullptr;
+    int64_t band_cap_P = 0;
+
     // imaging: channel velocities
     double *d_vch = nullptr;
     int vch_cap = 0;
@@ -279,6 +313,7 @@ hipError_t scan_lengths(int64_t *len_then_off, int64_t n, void *tmp, size_t *tmp
 hipError_t launch_line_coef(const SpeciesDev &sp, const CellRec *cell, const double *pops,
                             int64_t P, int fp32, void *lc, int64_t *maser_count, hipStream_t s);
 hipError_t launch_formal_solve(const SolveArgs &a, const SolveConfig &cfg, int fp32, hipStream_t s);
+hipError_t launch_formal_solve_band(const SolveArgs &a, hipStream_t s);
 hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, unsigned long long *point_cost,
                               hipStream_t s);
 hipError_t sort_by_cost(unsigned long long *cost, int32_t *order, int64_t P, hipStream_t s);
@@ -297,6 +332,21 @@ hipError_t launch_stateq(const SpeciesDev &sp, const CellRec *cell, const double
 int64_t stateq_blocks(int64_t P);
 hipError_t launch_conv_final(const ConvPartial *partials, int64_t n, ConvResult *out,
                              hipStream_t s);
+
+// band ALO
+hipError_t launch_first_cells(const int64_t *roff, const int32_t *rcells, int64_t n, int32_t *first, hipStream_t s);
+hipError_t launch_band_setup(const BandArgs &b, const SpeciesDev &sp, const CellRec *cell, const double *nh2,
+                             const double *T, const double *old, hipStream_t s);
+hipError_t launch_band_apply(const BandArgs &b, const SpeciesDev &sp, const double *y, double *w, hipStream_t s);
+int64_t band_dot_blocks(int64_t P);
+hipError_t launch_band_dots(const DotArgs &d, const CellRec *cell, int n, int64_t P, double *part, double *out,
+                            hipStream_t s);
+hipError_t launch_band_lin(double *out, double a, const double *X, double b, const double *Y, double c,
+                           const double *Z, int64_t N, hipStream_t s);
+hipError_t launch_band_check(const double *x, int64_t N, unsigned long long *bad, hipStream_t s);
+hipError_t launch_band_finish(const double *x, const double *old, const CellRec *cell, int n, int64_t P,
+                              double *pops_new, uint8_t *flags, ConvPartial *partials, const uint8_t *done,
+                              const int32_t *model_of, unsigned long long *model_change, hipStream_t s);
 
 // imaging
 hipError_t launch_image(const ImageArgs &a, double3 e1, double3 e2, double *xy, hipStream_t s);
