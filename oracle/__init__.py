@@ -71,6 +71,11 @@ def lib():
         L.or_walk_all.restype = C.c_int64
         L.or_features.argtypes = [C.c_void_p, _dp]
         L.or_formal_solve_band.argtypes = [C.c_void_p, _dp, C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_solve_ray_gen.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int,
+                                       C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_formal_solve_scat.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp]
+        L.or_formal_solve_scat.restype = C.c_int
         _lib = L
     return _lib
 
@@ -98,6 +103,16 @@ def solve_ray(z, chi, S, I_lo, I_hi, o, tau_floor=1e-100, want_all=False):
     if want_all:
         return u.value, lam.value, ue.value, ua
     return u.value, lam.value, ue.value
+
+
+def solve_ray_gen(z, chi, Splus, sigma, I_lo, I_hi, o, own=0.0, tau_floor=1e-100):
+    """Generalised Feautrier solve (Eq. GFE with an isotropic scattering opacity) on
+    explicit nodes: returns (u_o, Lambda_oo, ueff_o, v_o)."""
+    z, chi, Splus, sigma = _f64(z), _f64(chi), _f64(Splus), _f64(sigma)
+    u, lam, ue, v = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    lib().or_solve_ray_gen(z.shape[0], z, chi, Splus, sigma, I_lo, I_hi, int(o), tau_floor, own,
+                           C.byref(u), C.byref(lam), C.byref(ue), C.byref(v))
+    return u.value, lam.value, ue.value, v.value
 
 
 class Oracle:
@@ -136,6 +151,7 @@ class Oracle:
         self.t_cmb = t_cmb
         self.tau_floor = tau_floor
         L.or_set_quadrature(self.c, int(quad_x.shape[0]), _f64(quad_x), _f64(quad_w))
+        self.n_q = int(quad_x.shape[0])
         L.or_set_params(self.c, t_cmb, f_sub, tau_floor, 1 if use_alo else 0)
 
     def __del__(self):
@@ -222,6 +238,48 @@ class Oracle:
         Ln = np.zeros((n, self.n_lines, self.n_rays))
         self._L.or_formal_solve_band(self.c, pops, n, selp, *out, Ln)
         return (*out, Ln)
+
+    def line_frequencies(self):
+        sp = self.species
+        return (sp.energy[sp.line_up] - sp.energy[sp.line_lo]) / 6.62607015e-27
+
+    def scattering_start(self):
+        """Initial J_nu [P][n_lines][n_q] of the scattering iteration: the boundary
+        intensity (CMB at each line's centre) everywhere."""
+        Ib = np.array([planck(nu, self.t_cmb) for nu in self.line_frequencies()])
+        return np.broadcast_to(Ib[None, :, None], (self.P, self.n_lines, self.n_q)).copy()
+
+    def formal_solve_scat(self, pops, chi_sca, Jnu_in, sel=None):
+        """Formal solve with isotropic coherent scattering (chi_sca [P][n_lines], cm^-1)
+        driven by the previous J_nu: returns (J, Jeff, L, Jnu_out [n][n_lines][n_q])."""
+        pops = _f64(pops)
+        if sel is None:
+            n, selp = self.P, None
+        else:
+            sel_arr = np.ascontiguousarray(sel, dtype=np.int64)
+            n, selp = sel_arr.shape[0], sel_arr.ctypes.data
+        J, Je, Ls = (np.zeros((n, self.n_lines)) for _ in range(3))
+        Jnu = np.zeros((n, self.n_lines, self.n_q))
+        rc = self._L.or_formal_solve_scat(self.c, pops, _f64(chi_sca), _f64(Jnu_in), n, selp, J, Je, Ls, Jnu)
+        if rc != 0:
+            raise ValueError("the scattering solve needs an ascending quadrature")
+        return J, Je, Ls, Jnu
+
+    def run_ali_scat(self, chi_sca, pops_init=None, max_iter=50, tol=1e-4):
+        """ALI with scattering: each iteration one formal solve driven by the previous J_nu
+        (starting from scattering_start()), then the statistical equilibrium.  Returns
+        (populations, changes, last J_nu)."""
+        pops = self.lte() if pops_init is None else _f64(pops_init).copy()
+        Jnu = self.scattering_start()
+        ch = []
+        for _ in range(max_iter):
+            J, Je, Ls, Jnu = self.formal_solve_scat(pops, chi_sca, Jnu)
+            new, _ = self.stateq(pops, J, Je, Ls)
+            ch.append(self.rel_change(pops, new)[0])
+            pops = new
+            if ch[-1] < tol:
+                break
+        return pops, np.array(ch), Jnu
 
     def stateq(self, pops_old, J, Jeff, L):
         out = np.zeros((self.P, self.n_lev))

@@ -348,8 +348,22 @@ static int n_sub(double f, double s0, double s1, double w0, double w1)
  * Returns the node count (or the count needed if cap is too small); *io receives the
  * index of O.  kap and S are [node][line].
  */
+static int pair_nodes_src(const or_ctx *c, const double *pops, int64_t O, int pair, int cap,
+                          double *z, double *a, double *b, double *kap, double *S, int64_t *c_lo,
+                          int64_t *c_hi, double *t_hi, int *io);
+
 int or_pair_nodes(const or_ctx *c, const double *pops, int64_t O, int pair, int cap, double *z,
                   double *a, double *b, double *kap, double *S, int *io)
+{
+    return pair_nodes_src(c, pops, O, pair, cap, z, a, b, kap, S, NULL, NULL, NULL, io);
+}
+
+/* As or_pair_nodes; c_lo, c_hi, t_hi (nullable) receive for every node the base cells it
+ * lies between (lower and higher z) and its fraction t of the way from c_lo to c_hi (a
+ * base node is its own c_lo = c_hi with t = 0). */
+static int pair_nodes_src(const or_ctx *c, const double *pops, int64_t O, int pair, int cap,
+                          double *z, double *a, double *b, double *kap, double *S, int64_t *c_lo,
+                          int64_t *c_hi, double *t_hi, int *io)
 {
     int r = c->pair_r[pair], rb = c->anti[r];
     int nl = c->n_lines;
@@ -394,6 +408,10 @@ int or_pair_nodes(const or_ctx *c, const double *pops, int64_t O, int pair, int 
         z[w] = bz[i];
         a[w] = ai;
         b[w] = bi;
+        if (c_lo) {
+            c_lo[w] = c_hi[w] = cell[i];
+            t_hi[w] = 0.0;
+        }
         for (int l = 0; l < nl; ++l) line_coefs(c, pops, cell[i], l, &kap[w * nl + l], &S[w * nl + l]);
         ++w;
         if (i + 1 == nb) break;
@@ -406,6 +424,11 @@ int or_pair_nodes(const or_ctx *c, const double *pops, int64_t O, int pair, int 
                 z[w] = bz[i] + t * (bz[i + 1] - bz[i]);
                 a[w] = ai + t * (a1 - ai);
                 b[w] = bi + t * (b1 - bi);
+                if (c_lo) {
+                    c_lo[w] = cell[i];
+                    c_hi[w] = cell[i + 1];
+                    t_hi[w] = t;
+                }
                 for (int l = 0; l < nl; ++l) {
                     double k0 = kap[(w - j) * nl + l], s0 = S[(w - j) * nl + l];
                     kap[w * nl + l] = k0 + t * (bk[2 * l] - k0);
@@ -912,4 +935,210 @@ void or_formal_solve_band(const or_ctx *c, const double *pops, int64_t n_sel, co
         }
         free(Js); free(Ls); free(Es); free(Bs); free(Ds); free(Ns);
     }
+}
+
+/* ------------------------------------------------------------------ scattering */
+
+/*
+ * Generalised Feautrier equation on a ray pair (Sec. 3.3, Eq. GFE) with an isotropic
+ * scattering opacity (chi^- = 0), so D = d/dtau with dtau = (chi + chi^+) dz, and known
+ * (previous-iteration) right-hand sides: Splus = (eta + Psi^+)/(chi + chi^+) and
+ * sigma = Psi^-/(chi + chi^+) per node:
+ *     u - d^2u/dtau^2 = Splus - d sigma/dtau.
+ * The first-order pair of Eq. RTE2 reads du/dtau = -v + sigma, dv/dtau = Splus - u; with
+ * the half-node fluxes v_{i+1/2} = -(u_{i+1} - u_i)/dt_{i+1/2} + (sigma_i + sigma_{i+1})/2
+ * the interior rows are those of or_solve_ray with
+ *     R_i = Splus_i - (sigma_{i+1} - sigma_{i-1})/(dt_- + dt_+),
+ * and the boundary rows (incoming I_lo along +z at node 0, I_hi along -z at node N-1,
+ * v_0 = I_lo - u_0, v_{N-1} = u_{N-1} - I_hi, half-cell integration of dv/dtau) take
+ *     R_0 = Splus_0 + (2/dt)(I_lo - (sigma_0 + sigma_1)/2),
+ *     R_{N-1} = Splus_{N-1} + (2/dt)(I_hi + (sigma_{N-2} + sigma_{N-1})/2).
+ * With sigma = 0 this is exactly the system of or_solve_ray.
+ * Solved by the Rybicki-Hummer elimination from both ends toward o (F, z from node 0, G, w
+ * from node N-1) and the two-sided combine at o.  Outputs at node o: u_o, Lambda_oo
+ * (diagonal of the inverse), ueff_o (the solution with `own` removed from R_o) and the
+ * flux-like v_o = (I(+z) - I(-z))/2 at o: the half-node fluxes on both sides, whose
+ * differences u_o - u_{o-+1} come from the elimination relations (well conditioned when
+ * the optical depth steps are tiny), interpolated linearly in tau to the node
+ * (v_o = (dt_+ v_{o-1/2} + dt_- v_{o+1/2})/(dt_- + dt_+)); at an end node the boundary
+ * condition gives it, and a single node has v = (I_lo - I_hi)/2.
+ */
+void or_solve_ray_gen(int N, const double *z, const double *chi, const double *Splus,
+                      const double *sigma, double I_lo, double I_hi, int o, double tau_floor,
+                      double own, double *u_o, double *lam_o, double *ueff_o, double *v_o)
+{
+    if (N == 1) {
+        *u_o = 0.5 * (I_lo + I_hi);
+        *lam_o = 0.0;
+        *ueff_o = *u_o;
+        *v_o = 0.5 * (I_lo - I_hi);
+        return;
+    }
+    double *dt = malloc(sizeof(double) * N);
+    double *Ac = calloc(N, sizeof(double)), *Cc = calloc(N, sizeof(double));
+    double *Hc = malloc(sizeof(double) * N), *R = malloc(sizeof(double) * N);
+    double *F = malloc(sizeof(double) * N), *zz = malloc(sizeof(double) * N);
+    double *G = malloc(sizeof(double) * N), *ww = malloc(sizeof(double) * N);
+    for (int i = 0; i + 1 < N; ++i) {
+        double d = 0.5 * (chi[i] + chi[i + 1]) * (z[i + 1] - z[i]);
+        dt[i] = d > tau_floor ? d : tau_floor;
+    }
+    for (int i = 0; i < N; ++i) Hc[i] = 1.0;
+    Cc[0] = 2.0 / (dt[0] * dt[0]);
+    Hc[0] = 1.0 + 2.0 / dt[0];
+    R[0] = Splus[0] + 2.0 / dt[0] * (I_lo - 0.5 * (sigma[0] + sigma[1]));
+    for (int i = 1; i < N - 1; ++i) {
+        Ac[i] = 2.0 / (dt[i - 1] * (dt[i - 1] + dt[i]));
+        Cc[i] = 2.0 / (dt[i] * (dt[i - 1] + dt[i]));
+        R[i] = Splus[i] - (sigma[i + 1] - sigma[i - 1]) / (dt[i - 1] + dt[i]);
+    }
+    Ac[N - 1] = 2.0 / (dt[N - 2] * dt[N - 2]);
+    Hc[N - 1] = 1.0 + 2.0 / dt[N - 2];
+    R[N - 1] = Splus[N - 1] + 2.0 / dt[N - 2] * (I_hi + 0.5 * (sigma[N - 2] + sigma[N - 1]));
+
+    /* Rybicki-Hummer elimination from both ends toward o: u_{i-1} = zz_{i-1} + u_i/(1 + F_{i-1})
+     * below o and u_{i+1} = ww_{i+1} + u_i/(1 + G_{i+1}) above it */
+    for (int i = 0; i < o; ++i) {
+        double q = i > 0 ? Ac[i] * F[i - 1] / (1.0 + F[i - 1]) : 0.0;
+        F[i] = (Hc[i] + q) / Cc[i];
+        zz[i] = (R[i] + (i > 0 ? Ac[i] * zz[i - 1] : 0.0)) / (Cc[i] * (1.0 + F[i]));
+    }
+    for (int i = N - 1; i > o; --i) {
+        double q = i < N - 1 ? Cc[i] * G[i + 1] / (1.0 + G[i + 1]) : 0.0;
+        G[i] = (Hc[i] + q) / Ac[i];
+        ww[i] = (R[i] + (i < N - 1 ? Cc[i] * ww[i + 1] : 0.0)) / (Ac[i] * (1.0 + G[i]));
+    }
+    double den = Hc[o], num = R[o];
+    if (o > 0) {
+        den += Ac[o] * F[o - 1] / (1.0 + F[o - 1]);
+        num += Ac[o] * zz[o - 1];
+    }
+    if (o < N - 1) {
+        den += Cc[o] * G[o + 1] / (1.0 + G[o + 1]);
+        num += Cc[o] * ww[o + 1];
+    }
+    double u = num / den;
+    *u_o = u;
+    *lam_o = 1.0 / den;
+    *ueff_o = (num - own) / den;
+    if (o == 0) {
+        *v_o = I_lo - u;
+    } else if (o == N - 1) {
+        *v_o = u - I_hi;
+    } else {
+        double dm = dt[o - 1], dp = dt[o];
+        /* (u_o - u_{o-1})/dt_- and (u_o - u_{o+1})/dt_+ from the elimination relations */
+        double pb = (u * F[o - 1] / (1.0 + F[o - 1]) - zz[o - 1]) / dm;
+        double pf = (u * G[o + 1] / (1.0 + G[o + 1]) - ww[o + 1]) / dp;
+        double vm = -pb + 0.5 * (sigma[o - 1] + sigma[o]);
+        double vp = pf + 0.5 * (sigma[o] + sigma[o + 1]);
+        *v_o = (dp * vm + dm * vp) / (dm + dp);
+    }
+    free(dt); free(Ac); free(Cc); free(Hc); free(R); free(F); free(zz); free(G); free(ww);
+}
+
+/* J_nu of point q, line l at offset x (in q's line widths, q's frame): linear in x
+ * between the quadrature offsets (ascending), constant beyond the outermost ones. */
+static double jnu_at(const or_ctx *c, const double *Jnu, int64_t q, int l, double x)
+{
+    const double *row = Jnu + ((size_t)q * c->n_lines + l) * c->nq;
+    int nq = c->nq;
+    if (x <= c->qx[0]) return row[0];
+    if (x >= c->qx[nq - 1]) return row[nq - 1];
+    int i = 0;
+    while (c->qx[i + 1] <= x) ++i;
+    double t = (x - c->qx[i]) / (c->qx[i + 1] - c->qx[i]);
+    return row[i] + t * (row[i + 1] - row[i]);
+}
+
+/*
+ * Formal solve with scattering (Sec. 2.1 Eq. RTE, 3.3, 3.4).  The scattering opacity
+ * chi_sca [P][n_lines] (cm^-1) is isotropic and grey over each line's frequencies, and
+ * scatters coherently and isotropically in the comoving frame of each point, so a photon
+ * at offset y (widths, the scatterer's frame) is re-emitted with chi_sca J_nu(y), J_nu the
+ * scatterer's mean intensity there, taken from the previous iteration (Jnu_in
+ * [P][n_lines][n_q], at the quadrature offsets, interpolated by jnu_at).  The pair at
+ * lane offset x joins I(n, x) and I(-n, -x); at a node whose offset is y = a x - b the two
+ * directions see chi_sca J(y) and chi_sca J(-y), so
+ *     Psi^+ = chi_sca (J(y) + J(-y))/2,   Psi^- = chi_sca (J(y) - J(-y))/2,
+ * and with chi_tot = chi_line + chi_sca:  Splus = (chi_line S + Psi^+)/chi_tot,
+ * sigma = Psi^-/chi_tot (both 0 where chi_tot = 0).  Velocity sub-steps interpolate
+ * chi_sca and the J_nu of the segment's end cells linearly in t, at the sub-step's own
+ * offset.  Per selected point and line:
+ *   J     (2/N_rays) sum_pairs sum_n w_n u_o,
+ *   L     (2/N_rays) sum sum w_n Lambda_oo chi_line,o/chi_tot,o     (Eq. ALO),
+ *   Jeff  (2/N_rays) sum sum w_n (u_o - Lambda_oo (chi_line,o/chi_tot,o) S_o),
+ *   Jnu_out[n] = (1/N_rays) sum over pairs of I(n, x_n) + I(-n, x_n), with
+ *         I(n, x) = u(x) + v(x) and I(-n, x) = u(-x) - v(-x) (the mirrored offset).
+ * The quadrature must be ascending (and, as always, symmetric); returns -1 otherwise.
+ */
+int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_sca,
+                         const double *Jnu_in, int64_t n_sel, const int64_t *sel, double *J,
+                         double *Jeff, double *L, double *Jnu_out)
+{
+    int nl = c->n_lines, nq = c->nq;
+    for (int n = 0; n + 1 < nq; ++n)
+        if (!(c->qx[n] < c->qx[n + 1])) return -1;
+    double norm = 2.0 / (double)c->n_rays;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < n_sel; ++s) {
+        int64_t O = sel ? sel[s] : s;
+        double *Js = calloc(nl, sizeof(double)), *Ls = calloc(nl, sizeof(double));
+        double *Es = calloc(nl, sizeof(double));
+        double *Jp = calloc((size_t)nl * nq, sizeof(double)), *Jm = calloc((size_t)nl * nq, sizeof(double));
+        for (int p = 0; p < c->n_pairs; ++p) {
+            int io;
+            int N = pair_nodes_src(c, pops, O, p, 0, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL, &io);
+            double *z = malloc(sizeof(double) * N), *a = malloc(sizeof(double) * N);
+            double *b = malloc(sizeof(double) * N), *th = malloc(sizeof(double) * N);
+            int64_t *clo = malloc(sizeof(int64_t) * N), *chh = malloc(sizeof(int64_t) * N);
+            double *kap = malloc(sizeof(double) * N * nl), *S = malloc(sizeof(double) * N * nl);
+            pair_nodes_src(c, pops, O, p, N, z, a, b, kap, S, clo, chh, th, &io);
+            double *ct = malloc(sizeof(double) * N), *Sp = malloc(sizeof(double) * N);
+            double *sg = malloc(sizeof(double) * N);
+            for (int l = 0; l < nl; ++l) {
+                double Ib = or_planck(c->nu[l], c->t_cmb);
+                for (int n = 0; n < nq; ++n) {
+                    double clO = 0.0, ctO = 0.0;
+                    for (int i = 0; i < N; ++i) {
+                        double y = a[i] * c->qx[n] - b[i];
+                        double cl = kap[i * nl + l] * exp(-y * y);
+                        double t = th[i];
+                        double cs = (1.0 - t) * chi_sca[clo[i] * nl + l] + t * chi_sca[chh[i] * nl + l];
+                        double jp = (1.0 - t) * jnu_at(c, Jnu_in, clo[i], l, y) + t * jnu_at(c, Jnu_in, chh[i], l, y);
+                        double jm = (1.0 - t) * jnu_at(c, Jnu_in, clo[i], l, -y) + t * jnu_at(c, Jnu_in, chh[i], l, -y);
+                        double tot = cl + cs;
+                        ct[i] = tot;
+                        Sp[i] = tot > 0.0 ? (cl * S[i * nl + l] + cs * 0.5 * (jp + jm)) / tot : 0.0;
+                        sg[i] = tot > 0.0 ? cs * 0.5 * (jp - jm) / tot : 0.0;
+                        if (i == io) {
+                            clO = cl;
+                            ctO = tot;
+                        }
+                    }
+                    double own = ctO > 0.0 ? clO * S[io * nl + l] / ctO : 0.0;
+                    double u, lam, ue, v;
+                    or_solve_ray_gen(N, z, ct, Sp, sg, Ib, Ib, io, c->tau_floor, own, &u, &lam, &ue, &v);
+                    double w = c->qw[n];
+                    Js[l] += w * u;
+                    Ls[l] += w * lam * (ctO > 0.0 ? clO / ctO : 0.0);
+                    Es[l] += w * ue;
+                    Jp[(size_t)l * nq + n] += u + v;
+                    Jm[(size_t)l * nq + n] += u - v;
+                }
+            }
+            free(z); free(a); free(b); free(th); free(clo); free(chh); free(kap); free(S);
+            free(ct); free(Sp); free(sg);
+        }
+        for (int l = 0; l < nl; ++l) {
+            J[s * nl + l] = norm * Js[l];
+            L[s * nl + l] = norm * Ls[l];
+            Jeff[s * nl + l] = norm * Es[l];
+            for (int n = 0; n < nq; ++n)
+                Jnu_out[((size_t)s * nl + l) * nq + n] =
+                    (Jp[(size_t)l * nq + n] + Jm[(size_t)l * nq + (nq - 1 - n)]) / (double)c->n_rays;
+        }
+        free(Js); free(Ls); free(Es); free(Jp); free(Jm);
+    }
+    return 0;
 }
