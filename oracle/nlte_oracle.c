@@ -1068,6 +1068,7 @@ static double jnu_at(const or_ctx *c, const double *Jnu, int64_t q, int l, doubl
  *   J     (2/N_rays) sum_pairs sum_n w_n u_o,
  *   L     (2/N_rays) sum sum w_n Lambda_oo chi_line,o/chi_tot,o     (Eq. ALO),
  *   Jeff  (2/N_rays) sum sum w_n (u_o - Lambda_oo (chi_line,o/chi_tot,o) S_o),
+ *         with the share chi_line,o/chi_tot,o taken as 1 where chi_tot,o = 0,
  *   Jnu_out[n] = (1/N_rays) sum over pairs of I(n, x_n) + I(-n, x_n), with
  *         I(n, x) = u(x) + v(x) and I(-n, x) = u(-x) - v(-x) (the mirrored offset).
  * The quadrature must be ascending (and, as always, symmetric); returns -1 otherwise.
@@ -1116,12 +1117,15 @@ int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_
                             ctO = tot;
                         }
                     }
-                    double own = ctO > 0.0 ? clO * S[io * nl + l] / ctO : 0.0;
+                    /* the line's share of O's source; all of it where O has no opacity at all
+                     * (as in the line-only solve) */
+                    double share = ctO > 0.0 ? clO / ctO : 1.0;
+                    double own = share * S[io * nl + l];
                     double u, lam, ue, v;
                     or_solve_ray_gen(N, z, ct, Sp, sg, Ib, Ib, io, c->tau_floor, own, &u, &lam, &ue, &v);
                     double w = c->qw[n];
                     Js[l] += w * u;
-                    Ls[l] += w * lam * (ctO > 0.0 ? clO / ctO : 0.0);
+                    Ls[l] += w * lam * share;
                     Es[l] += w * ue;
                     Jp[(size_t)l * nq + n] += u + v;
                     Jm[(size_t)l * nq + n] += u - v;

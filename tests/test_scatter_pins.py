@@ -29,7 +29,11 @@ def test_generalised_solve_without_sigma_is_the_line_solve(oracle_lib, seed):
 def test_zero_scattering_opacity_gives_the_line_formal_solve(oracle_lib):
     w = configs.outflow5(n_points=120, seed=2, nside=1)
     o = oracle_lib.from_workload(w)
-    pops = o.lte()
+    # strongly perturbed populations: some lines are inverted (masers, zero line opacity)
+    pops = o.lte() * np.random.default_rng(4).uniform(0.3, 3.0, (w.n_points, w.species.n_lev))
+    g = w.species.weight
+    inverted = (pops[:, 1:] / g[1:] > pops[:, :-1] / g[:-1]).any(axis=1)
+    assert inverted.any()
     sel = np.arange(0, 120, 7)
     J0, E0, L0 = o.formal_solve(pops, sel=sel)
     rng = np.random.default_rng(1)
