@@ -264,6 +264,36 @@ nlte_status nlte_stateq_band(nlte_ctx *ctx, const double *pops_old, const double
                              const double *Ld, const double *Ln, double *pops_new, int *band_used,
                              int *solver_iterations);
 
+/*
+ * Scattering (Sec. 2.1 Eq. RTE; Sec. 3.3 Eq. RTE2, GFE).  chi_sca [P][n_lines] (cm^-1, >= 0,
+ * host, copied) is an isotropic scattering opacity, grey over each line's frequencies,
+ * that scatters coherently and isotropically in the comoving frame of each point.  The
+ * formal solve then solves the u-equation of the generalised Feautrier form with
+ * chi^+ = chi_sca, chi^- = 0 and the Psi^+- terms of the mean intensity J_nu of the
+ * previous iteration (the paper's iterative treatment of the coupling), and returns the
+ * new J_nu [P][n_lines][n_q] (at the quadrature offsets, in each point's frame and line
+ * widths) from u and the flux-like v at the origin.  L* and Jeff take the line's share
+ * chi_line/(chi_line + chi_sca) of the origin's source (Eq. ALO).  With scattering set,
+ * nlte_run_ali uses this solve (FP64 whatever the precision setting, not graph-captured),
+ * starting from J_nu = the boundary intensity of each line.  Needs an ascending
+ * quadrature (E_INVALID_ARG otherwise); does not combine with alo_band.  NULL clears it;
+ * nlte_set_species and nlte_set_models clear it too.
+ */
+nlte_status nlte_set_scattering(nlte_ctx *ctx, const double *chi_sca);
+
+/* One formal solve with scattering driven by jnu_in (host arrays, [P][n_lines][n_q]):
+ * J, Jeff, Lstar [P][n_lines] and jnu_out. */
+nlte_status nlte_formal_solve_scat(nlte_ctx *ctx, const double *pops, const double *jnu_in,
+                                   double *J, double *Jeff, double *Lstar, double *jnu_out);
+/* Device-pointer variant on `stream` (hipStream_t; NULL = the context's stream);
+ * jnu_in and jnu_out must not alias. */
+nlte_status nlte_formal_solve_scat_dev(nlte_ctx *ctx, const double *d_pops, const double *d_jnu_in,
+                                       double *d_J, double *d_Jeff, double *d_Lstar,
+                                       double *d_jnu_out, void *stream);
+/* J_nu [P][n_lines][n_q] after the last formal solve of the last nlte_run_ali with
+ * scattering (host copy); E_STATE if there is none. */
+nlte_status nlte_scattering_field(nlte_ctx *ctx, double *jnu);
+
 /* ---------------------------------------------------------------- ALI */
 
 /*

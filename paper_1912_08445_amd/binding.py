@@ -32,7 +32,8 @@ EXPORTS = (
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
     "nlte_get_ray", "nlte_get_order", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_stateq", "nlte_stateq_dev",
-    "nlte_formal_solve_band", "nlte_stateq_band",
+    "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_scattering", "nlte_formal_solve_scat",
+    "nlte_formal_solve_scat_dev", "nlte_scattering_field",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
     "nlte_kernel_stats", "nlte_reset_kernel_stats",
     "nlte_default_train_params", "nlte_mlp_param_count", "nlte_features", "nlte_features_dev",
@@ -114,6 +115,10 @@ def load():
     L.nlte_stateq_dev.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.nlte_formal_solve_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.nlte_stateq_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.nlte_set_scattering.argtypes = [vp, vp]
+    L.nlte_formal_solve_scat.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.nlte_formal_solve_scat_dev.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.nlte_scattering_field.argtypes = [vp, vp]
     L.nlte_run_ali.argtypes = [vp, vp, vp, C.POINTER(AliReport)]
     L.nlte_run_ali_dev.argtypes = [vp, vp, vp, C.POINTER(AliReport), vp]
     L.nlte_get_model_status.argtypes = [vp, vp, vp, vp]
@@ -331,6 +336,32 @@ class Solver:
         used, its = C.c_int(), C.c_int()
         self._chk(self.L.nlte_stateq_band(self.h, *[_p(a) for a in args], _p(out), C.byref(used), C.byref(its)))
         return out, bool(used.value), its.value
+
+    def set_scattering(self, chi_sca=None):
+        """Isotropic coherent scattering opacity [P][n_lines] (cm^-1); None clears it."""
+        if chi_sca is None:
+            self._chk(self.L.nlte_set_scattering(self.h, None))
+            return
+        self._scat = _c(chi_sca, np.float64)
+        self._chk(self.L.nlte_set_scattering(self.h, _p(self._scat)))
+
+    def formal_solve_scat(self, pops, jnu_in):
+        """(J, Jeff, L*, J_nu out) of one formal solve with scattering."""
+        pops, jin = _c(pops, np.float64), _c(jnu_in, np.float64)
+        J, Je, Ls = (np.zeros((self.P, self.n_lines)) for _ in range(3))
+        jout = np.zeros_like(jin)
+        self._chk(self.L.nlte_formal_solve_scat(self.h, _p(pops), _p(jin), _p(J), _p(Je), _p(Ls), _p(jout)))
+        return J, Je, Ls, jout
+
+    def formal_solve_scat_dev(self, pops, jnu_in, J, Jeff, L, jnu_out, stream=None):
+        self._chk(self.L.nlte_formal_solve_scat_dev(self.h, _tp(pops), _tp(jnu_in), _tp(J), _tp(Jeff), _tp(L),
+                                                    _tp(jnu_out), _stream(stream)))
+
+    def scattering_field(self):
+        """J_nu [P][n_lines][n_q] after the last ALI with scattering."""
+        out = np.zeros((self.P, self.n_lines, self.n_q))
+        self._chk(self.L.nlte_scattering_field(self.h, _p(out)))
+        return out
 
     def run_ali(self, pops_init=None):
         out = np.zeros((self.P, self.n_lev))

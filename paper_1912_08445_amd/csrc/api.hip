@@ -657,6 +657,86 @@ nlte_status iteration_band(nlte_ctx *c, const double *cur, double *nxt, hipStrea
     return NLTE_OK;
 }
 
+// ------------------------------------------------------------------ scattering helpers
+
+nlte_status need_scat(nlte_ctx *c)
+{
+    if (!c->scat_on) return fail(c, NLTE_E_STATE, "nlte_set_scattering has not been called");
+    if (!c->q_ascending)
+        return fail(c, NLTE_E_INVALID_ARG, "the scattering solve needs an ascending quadrature");
+    return NLTE_OK;
+}
+
+// Formal solve with scattering (FP64 whatever the precision setting): J, Jeff, L and the new
+// J_nu from the previous one.
+nlte_status formal_solve_scat_impl(nlte_ctx *c, const double *d_pops, const double *d_jin, double *d_J,
+                                   double *d_Jeff, double *d_L, double *d_jout, hipStream_t s, bool ali)
+{
+    HIPCHK(c, launch_line_coef(c->sp, c->d_cell, d_pops, c->P, 0, c->d_lc, c->d_maser, s));
+    ScatArgs a{};
+    a.cell = c->d_cell;
+    a.lc = c->d_lc;
+    a.roff = c->d_roff;
+    a.rcells = c->d_rcells;
+    a.dir = c->d_dir;
+    a.pair_r = c->d_pair_r;
+    a.anti = c->d_anti;
+    a.qx = c->d_qx;
+    a.qw = c->d_qw;
+    a.ibdy = c->d_ibdy;
+    a.chi_sca = c->d_chi_sca;
+    a.Jin = d_jin;
+    a.Jout = d_jout;
+    a.J = d_J;
+    a.Jeff = d_Jeff;
+    a.L = d_L;
+    a.f_sub = c->params.f_sub;
+    a.norm = 2.0 / (double)c->n_rays;
+    a.inv_rays = 1.0 / (double)c->n_rays;
+    a.P = c->P;
+    a.n_rays = c->n_rays;
+    a.n_pairs = c->n_pairs;
+    a.n_q = c->n_q;
+    a.n_lines = c->n_lines;
+    if (ali) {
+        a.model_done = c->d_model_done;
+        a.model_of = c->d_model_of;
+    }
+    HIPCHK(c, timed(c, c->st_formal, s, [&] { return launch_formal_solve_scat(a, s); }));
+    return NLTE_OK;
+}
+
+nlte_status ensure_jnu(nlte_ctx *c)
+{
+    const int64_t n = c->P * c->n_lines * c->n_q;
+    if (n != c->jnu_elems || !c->d_jnu[0]) {
+        nlte_status st;
+        if ((st = dalloc(c, &c->d_jnu[0], (size_t)n)) || (st = dalloc(c, &c->d_jnu[1], (size_t)n))) return st;
+        c->jnu_elems = n;
+    }
+    return NLTE_OK;
+}
+
+// One ALI iteration with scattering, cur -> nxt (launched eagerly: the J_nu buffers
+// alternate).
+nlte_status iteration_scat(nlte_ctx *c, const double *cur, double *nxt, hipStream_t s)
+{
+    nlte_status st;
+    const int jin = c->jnu_last;
+    HIPCHK(c, launch_fill_u64(c->d_model_change, c->n_models, 0ull, s));
+    HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->d_maser), 1, 0ull, s));
+    HIPCHK(c, launch_fill_u8(reinterpret_cast<uint8_t *>(c->d_active), sizeof(int32_t), 0, s));
+    if ((st = formal_solve_scat_impl(c, cur, c->d_jnu[jin], c->d_J, c->d_Jeff, c->d_L, c->d_jnu[jin ^ 1], s, true)))
+        return st;
+    c->jnu_last = jin ^ 1;
+    if ((st = stateq_impl(c, cur, c->d_J, c->d_Jeff, c->d_L, nxt, c->d_flags, c->d_conv, s, true, false))) return st;
+    HIPCHK(c, launch_model_update(c->n_models, c->d_model_change, c->d_model_done, c->d_model_iters,
+                                  c->d_model_last, c->params.tol, c->d_active, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_conv, c->d_conv, sizeof(ConvResult), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_active, c->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    return NLTE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -748,6 +828,9 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_model_off);
     dfree(c->d_morton);
     dfree(c->d_vch);
+    dfree(c->d_chi_sca);
+    dfree(c->d_jnu[0]);
+    dfree(c->d_jnu[1]);
     dfree(c->d_first);
     dfree(c->d_Jb);
     dfree(c->d_Ld);
@@ -893,6 +976,8 @@ nlte_status nlte_set_species(nlte_ctx *c, int n_lev, const double *E, const doub
     c->mass = mass;
     drop_graphs(c);
     c->have_species = true;
+    c->scat_on = false;     // scattering opacities are per line
+    c->jnu_last = -1;
     // line widths and work buffers depend on the species: the model must be set again
     c->have_model = false;
     c->traced = false;
@@ -981,6 +1066,8 @@ nlte_status nlte_set_models(nlte_ctx *c, int n_models, const int64_t *offsets, c
     c->offsets = off;
     c->have_model = true;
     c->traced = false;
+    c->scat_on = false;     // scattering opacities belong to the previous points
+    c->jnu_last = -1;
     drop_graphs(c);
     // point -> model map and per-model convergence state
     std::vector<int32_t> mo(P);
@@ -1086,7 +1173,11 @@ nlte_status nlte_set_quadrature(nlte_ctx *c, int n_q, const double *x, const dou
     c->n_q = n_q;
     c->xq_max = 0.0;
     for (int n = 0; n < n_q; ++n) c->xq_max = std::max(c->xq_max, fabs(x[n]));
+    c->q_ascending = true;
+    for (int n = 0; n + 1 < n_q; ++n)
+        if (!(x[n] < x[n + 1])) c->q_ascending = false;
     c->have_quad = true;
+    c->jnu_last = -1;
     drop_graphs(c);
     return NLTE_OK;
 }
@@ -1324,8 +1415,15 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
     HIPCHK(c, hipMemsetAsync(c->d_model_iters, 0, sizeof(int32_t) * c->n_models, s));
     double *buf[2] = {c->d_pops_a, c->d_pops_b};
     const bool band = c->params.alo_band != 0;
+    const bool scat = c->scat_on;
+    if (band && scat) return fail(c, NLTE_E_INVALID_ARG, "the band ALO does not take scattering");
     if (band && (st = ensure_band(c))) return st;
-    const bool graph = c->params.use_graph != 0 && !c->params.profile && !band;
+    if (scat) {
+        if ((st = need_scat(c)) || (st = ensure_jnu(c))) return st;
+        HIPCHK(c, launch_jnu_start(c->d_ibdy, c->P, c->n_lines, c->n_q, c->d_jnu[0], s));
+        c->jnu_last = 0;
+    }
+    const bool graph = c->params.use_graph != 0 && !c->params.profile && !band && !scat;
     if (graph) {
         if ((st = ensure_graph(c, 0, buf[0], buf[1]))) return st;
         if ((st = ensure_graph(c, 1, buf[1], buf[0]))) return st;
@@ -1343,6 +1441,8 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
             int used = 0;
             if ((st = iteration_band(c, buf[slot], buf[slot ^ 1], s, &used))) return st;
             n_band += used;
+        } else if (scat) {
+            if ((st = iteration_scat(c, buf[slot], buf[slot ^ 1], s))) return st;
         } else if (graph)
             HIPCHK(c, hipGraphLaunch(c->graph_exec[slot], s));
         else if ((st = enqueue_iteration(c, buf[slot], buf[slot ^ 1], s, false)))
@@ -1836,6 +1936,83 @@ nlte_status nlte_run_ali_warm(nlte_ctx *c, double *pops_out, nlte_ali_report *re
         rs = fail(c, NLTE_E_HIP, "copy of the populations failed");
     dfree(d_out);
     return rs;
+}
+
+// ------------------------------------------------------------------ scattering
+
+nlte_status nlte_set_scattering(nlte_ctx *c, const double *chi_sca)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!c->have_species) return fail(c, NLTE_E_STATE, "nlte_set_species has not been called");
+    if (!c->have_model) return fail(c, NLTE_E_STATE, "nlte_set_models has not been called");
+    (void)hipSetDevice(c->device);
+    c->jnu_last = -1;
+    if (!chi_sca) {
+        c->scat_on = false;
+        return NLTE_OK;
+    }
+    const int64_t n = c->P * c->n_lines;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(chi_sca[i] >= 0.0) || !std::isfinite(chi_sca[i]))
+            return fail(c, NLTE_E_INVALID_ARG, "scattering opacities must be finite and >= 0");
+    nlte_status st;
+    if ((st = dalloc(c, &c->d_chi_sca, (size_t)n))) return st;
+    HIPCHK(c, hipMemcpy(c->d_chi_sca, chi_sca, sizeof(double) * n, hipMemcpyHostToDevice));
+    c->scat_on = true;
+    return NLTE_OK;
+}
+
+nlte_status nlte_formal_solve_scat_dev(nlte_ctx *c, const double *d_pops, const double *d_jnu_in, double *d_J,
+                                       double *d_Jeff, double *d_L, double *d_jnu_out, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if ((st = need_scat(c))) return st;
+    if (!d_pops || !d_jnu_in || !d_J || !d_Jeff || !d_L || !d_jnu_out)
+        return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    if (d_jnu_in == d_jnu_out) return fail(c, NLTE_E_INVALID_ARG, "jnu_in and jnu_out must differ");
+    (void)hipSetDevice(c->device);
+    hipStream_t s = pick(c, stream);
+    HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->d_maser), 1, 0ull, s));
+    return formal_solve_scat_impl(c, d_pops, d_jnu_in, d_J, d_Jeff, d_L, d_jnu_out, s, false);
+}
+
+nlte_status nlte_formal_solve_scat(nlte_ctx *c, const double *pops, const double *jnu_in, double *J, double *Jeff,
+                                   double *Lstar, double *jnu_out)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if ((st = need_scat(c))) return st;
+    if (!pops || !jnu_in || !J || !Jeff || !Lstar || !jnu_out) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    (void)hipSetDevice(c->device);
+    if ((st = ensure_jnu(c))) return st;
+    c->jnu_last = -1;   // the ALI's buffers are used as scratch here
+    const size_t np = sizeof(double) * c->P * c->n_lev, nj = sizeof(double) * c->P * c->n_lines;
+    const size_t nn = sizeof(double) * c->jnu_elems;
+    HIPCHK(c, hipMemcpyAsync(c->d_pops_a, pops, np, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_jnu[0], jnu_in, nn, hipMemcpyHostToDevice, c->stream));
+    if ((st = nlte_formal_solve_scat_dev(c, c->d_pops_a, c->d_jnu[0], c->d_J, c->d_Jeff, c->d_L, c->d_jnu[1],
+                                         nullptr)))
+        return st;
+    HIPCHK(c, hipMemcpyAsync(J, c->d_J, nj, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Jeff, c->d_Jeff, nj, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Lstar, c->d_L, nj, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(jnu_out, c->d_jnu[1], nn, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NLTE_OK;
+}
+
+nlte_status nlte_scattering_field(nlte_ctx *c, double *jnu)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!jnu) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    if (c->jnu_last < 0 || !c->d_jnu[c->jnu_last])
+        return fail(c, NLTE_E_STATE, "no ALI with scattering has run since the last change of inputs");
+    (void)hipSetDevice(c->device);
+    HIPCHK(c, hipMemcpyAsync(jnu, c->d_jnu[c->jnu_last], sizeof(double) * c->jnu_elems, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NLTE_OK;
 }
 
 // ------------------------------------------------------------------ band ALO

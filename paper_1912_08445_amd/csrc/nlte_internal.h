@@ -110,6 +110,27 @@ struct DotArgs {
     int nd;
 };
 
+// Formal solve with scattering (see scatter.hip).
+struct ScatArgs {
+    const CellRec *cell;
+    const void *lc;          // [P][n_lines] double2 (kappa, S), FP64
+    const int64_t *roff;
+    const int32_t *rcells;
+    const double *dir;
+    const int32_t *pair_r, *anti;
+    const double *qx, *qw;   // [n_q], ascending and symmetric
+    const double *ibdy;      // [n_lines]
+    const double *chi_sca;   // [P][n_lines] scattering opacity [cm^-1]
+    const double *Jin;       // [P][n_lines][n_q] previous J_nu
+    double *Jout;            // [P][n_lines][n_q]
+    double *J, *Jeff, *L;    // [P][n_lines]
+    double f_sub, norm, inv_rays;
+    int64_t P;
+    int n_rays, n_pairs, n_q, n_lines;
+    const uint8_t *model_done;   // ALI only (null: solve every point)
+    const int32_t *model_of;
+};
+
 // Image of the model along one ray direction (see image.hip).
 struct ImageArgs {
     const CellRec *cell;
@@ -266,6 +287,14 @@ struct nlte_ctx {
     unsigned long long *d_bbad = nullptr, *h_bbad = nullptr;
     int64_t band_cap_P = 0;
 
+    // scattering: opacity and the ALI's J_nu in two buffers (last one written: jnu_last)
+    double *d_chi_sca = nullptr;         // [P][n_lines]
+    bool scat_on = false;
+    double *d_jnu[2] = {nullptr, nullptr};  // [P][n_lines][n_q] each
+    int64_t jnu_elems = 0;
+    int jnu_last = -1;
+    bool q_ascending = false;
+
     // imaging: channel velocities
     double *d_vch = nullptr;
     int vch_cap = 0;
@@ -350,6 +379,8 @@ hipError_t launch_band_finish(const double *x, const double *old, const CellRec 
 
 // imaging
 hipError_t launch_image(const ImageArgs &a, double3 e1, double3 e2, double *xy, hipStream_t s);
+hipError_t launch_formal_solve_scat(const ScatArgs &a, hipStream_t s);
+hipError_t launch_jnu_start(const double *ibdy, int64_t P, int n_lines, int n_q, double *jnu, hipStream_t s);
 
 // Ng acceleration
 int ng_chunks();
