@@ -698,6 +698,8 @@ nlte_status formal_solve_scat_impl(nlte_ctx *c, const double *d_pops, const doub
     a.n_pairs = c->n_pairs;
     a.n_q = c->n_q;
     a.n_lines = c->n_lines;
+    a.q_uniform = c->q_uniform ? 1 : 0;
+    a.q_inv_h = c->q_inv_h;
     if (ali) {
         a.model_done = c->d_model_done;
         a.model_of = c->d_model_of;
@@ -1176,6 +1178,17 @@ nlte_status nlte_set_quadrature(nlte_ctx *c, int n_q, const double *x, const dou
     c->q_ascending = true;
     for (int n = 0; n + 1 < n_q; ++n)
         if (!(x[n] < x[n + 1])) c->q_ascending = false;
+    // evenly spaced offsets let the scattering solve index the grid directly (it then
+    // checks the interval against the offsets themselves)
+    c->q_uniform = false;
+    if (c->q_ascending && n_q > 1) {
+        const double h = (x[n_q - 1] - x[0]) / (double)(n_q - 1);
+        bool even = true;
+        for (int n = 0; n < n_q; ++n)
+            if (fabs(x[n] - (x[0] + n * h)) > 1e-9 * h) even = false;
+        c->q_uniform = even;
+        c->q_inv_h = 1.0 / h;
+    }
     c->have_quad = true;
     c->jnu_last = -1;
     drop_graphs(c);

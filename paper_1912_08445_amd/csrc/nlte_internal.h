@@ -125,8 +125,10 @@ struct ScatArgs {
     double *Jout;            // [P][n_lines][n_q]
     double *J, *Jeff, *L;    // [P][n_lines]
     double f_sub, norm, inv_rays;
+    double q_inv_h;          // 1 / spacing of an evenly spaced quadrature
     int64_t P;
     int n_rays, n_pairs, n_q, n_lines;
+    int q_uniform;           // 1: evenly spaced quadrature offsets
     const uint8_t *model_done;   // ALI only (null: solve every point)
     const int32_t *model_of;
 };
@@ -294,6 +296,8 @@ struct nlte_ctx {
     int64_t jnu_elems = 0;
     int jnu_last = -1;
     bool q_ascending = false;
+    bool q_uniform = false;          // evenly spaced offsets (spacing 1/q_inv_h)
+    double q_inv_h = 0.0;
 
     // imaging: channel velocities
     double *d_vch = nullptr;

@@ -29,6 +29,7 @@ def _fields(o, w, seed):
 def _check(got, ref, tol=1e-10):
     J, Je, L, Jn = got
     rJ, rJe, rL, rJn = ref
+    assert all(np.all(np.isfinite(a)) for a in got)
     assert rel(J, rJ).max() <= tol and rel(L, rL).max() <= tol
     assert (np.abs(Je - rJe) / np.abs(rJ)).max() <= tol
     assert rel(Jn, rJn).max() <= tol
@@ -65,6 +66,7 @@ def test_zero_scattering_opacity_gives_the_line_formal_solve():
     J0, E0, L0 = s.formal_solve(pops)
     s.set_scattering(np.zeros((w.n_points, w.species.n_lines)))
     J, E, L, _ = s.formal_solve_scat(pops, Jnu)
+    assert np.all(np.isfinite(J)) and np.all(np.isfinite(E)) and np.all(np.isfinite(L))
     assert rel(J, J0).max() < 1e-12 and rel(L, L0).max() < 1e-12
     assert (np.abs(E - E0) / J0).max() < 1e-12
 
