@@ -219,7 +219,75 @@ def ali_forms(s, w, make, args, dev):
                                         "wall_ratio": a["wall_s"] / b["wall_s"],
                                         "max_rel_diff_vs_fp64_reference": a["max_rel_diff_vs_fp64_reference"]}
         res["mlp"] = mlp_timing(s, w, dev)
+    res.update(ali_variants(s, w, out, ref, ntot))
     s.set_params(precision=args.precision)
+    return res
+
+
+def _timed_ali(s, out, runs=3):
+    import torch
+    best = None
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.run_ali_dev(None, out)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if best is None or wall < best[0]:
+            best = (wall, r)
+    return best
+
+
+def line_centre_opacity(s, w):
+    """Median over points of each line's centre opacity with LTE populations [cm^-1]
+    (an input scale for the scattering opacity)."""
+    import numpy as np
+    h, c, kb = 6.62607015e-27, 2.99792458e10, 1.380649e-16
+    sp = w.species
+    pops = s.lte()
+    nu = (sp.energy[sp.line_up] - sp.energy[sp.line_lo]) / h
+    bul = sp.line_A * c ** 2 / (2 * h * nu ** 3)
+    blu = sp.weight[sp.line_up] / sp.weight[sp.line_lo] * bul
+    vw = np.sqrt(2 * kb * w.model.temperature / (sp.mass) + w.model.v_turb ** 2)
+    kchi = h * nu / (4 * np.pi) * (pops[:, sp.line_lo] * blu - pops[:, sp.line_up] * bul)
+    return np.median(kchi / (np.sqrt(np.pi) * nu * vw[:, None] / c), axis=0)
+
+
+def ali_variants(s, w, out, ref, ntot):
+    """FP64 from LTE with Ng acceleration (M = 4) and with the band ALO, against the same
+    reference; and the ALI with a grey scattering opacity of half the median line-centre
+    opacity (different physics: its own iterations, wall time and formal-solve time)."""
+    import numpy as np
+    import torch
+    res = {}
+    for key, extra in (("fp64_lte_ng4", {"ng_every": 4}), ("fp64_lte_band", {"alo_band": 1})):
+        s.set_params(precision="fp64", tol=1e-4, max_iter=200, **extra)
+        wall, r = _timed_ali(s, out)
+        err = _rel_err(out.cpu().numpy(), ref, ntot)
+        res[key] = {"iterations": r["iterations"], "converged": r["converged"], "wall_s": wall,
+                    "max_rel_diff_vs_fp64_reference": err, "n_ng_steps": r["n_ng_steps"],
+                    "n_band": r["n_band"], "max_change": [float(c) for c in r["max_change"]]}
+        log(f"ALI {key}: {r['iterations']} iterations, {wall * 1e3:.1f} ms, max rel diff vs FP64 "
+            f"reference {err:.2e}")
+        s.set_params(ng_every=0, alo_band=0)
+    chi = np.broadcast_to(0.5 * line_centre_opacity(s, w), (w.n_points, w.species.n_lines)).copy()
+    s.set_scattering(chi)
+    s.set_params(precision="fp64", tol=1e-4, max_iter=200)
+    wall, r = _timed_ali(s, out)
+    s.set_params(profile=1)
+    s.reset_kernel_stats()
+    s.set_params(max_iter=1, tol=0.0)
+    s.run_ali_dev(None, out)
+    torch.cuda.synchronize()
+    f_ms, f_n = s.kernel_stats("formal_solve")
+    s.set_params(profile=0, max_iter=200, tol=1e-4)
+    s.set_scattering(None)
+    res["fp64_lte_scattering"] = {"chi_sca": "0.5 x median line-centre opacity (LTE) of each line, grey, isotropic",
+                                  "iterations": r["iterations"], "converged": r["converged"], "wall_s": wall,
+                                  "formal_solve_ms": f_ms / f_n,
+                                  "max_change": [float(c) for c in r["max_change"]]}
+    log(f"ALI with scattering: {r['iterations']} iterations, {wall * 1e3:.1f} ms, formal solve "
+        f"{f_ms / f_n:.1f} ms per sweep")
     return res
 
 

@@ -213,7 +213,9 @@ __global__ __launch_bounds__(256) void k_band_finish(const double *__restrict__ 
 {
     __shared__ double s_max[256], s_sum[256];
     __shared__ int64_t s_cnt[256];
+    __shared__ int s_one_model;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (threadIdx.x == 0) s_one_model = block_in_one_model(model_of, P);
     double mx = 0.0, sum = 0.0;
     int64_t cnt = 0;
     if (p < P) {
@@ -230,14 +232,14 @@ __global__ __launch_bounds__(256) void k_band_finish(const double *__restrict__ 
             }
         }
         if (flags) flags[p] = 0;
-        if (model_change != nullptr && cnt > 0)
-            atomicMax(&model_change[model_of[p]], (unsigned long long)__double_as_longlong(mx));
     }
     const int t = threadIdx.x;
     s_max[t] = mx;
     s_sum[t] = sum;
     s_cnt[t] = cnt;
     __syncthreads();
+    if (model_change != nullptr && !s_one_model && cnt > 0)
+        atomicMax(&model_change[model_of[p]], (unsigned long long)__double_as_longlong(mx));
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
             s_max[t] = fmax(s_max[t], s_max[t + w]);
@@ -246,6 +248,9 @@ __global__ __launch_bounds__(256) void k_band_finish(const double *__restrict__ 
         }
         __syncthreads();
     }
+    if (t == 0 && model_change != nullptr && s_one_model && s_cnt[0] > 0)
+        atomicMax(&model_change[model_of[blockIdx.x * (int64_t)blockDim.x]],
+                  (unsigned long long)__double_as_longlong(s_max[0]));
     if (t == 0 && partials) {
         ConvPartial cp;
         cp.max_change = s_max[0];

@@ -329,6 +329,17 @@ struct nlte_ctx {
 
 namespace nlte {
 
+// 1 if every point of this block (indices blockIdx.x * blockDim.x + [0, blockDim.x), cut
+// at P) belongs to one model; models are contiguous index ranges, so the first and the
+// last point decide.  0 for an empty block or without a point-to-model map.
+__device__ inline int block_in_one_model(const int32_t *model_of, int64_t P)
+{
+    const int64_t p0 = blockIdx.x * (int64_t)blockDim.x;
+    if (model_of == nullptr || p0 >= P) return 0;
+    const int64_t p1 = (p0 + blockDim.x < P ? p0 + blockDim.x : P) - 1;
+    return model_of[p0] == model_of[p1];
+}
+
 // Launchers (each enqueues on `stream`; return hipSuccess or the launch error).
 hipError_t launch_setup_points(const double *pos, const double *vel, const double *nh2,
                                const double *T, const double *vturb, const double *X,

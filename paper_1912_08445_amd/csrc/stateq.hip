@@ -64,7 +64,9 @@ __global__ __launch_bounds__(256) void k_stateq(SpeciesDev sp, const CellRec *__
 {
     __shared__ double s_max[256], s_sum[256];
     __shared__ int64_t s_cnt[256], s_fb[256], s_kept[256];
+    __shared__ int s_one_model;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (threadIdx.x == 0) s_one_model = block_in_one_model(model_of, P);
     double mx = 0.0, sum = 0.0;
     int64_t cnt = 0, fb = 0, kept = 0;
     const bool skip = p < P && model_done != nullptr && model_done[model_of[p]];
@@ -99,9 +101,6 @@ __global__ __launch_bounds__(256) void k_stateq(SpeciesDev sp, const CellRec *__
         if (flags) flags[p] = f;
         fb = (f == 1);
         kept = (f == 2);
-        // per-model maximum: non-negative doubles order like their bit patterns
-        if (model_change != nullptr && cnt > 0)
-            atomicMax(&model_change[model_of[p]], (unsigned long long)__double_as_longlong(mx));
     }
     const int t = threadIdx.x;
     s_max[t] = mx;
@@ -110,6 +109,10 @@ __global__ __launch_bounds__(256) void k_stateq(SpeciesDev sp, const CellRec *__
     s_fb[t] = fb;
     s_kept[t] = kept;
     __syncthreads();
+    // per-model maximum (non-negative doubles order like their bit patterns): per point
+    // only where the block straddles a model boundary, else once per block below
+    if (model_change != nullptr && !s_one_model && cnt > 0)
+        atomicMax(&model_change[model_of[p]], (unsigned long long)__double_as_longlong(mx));
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
             s_max[t] = fmax(s_max[t], s_max[t + w]);
@@ -120,6 +123,9 @@ __global__ __launch_bounds__(256) void k_stateq(SpeciesDev sp, const CellRec *__
         }
         __syncthreads();
     }
+    if (t == 0 && model_change != nullptr && s_one_model && s_cnt[0] > 0)
+        atomicMax(&model_change[model_of[blockIdx.x * (int64_t)blockDim.x]],
+                  (unsigned long long)__double_as_longlong(s_max[0]));
     if (t == 0 && partials) {
         ConvPartial cp;
         cp.max_change = s_max[0];
