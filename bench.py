@@ -92,11 +92,29 @@ def cpu_baseline(w, target_s=15.0):
     t0 = time.perf_counter()
     o.formal_solve(pops, sel)
     dt = time.perf_counter() - t0
-    units = n * w.rays.shape[0] * w.species.n_lines * w.quad_x.shape[0]
+    per_point = w.rays.shape[0] * w.species.n_lines * w.quad_x.shape[0]
+    units = n * per_point
+    # one thread on a smaller sample of the same points (about a fifth of the time)
+    n1 = max(1, n // (5 * max(threads, 1)))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.formal_solve(pops, sel[:n1])
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": units / dt, "unit": "point*ray*freq/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} random origin points of {w.n_points} (all {w.rays.shape[0]} rays, "
                       f"{w.species.n_lines} lines x {w.quad_x.shape[0]} frequencies), LTE "
-                      f"populations, formal solve only, {dt:.1f} s wall"}
+                      f"populations, formal solve only, {dt:.1f} s wall",
+            "cpu_model": cpu, "value_1_thread": n1 * per_point / dt1,
+            "sample_1_thread": f"the first {n1} of those points, {dt1:.1f} s wall"}
 
 
 def _rel_err(p, ref, ntot):

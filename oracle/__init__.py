@@ -76,6 +76,7 @@ def lib():
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.or_formal_solve_scat.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp]
         L.or_formal_solve_scat.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -86,6 +87,11 @@ def _f64(a):
 
 def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's loops over origin points."""
+    lib().or_set_threads(int(n))
 
 
 def planck(nu: float, T: float) -> float:

@@ -31,6 +31,10 @@
 
 #include "nlte_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 /* CGS constants (SI-exact values) */
 #define OR_H 6.62607015e-27
 #define OR_KB 1.380649e-16
@@ -1145,4 +1149,14 @@ int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_
         free(Js); free(Ls); free(Es); free(Jp); free(Jm);
     }
     return 0;
+}
+
+/* Threads of the OpenMP loops over origin points (timing runs). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

@@ -46,4 +46,5 @@ void or_solve_ray_gen(int N, const double *z, const double *chi, const double *S
 int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_sca,
                          const double *Jnu_in, int64_t n_sel, const int64_t *sel, double *J,
                          double *Jeff, double *L, double *Jnu_out);
+void or_set_threads(int n);
 #endif
