@@ -291,7 +291,8 @@ nlte_status nlte_formal_solve_scat_dev(nlte_ctx *ctx, const double *d_pops, cons
                                        double *d_J, double *d_Jeff, double *d_Lstar,
                                        double *d_jnu_out, void *stream);
 /* J_nu [P][n_lines][n_q] after the last formal solve of the last nlte_run_ali with
- * scattering (host copy); E_STATE if there is none. */
+ * scattering (host copy); E_STATE if there is none.  nlte_formal_solve_scat (host) works
+ * in the same buffers: read the field before calling it. */
 nlte_status nlte_scattering_field(nlte_ctx *ctx, double *jnu);
 
 /* ---------------------------------------------------------------- ALI */
