@@ -464,9 +464,9 @@ nlte_status ensure_band(nlte_ctx *c)
 {
     const int64_t P = c->P;
     const int n = c->n_lev, nl = c->n_lines, R = c->n_rays;
-    const int64_t key = P * 1000003 + (int64_t)n * 1009 + nl * 31 + R;
+    const int64_t dims[4] = {P, n, nl, R};
     nlte_status st;
-    if (key != c->band_cap_P) {
+    if (memcmp(dims, c->band_dims, sizeof dims) != 0) {
         if ((st = dalloc(c, &c->d_first, (size_t)P * R))) return st;
         if ((st = dalloc(c, &c->d_Jb, (size_t)P * nl))) return st;
         if ((st = dalloc(c, &c->d_Ld, (size_t)P * nl))) return st;
@@ -482,7 +482,7 @@ nlte_status ensure_band(nlte_ctx *c)
         if (!c->h_bdot) HIPCHK(c, hipHostMalloc((void **)&c->h_bdot, sizeof(double) * 3, hipHostMallocDefault));
         if (!c->h_bbad)
             HIPCHK(c, hipHostMalloc((void **)&c->h_bbad, sizeof(unsigned long long), hipHostMallocDefault));
-        c->band_cap_P = key;
+        memcpy(c->band_dims, dims, sizeof dims);
         c->first_valid = false;
     }
     if (!c->first_valid) {

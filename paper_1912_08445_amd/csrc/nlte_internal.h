@@ -287,7 +287,7 @@ struct nlte_ctx {
     double *d_bvec = nullptr;            // 8 vectors of [P][n_lev]
     double *d_bpart = nullptr, *d_bdot = nullptr, *h_bdot = nullptr;
     unsigned long long *d_bbad = nullptr, *h_bbad = nullptr;
-    int64_t band_cap_P = 0;
+    int64_t band_dims[4] = {0, 0, 0, 0};   // P, n_lev, n_lines, n_rays the buffers were sized for
 
     // scattering: opacity and the ALI's J_nu in two buffers (last one written: jnu_last)
     double *d_chi_sca = nullptr;         // [P][n_lines]
