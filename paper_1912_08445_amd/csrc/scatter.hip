@@ -25,6 +25,7 @@
 // quadrature offsets from u and the flux-like v at the origin: I(n, x) = u(x) + v(x) and
 // I(-n, x) = u(-x) - v(-x) for the pair representative n.
 #include "nlte_internal.h"
+#include "device_math.h"
 
 namespace nlte {
 
@@ -130,7 +131,7 @@ __device__ inline NodeVal node_val(double Z, double cl, double cs, double S, dou
     NodeVal v;
     v.Z = Z;
     v.chit = cl + cs;
-    const double r = v.chit > 0.0 ? cs / v.chit : 0.0;
+    const double r = cs > 0.0 ? cs * rcp_refined(v.chit) : 0.0;   // chit >= cs > 0
     v.Sp = v.chit > 0.0 ? S + r * (0.5 * (jp + jm) - S) : 0.0;
     v.sg = r * 0.5 * (jm - jp);
     return v;
@@ -212,7 +213,10 @@ __device__ inline void half(const ScatArgs &a, const QGrid &g, int64_t O, const 
             const double mr = ceil(ds / thr);
             m = mr < (double)kMaxSub ? (int)mr : kMaxSub;
         }
-        for (int j = 1; j < m; ++j) step(h, eval_sub(prev, cur, (double)j / (double)m, x, g));
+        if (m > 1) {
+            const double inv_m = 1.0 / (double)m;
+            for (int j = 1; j < m; ++j) step(h, eval_sub(prev, cur, (double)j * inv_m, x, g));
+        }
         step(h, eval_base(cur, x, g));
         prev = cur;
     }
@@ -269,7 +273,7 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
         const double inv = 1.0 / (h + f.n * idf + b.n * idb);
         const double u = (h * f.prev.Sp + yy + sgO) * inv;
         // line part of O's own source, for L* and Jeff (Eq. ALO)
-        const double clO = lcO.x * exp(-(x * x));
+        const double clO = lcO.x * exp_le700(-(x * x));
         const double ratio = f.prev.chit > 0.0 ? clO / f.prev.chit : 1.0;   // all of it without opacity
         accJ += w * u;
         accL += w * (h * inv) * ratio;
