@@ -35,12 +35,15 @@ def _check(got, ref, tol=1e-10):
     assert rel(Jn, rJn).max() <= tol
 
 
-@pytest.mark.parametrize("nq", [31, 80, 1])
+@pytest.mark.parametrize("nq", [31, 80, 1, "gh24"])
 def test_scat_formal_solve_matches_oracle(nq):
     # outflow: velocity sub-steps and four lines; 80 frequencies take two waves; one
-    # frequency is the degenerate grid
+    # frequency is the degenerate grid; Gauss-Hermite offsets are not evenly spaced
     w = configs.outflow5(n_points=300, seed=2, nside=1)
-    w.quad_x, w.quad_w = directions.uniform_grid(nq, 4.0) if nq > 1 else (np.array([0.0]), np.array([1.0]))
+    if nq == "gh24":
+        w.quad_x, w.quad_w = directions.gauss_hermite(24)
+    else:
+        w.quad_x, w.quad_w = directions.uniform_grid(nq, 4.0) if nq > 1 else (np.array([0.0]), np.array([1.0]))
     o = oracle_for(w)
     pops, chi_sca, Jnu = _fields(o, w, 5)
     ref = o.formal_solve_scat(pops, chi_sca, Jnu)
