@@ -1353,7 +1353,8 @@ nlte_status nlte_formal_solve_dev(nlte_ctx *c, const double *d_pops, double *d_J
     if (!d_pops || !d_J || !d_Jeff || !d_L) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
     (void)hipSetDevice(c->device);
     hipStream_t s = pick(c, stream);
-    HIPCHK(c, hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s));
+    // a fill kernel, not a memset node: callers may capture this stream in a graph
+    HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->d_maser), 1, 0ull, s));
     return formal_solve_impl(c, d_pops, d_J, d_Jeff, d_L, s);
 }
 
@@ -1425,7 +1426,8 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
     else
         HIPCHK(c, launch_lte(c->sp, c->d_cell, c->d_T, c->P, c->d_pops_a, s));
     HIPCHK(c, launch_fill_u8(c->d_model_done, c->n_models, 0, s));
-    HIPCHK(c, hipMemsetAsync(c->d_model_iters, 0, sizeof(int32_t) * c->n_models, s));
+    HIPCHK(c, launch_fill_u8(reinterpret_cast<uint8_t *>(c->d_model_iters), sizeof(int32_t) * (int64_t)c->n_models, 0,
+                             s));
     double *buf[2] = {c->d_pops_a, c->d_pops_b};
     const bool band = c->params.alo_band != 0;
     const bool scat = c->scat_on;
