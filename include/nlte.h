@@ -152,6 +152,17 @@ nlte_status nlte_set_models(nlte_ctx *ctx, int n_models, const int64_t *offsets,
 nlte_status nlte_set_rays(nlte_ctx *ctx, int n_rays, const double *dir);
 
 /*
+ * The 12 nside^2 HEALPix pixel centres (Sec. 3.1.3: rays along the centres of HEALPix
+ * pixels; RING scheme of Gorski et al. 2005, ring by ring from the north pole) as the
+ * ray set, nside 1..9 (up to 972 rays); as nlte_set_rays otherwise.
+ */
+nlte_status nlte_set_rays_healpix(nlte_ctx *ctx, int nside);
+
+/* The current ray set: *n_rays (nullable) and, if dir is not NULL, the directions
+ * [n_rays][3] (host memory of the caller).  E_STATE before any rays are set. */
+nlte_status nlte_get_rays(nlte_ctx *ctx, int *n_rays, double *dir);
+
+/*
  * Frequency quadrature (Sec. 3.1.2): offsets x[n] in units of the local line width and
  * weights w[n] against the normalised profile, symmetric (x[n] = -x[N-1-n],
  * w[n] = w[N-1-n] within 1e-12) with sum w = 1 within 1e-12.  1 <= n_q <= 256.

@@ -32,7 +32,7 @@ EXPORTS = (
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
     "nlte_get_ray", "nlte_get_order", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_stateq", "nlte_stateq_dev",
-    "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_scattering", "nlte_formal_solve_scat",
+    "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_rays_healpix", "nlte_get_rays", "nlte_set_scattering", "nlte_formal_solve_scat",
     "nlte_formal_solve_scat_dev", "nlte_scattering_field",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
     "nlte_kernel_stats", "nlte_reset_kernel_stats",
@@ -116,6 +116,8 @@ def load():
     L.nlte_formal_solve_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.nlte_stateq_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.nlte_set_scattering.argtypes = [vp, vp]
+    L.nlte_set_rays_healpix.argtypes = [vp, C.c_int]
+    L.nlte_get_rays.argtypes = [vp, C.POINTER(C.c_int), vp]
     L.nlte_formal_solve_scat.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.nlte_formal_solve_scat_dev.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.nlte_scattering_field.argtypes = [vp, vp]
@@ -336,6 +338,18 @@ class Solver:
         used, its = C.c_int(), C.c_int()
         self._chk(self.L.nlte_stateq_band(self.h, *[_p(a) for a in args], _p(out), C.byref(used), C.byref(its)))
         return out, bool(used.value), its.value
+
+    def set_rays_healpix(self, nside):
+        """HEALPix pixel centres as the ray set (invalidates the trace)."""
+        self._chk(self.L.nlte_set_rays_healpix(self.h, int(nside)))
+        self.n_rays = 12 * int(nside) ** 2
+
+    def get_rays(self):
+        n = C.c_int()
+        self._chk(self.L.nlte_get_rays(self.h, C.byref(n), None))
+        out = np.zeros((n.value, 3))
+        self._chk(self.L.nlte_get_rays(self.h, C.byref(n), _p(out)))
+        return out
 
     def set_scattering(self, chi_sca=None):
         """Isotropic coherent scattering opacity [P][n_lines] (cm^-1); None clears it."""

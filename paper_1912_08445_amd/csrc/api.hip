@@ -1149,9 +1149,52 @@ nlte_status nlte_set_rays(nlte_ctx *c, int n_rays, const double *dir)
     c->n_pairs = (int)pr.size();
     c->anti = anti;
     c->pair_r = pr;
+    c->dir_host.assign(dir, dir + 3 * (size_t)n_rays);
     c->have_rays = true;
     c->traced = false;
     drop_graphs(c);
+    return NLTE_OK;
+}
+
+nlte_status nlte_set_rays_healpix(nlte_ctx *c, int nside)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (nside < 1 || 12 * nside * nside > 1024) return fail(c, NLTE_E_INVALID_ARG, "nside must be in 1..9");
+    // HEALPix RING pixel centres (Gorski et al. 2005), ring by ring from the north pole;
+    // within a ring by increasing azimuth, starting where the RING scheme numbers it
+    const int N = nside;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> dir;
+    dir.reserve(3 * (size_t)12 * N * N);
+    auto push = [&](double z, double phi) {
+        const double st = sqrt(fmax(0.0, (1.0 - z) * (1.0 + z)));
+        dir.push_back(st * cos(phi));
+        dir.push_back(st * sin(phi));
+        dir.push_back(z);
+    };
+    for (int i = 1; i < 4 * N; ++i) {
+        if (i < N) {                      // north polar cap: 4 i pixels
+            const double z = 1.0 - (double)(i * i) / (3.0 * N * N);
+            for (int j = 1; j <= 4 * i; ++j) push(z, (j - 0.5) * (0.5 * pi) / i);
+        } else if (i <= 3 * N) {          // equatorial belt: 4 N pixels, every other ring offset by half
+            const double z = (2 * N - i) * 2.0 / (3.0 * N);
+            const double shift = ((i + N) & 1) ? 1.0 : 0.5;
+            for (int j = 1; j <= 4 * N; ++j) push(z, (j - shift) * pi / (2.0 * N));
+        } else {                          // south polar cap, k-th ring from the south pole
+            const int k = 4 * N - i;
+            const double z = -1.0 + (double)(k * k) / (3.0 * N * N);
+            for (int j = 1; j <= 4 * k; ++j) push(z, (j - 0.5) * (0.5 * pi) / k);
+        }
+    }
+    return nlte_set_rays(c, (int)(dir.size() / 3), dir.data());
+}
+
+nlte_status nlte_get_rays(nlte_ctx *c, int *n_rays, double *dir)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!c->have_rays) return fail(c, NLTE_E_STATE, "no rays have been set");
+    if (n_rays) *n_rays = c->n_rays;
+    if (dir) memcpy(dir, c->dir_host.data(), sizeof(double) * c->dir_host.size());
     return NLTE_OK;
 }
 

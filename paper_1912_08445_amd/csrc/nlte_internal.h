@@ -289,6 +289,8 @@ struct nlte_ctx {
     unsigned long long *d_bbad = nullptr, *h_bbad = nullptr;
     int64_t band_dims[4] = {0, 0, 0, 0};   // P, n_lev, n_lines, n_rays the buffers were sized for
 
+    std::vector<double> dir_host;        // [n_rays][3] as set
+
     // scattering: opacity and the ALI's J_nu in two buffers (last one written: jnu_last)
     double *d_chi_sca = nullptr;         // [P][n_lines]
     bool scat_on = false;
