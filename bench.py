@@ -9,9 +9,12 @@ Workload (default): outflow5 -- 50,000 points in a sphere, 48 HEALPix rays, 5-le
 linear rotor (4 lines x 31 frequencies), radial outflow of 15 km/s.
 
 Prints one JSON line.  `value` is formal-solve throughput in point*ray*frequency per
-second of step time; `roofline` covers the formal-solve kernel (VALU bound, FP64 flops
-per node-frequency step; see the design doc for the count); `cpu_baseline` is the FP64 CPU
-oracle timed on a bounded sample of origin points on this host.
+second of step time; `roofline` covers the formal-solve kernel, which is bound by VALU
+issue: 17 FP64 flops per node-frequency step (profile: x, x^2, exponential, kappa g;
+optical depth: add, multiply; Rybicki-Hummer step: h, T, 1 + D T, reciprocal, Q, y;
+an FMA counted as 2, the exponential and the reciprocal as 1 each) against the
+78.6 TFLOP/s FP64 vector peak; `cpu_baseline` is the FP64 CPU oracle timed on a bounded
+sample of origin points on this host.
 """
 from __future__ import annotations
 
@@ -381,7 +384,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method shards by "
-              "origin point across GPUs but this build measures a single MI355X.", file=sys.stderr)
+              "origin point across GPUs but this benchmark measures a single MI355X.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
