@@ -74,8 +74,8 @@ typedef struct {
                          iterate.  0 = off, else 3..8 (the paper's default is 4).  0 */
     int alo_band;     /* 1: band ALO of one node on each side of the origin (Sec. 3.4; see
                          nlte_formal_solve_band), the coupled rate equations of all points
-                         solved together each iteration, with the local (diagonal) solve
-                         whenever the band's populations are not all positive (Sec. 6.1).
+                         solved together each iteration; a model whose band populations are
+                         not all positive takes the local (diagonal) solve (Sec. 6.1).
                          FP64 formal solve whatever the precision; no graph replay.  Needs
                          use_alo.  0 */
 } nlte_params;
@@ -97,7 +97,8 @@ typedef struct {
     double ms_total;         /* wall time of the iteration loop [ms] */
     int n_ng_steps;          /* Ng extrapolations applied (ng_every > 0) */
     int64_t n_ng_rejected;   /* points that kept the newest iterate in those steps */
-    int n_band;              /* iterations whose populations came from the band ALO (alo_band) */
+    int n_band;              /* iterations in which at least one model kept the band ALO's
+                                populations (alo_band) */
 } nlte_ali_report;
 
 /* ---------------------------------------------------------------- context */
@@ -265,10 +266,12 @@ nlte_status nlte_formal_solve_band(nlte_ctx *ctx, const double *pops, double *J,
  * ray the coupling -A (k_O / k_c) Ln n_u,c of the first cell c in the net downward rate
  * (k = h nu/4pi (n_l B_lu - n_u B_ul) with pops_old; no coupling where either k is not
  * positive).  Solved by BiCGSTAB preconditioned with the points' own rate matrices, from
- * their uncoupled solution, to a weighted relative residual of 1e-13.  If that fails or some
- * population is not positive and finite, pops_new is the local solve of nlte_stateq with J,
- * Jeff, Lstar.  *band_used and *solver_iterations (nullable) say which and how many solver
- * steps ran.  Host arrays; needs use_alo.
+ * their uncoupled solution, to a weighted relative residual of 1e-13.  Per model: a model
+ * with a singular local matrix, or with a population that is not positive and finite,
+ * takes the local solve of nlte_stateq with J, Jeff, Lstar (Sec. 6.1), the others keep the
+ * band's populations; if the solver fails, every model takes the local solve.
+ * *band_used (nullable): the number of models that kept the band's populations;
+ * *solver_iterations (nullable): solver steps.  Host arrays; needs use_alo.
  */
 nlte_status nlte_stateq_band(nlte_ctx *ctx, const double *pops_old, const double *J,
                              const double *Jeff, const double *Lstar, const double *Jb,

@@ -332,12 +332,13 @@ class Solver:
         return (*out, Ln)
 
     def stateq_band(self, pops_old, J, Jeff, L, Jb, Ld, Ln):
-        """(populations, band used, solver iterations) of the coupled band-ALO solve."""
+        """(populations, models that kept the band's populations, solver iterations) of the
+        coupled band-ALO solve."""
         args = [_c(a, np.float64) for a in (pops_old, J, Jeff, L, Jb, Ld, Ln)]
         out = np.zeros((self.P, self.n_lev))
         used, its = C.c_int(), C.c_int()
         self._chk(self.L.nlte_stateq_band(self.h, *[_p(a) for a in args], _p(out), C.byref(used), C.byref(its)))
-        return out, bool(used.value), its.value
+        return out, used.value, its.value
 
     def set_rays_healpix(self, nside):
         """HEALPix pixel centres as the ray set (invalidates the trace)."""

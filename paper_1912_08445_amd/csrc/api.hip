@@ -464,7 +464,7 @@ nlte_status ensure_band(nlte_ctx *c)
 {
     const int64_t P = c->P;
     const int n = c->n_lev, nl = c->n_lines, R = c->n_rays;
-    const int64_t dims[4] = {P, n, nl, R};
+    const int64_t dims[5] = {P, n, nl, R, c->n_models};
     nlte_status st;
     if (memcmp(dims, c->band_dims, sizeof dims) != 0) {
         if ((st = dalloc(c, &c->d_first, (size_t)P * R))) return st;
@@ -479,6 +479,8 @@ nlte_status ensure_band(nlte_ctx *c)
         if ((st = dalloc(c, &c->d_bpart, (size_t)band_dot_blocks(P) * 3))) return st;
         if ((st = dalloc(c, &c->d_bdot, 3))) return st;
         if ((st = dalloc(c, &c->d_bbad, 1))) return st;
+        if ((st = dalloc(c, &c->d_bmodel_bad, (size_t)c->n_models))) return st;
+        c->h_bmodel_bad.assign((size_t)c->n_models, 0);
         if (!c->h_bdot) HIPCHK(c, hipHostMalloc((void **)&c->h_bdot, sizeof(double) * 3, hipHostMallocDefault));
         if (!c->h_bbad)
             HIPCHK(c, hipHostMalloc((void **)&c->h_bbad, sizeof(unsigned long long), hipHostMallocDefault));
@@ -533,10 +535,12 @@ nlte_status band_dots(nlte_ctx *c, int nd, const double *a0, const double *b0, c
 }
 
 // Coupled statistical equilibrium of the band ALO by preconditioned BiCGSTAB (see
-// band.hip); when the local matrices are singular, the solver breaks down or does not
-// converge, or a population is not positive and finite, the band is dropped and the local
-// solve (diagonal ALO) gives the populations (Sec. 6.1).  Leaves the change partials for
-// launch_conv_final.  *used: 1 if the band's populations were taken; *iters: solver steps.
+// band.hip).  The band is dropped per model (Sec. 6.1): a model with a singular local
+// matrix, or whose coupled solution has a population that is not positive and finite,
+// takes the local solve (diagonal ALO) and the other models keep the band's populations;
+// if the coupled solve itself breaks down or does not converge, every model takes the
+// local solve.  Leaves the change partials for launch_conv_final.  *used: models whose
+// populations came from the band; *iters: solver steps.
 nlte_status stateq_band_impl(nlte_ctx *c, const double *d_old, const double *d_J, const double *d_Jeff,
                              const double *d_L, double *d_new, uint8_t *d_flags, hipStream_t s, bool ali, int *used,
                              int *iters)
@@ -558,84 +562,89 @@ nlte_status stateq_band_impl(nlte_ctx *c, const double *d_old, const double *d_J
     b.cpl = c->d_bcpl;
     b.x0 = c->d_bx0;
     b.bad = c->d_bbad;
+    b.model_bad = c->d_bmodel_bad;
     b.P = c->P;
     b.R = c->n_rays;
     double *x = c->d_bvec, *r = x + N, *r0 = r + N, *p = r0 + N, *v = p + N, *sv = v + N, *t = sv + N, *w = t + N;
     HIPCHK(c, launch_fill_u64(c->d_bbad, 1, 0ull, s));
+    HIPCHK(c, launch_fill_u8(c->d_bmodel_bad, c->n_models, 0, s));
     HIPCHK(c, launch_band_setup(b, c->sp, c->d_cell, c->d_nh2, c->d_T, d_old, s));
-    HIPCHK(c, hipMemcpyAsync(c->h_bbad, c->d_bbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    bool ok = *c->h_bbad == 0;
+    HIPCHK(c, launch_band_mask(b, c->n_lines, s));
     nlte_status st;
-    if (ok) {
-        // x = K^-1 b; r = K^-1 b - (I + K^-1 C) x = -(K^-1 C) x
-        HIPCHK(c, launch_band_lin(x, 1.0, c->d_bx0, 0.0, c->d_bx0, 0.0, nullptr, N, s));
-        HIPCHK(c, launch_band_apply(b, c->sp, x, w, s));
-        HIPCHK(c, launch_band_lin(r, 1.0, x, -1.0, w, 0.0, nullptr, N, s));
-        HIPCHK(c, launch_band_lin(r0, 1.0, r, 0.0, r, 0.0, nullptr, N, s));
-        HIPCHK(c, launch_band_lin(p, 0.0, r, 0.0, r, 0.0, nullptr, N, s));
-        HIPCHK(c, launch_band_lin(v, 0.0, r, 0.0, r, 0.0, nullptr, N, s));
-        if ((st = band_dots(c, 3, r0, r, r, r, x, x, s))) return st;
-        double rho = 1.0, alpha = 1.0, omega = 1.0, rho1 = c->h_bdot[0];
-        bool conv = !(c->h_bdot[2] > 0.0) || c->h_bdot[1] <= tol * tol * c->h_bdot[2];
-        for (int it = 0; it < 200 && !conv && ok; ++it) {
-            *iters = it + 1;
-            if (!(rho1 != 0.0) || !std::isfinite(rho1)) {
-                ok = false;
-                break;
-            }
-            const double beta = (rho1 / rho) * (alpha / omega);
-            HIPCHK(c, launch_band_lin(p, 1.0, r, beta, p, -beta * omega, v, N, s));
-            HIPCHK(c, launch_band_apply(b, c->sp, p, v, s));
-            if ((st = band_dots(c, 1, r0, v, nullptr, nullptr, nullptr, nullptr, s))) return st;
-            const double sigma = c->h_bdot[0];
-            if (!(sigma != 0.0) || !std::isfinite(sigma)) {
-                ok = false;
-                break;
-            }
-            alpha = rho1 / sigma;
-            HIPCHK(c, launch_band_lin(sv, 1.0, r, -alpha, v, 0.0, nullptr, N, s));
-            if ((st = band_dots(c, 2, sv, sv, x, x, nullptr, nullptr, s))) return st;
-            if (c->h_bdot[0] <= tol * tol * c->h_bdot[1]) {
-                HIPCHK(c, launch_band_lin(x, 1.0, x, alpha, p, 0.0, nullptr, N, s));
-                conv = true;
-                break;
-            }
-            HIPCHK(c, launch_band_apply(b, c->sp, sv, t, s));
-            if ((st = band_dots(c, 2, t, sv, t, t, nullptr, nullptr, s))) return st;
-            if (!(c->h_bdot[1] > 0.0)) {
-                ok = false;
-                break;
-            }
-            omega = c->h_bdot[0] / c->h_bdot[1];
-            HIPCHK(c, launch_band_lin(x, 1.0, x, alpha, p, omega, sv, N, s));
-            HIPCHK(c, launch_band_lin(r, 1.0, sv, -omega, t, 0.0, nullptr, N, s));
-            if ((st = band_dots(c, 3, r0, r, r, r, x, x, s))) return st;
-            rho = rho1;
-            rho1 = c->h_bdot[0];
-            conv = c->h_bdot[1] <= tol * tol * c->h_bdot[2];
-            if (!(omega != 0.0)) ok = false;
+    // x = K^-1 b; r = K^-1 b - (I + K^-1 C) x = -(K^-1 C) x
+    HIPCHK(c, launch_band_lin(x, 1.0, c->d_bx0, 0.0, c->d_bx0, 0.0, nullptr, N, s));
+    HIPCHK(c, launch_band_apply(b, c->sp, x, w, s));
+    HIPCHK(c, launch_band_lin(r, 1.0, x, -1.0, w, 0.0, nullptr, N, s));
+    HIPCHK(c, launch_band_lin(r0, 1.0, r, 0.0, r, 0.0, nullptr, N, s));
+    HIPCHK(c, launch_band_lin(p, 0.0, r, 0.0, r, 0.0, nullptr, N, s));
+    HIPCHK(c, launch_band_lin(v, 0.0, r, 0.0, r, 0.0, nullptr, N, s));
+    if ((st = band_dots(c, 3, r0, r, r, r, x, x, s))) return st;
+    double rho = 1.0, alpha = 1.0, omega = 1.0, rho1 = c->h_bdot[0];
+    bool ok = true;
+    bool conv = !(c->h_bdot[2] > 0.0) || c->h_bdot[1] <= tol * tol * c->h_bdot[2];
+    for (int it = 0; it < 200 && !conv && ok; ++it) {
+        *iters = it + 1;
+        if (!(rho1 != 0.0) || !std::isfinite(rho1)) {
+            ok = false;
+            break;
         }
-        ok = ok && conv;
+        const double beta = (rho1 / rho) * (alpha / omega);
+        HIPCHK(c, launch_band_lin(p, 1.0, r, beta, p, -beta * omega, v, N, s));
+        HIPCHK(c, launch_band_apply(b, c->sp, p, v, s));
+        if ((st = band_dots(c, 1, r0, v, nullptr, nullptr, nullptr, nullptr, s))) return st;
+        const double sigma = c->h_bdot[0];
+        if (!(sigma != 0.0) || !std::isfinite(sigma)) {
+            ok = false;
+            break;
+        }
+        alpha = rho1 / sigma;
+        HIPCHK(c, launch_band_lin(sv, 1.0, r, -alpha, v, 0.0, nullptr, N, s));
+        if ((st = band_dots(c, 2, sv, sv, x, x, nullptr, nullptr, s))) return st;
+        if (c->h_bdot[0] <= tol * tol * c->h_bdot[1]) {
+            HIPCHK(c, launch_band_lin(x, 1.0, x, alpha, p, 0.0, nullptr, N, s));
+            conv = true;
+            break;
+        }
+        HIPCHK(c, launch_band_apply(b, c->sp, sv, t, s));
+        if ((st = band_dots(c, 2, t, sv, t, t, nullptr, nullptr, s))) return st;
+        if (!(c->h_bdot[1] > 0.0)) {
+            ok = false;
+            break;
+        }
+        omega = c->h_bdot[0] / c->h_bdot[1];
+        HIPCHK(c, launch_band_lin(x, 1.0, x, alpha, p, omega, sv, N, s));
+        HIPCHK(c, launch_band_lin(r, 1.0, sv, -omega, t, 0.0, nullptr, N, s));
+        if ((st = band_dots(c, 3, r0, r, r, r, x, x, s))) return st;
+        rho = rho1;
+        rho1 = c->h_bdot[0];
+        conv = c->h_bdot[1] <= tol * tol * c->h_bdot[2];
+        if (!(omega != 0.0)) ok = false;
     }
+    ok = ok && conv;
+    int n_bad = c->n_models;
     if (ok) {
-        HIPCHK(c, launch_fill_u64(c->d_bbad, 1, 0ull, s));
-        HIPCHK(c, launch_band_check(x, N, c->d_bbad, s));
-        HIPCHK(c, hipMemcpyAsync(c->h_bbad, c->d_bbad, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, launch_band_check_models(x, n, c->P, c->d_model_of, c->d_bmodel_bad, s));
+        HIPCHK(c, hipMemcpyAsync(c->h_bmodel_bad.data(), c->d_bmodel_bad, (size_t)c->n_models, hipMemcpyDeviceToHost,
+                                 s));
         HIPCHK(c, hipStreamSynchronize(s));
-        ok = *c->h_bbad == 0;
+        n_bad = 0;
+        for (uint8_t f : c->h_bmodel_bad) n_bad += f != 0;
     }
-    if (ok) {
-        *used = 1;
-        HIPCHK(c, launch_band_finish(x, d_old, c->d_cell, n, c->P, d_new, d_flags, c->d_partials,
-                                     ali ? c->d_model_done : nullptr, c->d_model_of,
-                                     ali ? c->d_model_change : nullptr, s));
+    auto local = [&](double *out, ConvPartial *parts, unsigned long long *change) {
+        return launch_stateq(c->sp, c->d_cell, c->d_nh2, c->d_T, c->P, c->params.use_alo, d_old, d_J, d_Jeff, d_L,
+                             out, d_flags, parts, stateq_blocks(c->P), ali ? c->d_model_done : nullptr,
+                             c->d_model_of, change, s);
+    };
+    if (n_bad == c->n_models) {
+        // the band gave no model physical populations: the local solve everywhere
+        HIPCHK(c, local(d_new, c->d_partials, ali ? c->d_model_change : nullptr));
         return NLTE_OK;
     }
-    // the band gave no physical populations: the local solve
-    HIPCHK(c, launch_stateq(c->sp, c->d_cell, c->d_nh2, c->d_T, c->P, c->params.use_alo, d_old, d_J, d_Jeff, d_L,
-                            d_new, d_flags, c->d_partials, stateq_blocks(c->P), ali ? c->d_model_done : nullptr,
-                            c->d_model_of, ali ? c->d_model_change : nullptr, s));
+    if (n_bad > 0) HIPCHK(c, local(r0, nullptr, nullptr));   // r0 is free once the solve is done
+    *used = c->n_models - n_bad;
+    HIPCHK(c, launch_band_finish(x, n_bad > 0 ? r0 : nullptr, n_bad > 0 ? c->d_bmodel_bad : nullptr, d_old, c->d_cell, n,
+                                 c->P, d_new, d_flags, c->d_partials, ali ? c->d_model_done : nullptr, c->d_model_of,
+                                 ali ? c->d_model_change : nullptr, s));
     return NLTE_OK;
 }
 
@@ -845,6 +854,7 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_bpart);
     dfree(c->d_bdot);
     dfree(c->d_bbad);
+    dfree(c->d_bmodel_bad);
     if (c->h_bdot) (void)hipHostFree(c->h_bdot);
     if (c->h_bbad) (void)hipHostFree(c->h_bbad);
     dfree(c->d_ng_hist);
@@ -1498,7 +1508,7 @@ nlte_status nlte_run_ali_dev(nlte_ctx *c, const double *d_init, double *d_out, n
         if (band) {
             int used = 0;
             if ((st = iteration_band(c, buf[slot], buf[slot ^ 1], s, &used))) return st;
-            n_band += used;
+            n_band += used > 0;
         } else if (scat) {
             if ((st = iteration_scat(c, buf[slot], buf[slot ^ 1], s))) return st;
         } else if (graph)

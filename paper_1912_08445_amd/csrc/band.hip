@@ -8,7 +8,10 @@
 // rate matrices and C the couplings.  It is solved by BiCGSTAB (van der Vorst 1992) on the
 // block-Jacobi preconditioned system (I + K^-1 C) x = K^-1 b, starting from the uncoupled
 // solution K^-1 b, with inner products weighted by 1 / n_tot^2 (fractional populations).
-// Points of converged models are held fixed.
+// Points of converged models are held fixed.  A model with a singular local matrix, or
+// whose coupled solution has a population that is not positive and finite, takes the
+// local (diagonal ALO) solve instead (Sec. 6.1); its couplings are left out of the
+// coupled system, which is block diagonal over models.
 #include "rates.h"
 
 namespace nlte {
@@ -101,6 +104,7 @@ __global__ __launch_bounds__(kBandThreads) void k_band_setup(BandArgs b, Species
     }
     if (!lu_factor(n, M, pv)) {
         atomicAdd(b.bad, 1ull);
+        b.model_bad[b.model_of[p]] = 1;
         for (int i = 0; i < n * n; ++i) M[i] = (i % (n + 1) == 0) ? 1.0 : 0.0;
         for (int i = 0; i < n; ++i) {
             pv[i] = i;
@@ -124,6 +128,15 @@ __global__ __launch_bounds__(kBandThreads) void k_band_setup(BandArgs b, Species
             b.cpl[(p * nl + l) * R + r] = k;
         }
     }
+}
+
+// Couplings of the points of models that take the local solve are dropped, so their rows
+// read x = x0 and the coupled solve of the other models is unchanged.
+__global__ __launch_bounds__(kBandThreads) void k_band_mask(BandArgs b, int n_lines)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= b.P || !b.model_bad[b.model_of[p]]) return;
+    for (int i = 0; i < n_lines * b.R; ++i) b.cpl[p * n_lines * b.R + i] = 0.0;
 }
 
 // w = y + K^-1 C y
@@ -194,17 +207,23 @@ __global__ void k_band_lin(double *__restrict__ out, double a, const double *__r
     out[i] = v;
 }
 
-// Entries that are not positive and finite.
-__global__ void k_band_check(const double *__restrict__ x, int64_t N, unsigned long long *__restrict__ bad)
+// Models with a population that is not positive and finite.
+__global__ void k_band_check_models(const double *__restrict__ x, int n, int64_t P,
+                                    const int32_t *__restrict__ model_of, uint8_t *__restrict__ model_bad)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    if (!(x[i] > 0.0) || !isfinite(x[i])) atomicAdd(bad, 1ull);
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    bool ok = true;
+    for (int i = 0; i < n; ++i) ok = ok && x[p * n + i] > 0.0 && isfinite(x[p * n + i]);
+    if (!ok) model_bad[model_of[p]] = 1;
 }
 
-// Accept the band's populations: copy, change statistics and per-model changes as the
-// local solve reports them.
-__global__ __launch_bounds__(256) void k_band_finish(const double *__restrict__ x, const double *__restrict__ old,
+// New populations: the band's, or the local solve's for models marked in model_bad
+// (local and model_bad nullable: every model takes the band's); change statistics and
+// per-model changes as the local solve reports them.
+__global__ __launch_bounds__(256) void k_band_finish(const double *__restrict__ x, const double *__restrict__ local,
+                                                     const uint8_t *__restrict__ model_bad,
+                                                     const double *__restrict__ old,
                                                      const CellRec *__restrict__ cell, int n, int64_t P,
                                                      double *__restrict__ pops_new, uint8_t *__restrict__ flags,
                                                      ConvPartial *partials, const uint8_t *__restrict__ done,
@@ -220,9 +239,11 @@ __global__ __launch_bounds__(256) void k_band_finish(const double *__restrict__ 
     int64_t cnt = 0;
     if (p < P) {
         const bool fixed = done != nullptr && done[model_of[p]];
+        const bool loc = model_bad != nullptr && model_bad[model_of[p]];
+        const double *src = loc ? local : x;
         const double nt = cell[p].ntot;
         for (int i = 0; i < n; ++i) {
-            const double v = fixed ? old[p * n + i] : x[p * n + i];
+            const double v = fixed ? old[p * n + i] : src[p * n + i];
             pops_new[p * n + i] = v;
             if (!fixed && v / nt > 1e-10) {
                 const double d = fabs(v - old[p * n + i]) / v;
@@ -231,7 +252,7 @@ __global__ __launch_bounds__(256) void k_band_finish(const double *__restrict__ 
                 ++cnt;
             }
         }
-        if (flags) flags[p] = 0;
+        if (flags && !loc) flags[p] = 0;   // the local solve has set its own
     }
     const int t = threadIdx.x;
     s_max[t] = mx;
@@ -300,20 +321,31 @@ hipError_t launch_band_lin(double *out, double a, const double *X, double b, con
     return hipGetLastError();
 }
 
-hipError_t launch_band_check(const double *x, int64_t N, unsigned long long *bad, hipStream_t s)
+hipError_t launch_band_check_models(const double *x, int n, int64_t P, const int32_t *model_of, uint8_t *model_bad,
+                                   hipStream_t s)
 {
-    if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_band_check, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, x, N, bad);
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band_check_models, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, x, n, P, model_of,
+                       model_bad);
     return hipGetLastError();
 }
 
-hipError_t launch_band_finish(const double *x, const double *old, const CellRec *cell, int n, int64_t P,
-                              double *pops_new, uint8_t *flags, ConvPartial *partials, const uint8_t *done,
-                              const int32_t *model_of, unsigned long long *model_change, hipStream_t s)
+hipError_t launch_band_mask(const BandArgs &b, int n_lines, hipStream_t s)
+{
+    if (b.P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band_mask, dim3((unsigned)((b.P + kBandThreads - 1) / kBandThreads)), dim3(kBandThreads), 0,
+                       s, b, n_lines);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_finish(const double *x, const double *local, const uint8_t *model_bad, const double *old,
+                              const CellRec *cell, int n, int64_t P, double *pops_new, uint8_t *flags,
+                              ConvPartial *partials, const uint8_t *done, const int32_t *model_of,
+                              unsigned long long *model_change, hipStream_t s)
 {
     if (P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_band_finish, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, x, old, cell, n, P, pops_new,
-                       flags, partials, done, model_of, model_change);
+    hipLaunchKernelGGL(k_band_finish, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, x, local, model_bad, old,
+                       cell, n, P, pops_new, flags, partials, done, model_of, model_change);
     return hipGetLastError();
 }
 

@@ -100,6 +100,7 @@ struct BandArgs {
     double *cpl;                  // [P][n_lines][n_rays] coupling coefficients
     double *x0;                   // [P][n_lev] uncoupled solution
     unsigned long long *bad;      // singular local matrices
+    uint8_t *model_bad;           // [n_models] 1: the model takes the local solve this iteration
     int64_t P;
     int R;
 };
@@ -287,7 +288,9 @@ struct nlte_ctx {
     double *d_bvec = nullptr;            // 8 vectors of [P][n_lev]
     double *d_bpart = nullptr, *d_bdot = nullptr, *h_bdot = nullptr;
     unsigned long long *d_bbad = nullptr, *h_bbad = nullptr;
-    int64_t band_dims[4] = {0, 0, 0, 0};   // P, n_lev, n_lines, n_rays the buffers were sized for
+    int64_t band_dims[5] = {0, 0, 0, 0, 0};   // P, n_lev, n_lines, n_rays, n_models the buffers were sized for
+    uint8_t *d_bmodel_bad = nullptr;     // [n_models]
+    std::vector<uint8_t> h_bmodel_bad;
 
     std::vector<double> dir_host;        // [n_rays][3] as set
 
@@ -389,10 +392,13 @@ hipError_t launch_band_dots(const DotArgs &d, const CellRec *cell, int n, int64_
                             hipStream_t s);
 hipError_t launch_band_lin(double *out, double a, const double *X, double b, const double *Y, double c,
                            const double *Z, int64_t N, hipStream_t s);
-hipError_t launch_band_check(const double *x, int64_t N, unsigned long long *bad, hipStream_t s);
-hipError_t launch_band_finish(const double *x, const double *old, const CellRec *cell, int n, int64_t P,
-                              double *pops_new, uint8_t *flags, ConvPartial *partials, const uint8_t *done,
-                              const int32_t *model_of, unsigned long long *model_change, hipStream_t s);
+hipError_t launch_band_check_models(const double *x, int n, int64_t P, const int32_t *model_of, uint8_t *model_bad,
+                                   hipStream_t s);
+hipError_t launch_band_mask(const BandArgs &b, int n_lines, hipStream_t s);
+hipError_t launch_band_finish(const double *x, const double *local, const uint8_t *model_bad, const double *old,
+                              const CellRec *cell, int n, int64_t P, double *pops_new, uint8_t *flags,
+                              ConvPartial *partials, const uint8_t *done, const int32_t *model_of,
+                              unsigned long long *model_change, hipStream_t s);
 
 // imaging
 hipError_t launch_image(const ImageArgs &a, double3 e1, double3 e2, double *xy, hipStream_t s);

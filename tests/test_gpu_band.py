@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import band
-from synth import configs, directions
+from synth import configs, directions, species
 from synth.models import concat_models
 
 from _common import oracle_for, rel, solver_for
@@ -138,3 +138,56 @@ def test_band_needs_the_alo():
         s.set_params(alo_band=1, use_alo=0)
     with pytest.raises(NlteError):
         s.set_params(alo_band=2)
+
+
+def _radiative_sphere(n_points, seed):
+    # no collisions: with Ld = 1 and Jb = 0 a point's band rate matrix has no transitions
+    w = configs.sphere2(n_points=n_points, seed=seed)
+    w.species = species.two_level(100e9, 3.0, 1e-5, 0.0, 28.0)
+    return w
+
+
+def _singular_band_inputs(o, pops):
+    J, Je, L = o.formal_solve(pops)
+    n, nl, R = pops.shape[0], J.shape[1], o.n_rays
+    return J, Je, L, np.zeros((n, nl)), np.ones((n, nl)), np.zeros((n, nl, R))
+
+
+def test_band_fallback_on_singular_local_matrices():
+    w = _radiative_sphere(120, 21)
+    o = oracle_for(w)
+    pops = o.lte()
+    J, Je, L, Jb, Ld, Ln = _singular_band_inputs(o, pops)
+    got, used, _ = solver_for(w).stateq_band(pops, J, Je, L, Jb, Ld, Ln)
+    ref, ok = band.stateq_band(o, pops, J, Je, L, Jb, Ld, Ln, band.first_cells(o))
+    local, flags = o.stateq(pops, J, Je, L)
+    assert used == 0 and not ok and np.all(flags == 0)
+    assert rel(got, local).max() <= 1e-10 and rel(ref, local).max() == 0.0
+
+
+def test_band_fallback_is_per_model():
+    # model 0 has singular band matrices, model 1 a regular band solve: only model 0 drops
+    # to the local solve
+    ws = [_radiative_sphere(120, 22), _radiative_sphere(150, 23)]
+    offs, merged = concat_models([w.model for w in ws])
+    wb = _radiative_sphere(10, 24)
+    wb.model, wb.offsets = merged, offs
+    parts, refs = [], []
+    for m, w in enumerate(ws):
+        o = oracle_for(w)
+        pops = o.lte() * np.random.default_rng(30 + m).uniform(0.8, 1.2, (w.n_points, 2))
+        pops *= ((w.model.abundance * w.model.n_h2) / pops.sum(1))[:, None]
+        if m == 0:
+            inp = _singular_band_inputs(o, pops)
+            ref = o.stateq(pops, *inp[:3])[0]
+        else:
+            inp = o.formal_solve_band(pops)
+            ref, ok = band.stateq_band(o, pops, *inp, band.first_cells(o))
+            assert ok
+        parts.append((pops, *inp))
+        refs.append(ref)
+    cat = [np.concatenate([p[k] for p in parts]) for k in range(7)]
+    got, used, _ = solver_for(wb).stateq_band(*cat)
+    assert used == 1
+    assert rel(got[offs[0]:offs[1]], refs[0]).max() <= 1e-10
+    assert rel(got[offs[1]:offs[2]], refs[1]).max() <= 1e-9
