@@ -191,3 +191,17 @@ def test_band_fallback_is_per_model():
     assert used == 1
     assert rel(got[offs[0]:offs[1]], refs[0]).max() <= 1e-10
     assert rel(got[offs[1]:offs[2]], refs[1]).max() <= 1e-9
+
+
+def test_band_with_ng_reaches_the_fixed_point():
+    # Ng extrapolation of band iterates: same fixed point, no more iterations than either
+    w = _thick_sphere()
+    plain, rp = solver_for(w, max_iter=300, tol=1e-10).run_ali()
+    _, rb = solver_for(w, alo_band=1, max_iter=300, tol=1e-10).run_ali()
+    _, rn = solver_for(w, ng_every=4, max_iter=300, tol=1e-10).run_ali()
+    both, rbn = solver_for(w, alo_band=1, ng_every=4, max_iter=300, tol=1e-10).run_ali()
+    assert rbn["converged"] and rbn["n_ng_steps"] > 0 and rbn["n_band"] > 0
+    assert rbn["iterations"] <= min(rb["iterations"], rn["iterations"])
+    assert rel(both, plain).max() < 1e-8
+    print("iterations plain / band / Ng / band+Ng:", rp["iterations"], rb["iterations"], rn["iterations"],
+          rbn["iterations"])
