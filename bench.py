@@ -207,7 +207,7 @@ def ali_forms(s, w, make, args, dev):
     for prec, start in forms:
         s.set_params(precision=prec, tol=1e-4, max_iter=200)
         best = None
-        for _ in range(3):   # best of three: the first run of a form captures its graphs
+        for _ in range(max(1, args.ali_runs)):   # best of the runs: the first captures the graphs
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if start == "lte":
@@ -240,15 +240,16 @@ def ali_forms(s, w, make, args, dev):
                                         "wall_ratio": a["wall_s"] / b["wall_s"],
                                         "max_rel_diff_vs_fp64_reference": a["max_rel_diff_vs_fp64_reference"]}
         res["mlp"] = mlp_timing(s, w, dev)
-    res.update(ali_variants(s, w, out, ref, ntot))
+    if not args.no_variants:
+        res.update(ali_variants(s, w, out, ref, ntot, args.ali_runs))
     s.set_params(precision=args.precision)
     return res
 
 
-def _timed_ali(s, out, runs=3):
+def _timed_ali(s, out, runs):
     import torch
     best = None
-    for _ in range(runs):
+    for _ in range(max(1, runs)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = s.run_ali_dev(None, out)
@@ -274,7 +275,7 @@ def line_centre_opacity(s, w):
     return np.median(kchi / (np.sqrt(np.pi) * nu * vw[:, None] / c), axis=0)
 
 
-def ali_variants(s, w, out, ref, ntot):
+def ali_variants(s, w, out, ref, ntot, runs):
     """FP64 from LTE with Ng acceleration (M = 4) and with the band ALO, against the same
     reference; and the ALI with a grey scattering opacity of half the median line-centre
     opacity (different physics: its own iterations, wall time and formal-solve time)."""
@@ -283,7 +284,7 @@ def ali_variants(s, w, out, ref, ntot):
     res = {}
     for key, extra in (("fp64_lte_ng4", {"ng_every": 4}), ("fp64_lte_band", {"alo_band": 1})):
         s.set_params(precision="fp64", tol=1e-4, max_iter=200, **extra)
-        wall, r = _timed_ali(s, out)
+        wall, r = _timed_ali(s, out, runs)
         err = _rel_err(out.cpu().numpy(), ref, ntot)
         res[key] = {"iterations": r["iterations"], "converged": r["converged"], "wall_s": wall,
                     "max_rel_diff_vs_fp64_reference": err, "n_ng_steps": r["n_ng_steps"],
@@ -294,7 +295,7 @@ def ali_variants(s, w, out, ref, ntot):
     chi = np.broadcast_to(0.5 * line_centre_opacity(s, w), (w.n_points, w.species.n_lines)).copy()
     s.set_scattering(chi)
     s.set_params(precision="fp64", tol=1e-4, max_iter=200)
-    wall, r = _timed_ali(s, out)
+    wall, r = _timed_ali(s, out, runs)
     s.set_params(profile=1)
     s.reset_kernel_stats()
     s.set_params(max_iter=1, tol=0.0)
@@ -358,6 +359,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ali", action="store_true")
+    ap.add_argument("--ali-runs", type=int, default=3,
+                    help="runs per ALI form, the fastest reported (the first also captures the graphs)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the Ng, band-ALO and scattering ALI forms")
     ap.add_argument("--train-models", type=int, default=None,
                     help="other seeds of the workload whose converged populations train the warm start "
                          "(0: no warm start; default 48 for discs, else 8)")
