@@ -152,25 +152,41 @@ def train_warm_start(s, w, make, args, dev):
     factory, seed0 = training_factory(args, make)
     seeds = [seed0 + i for i in range(args.train_models)]
 
-    def model(sd):
+    def model(sd, precision="fp64"):
         st = Solver(0)
-        st.setup(factory(sd), precision="fp64")
+        st.setup(factory(sd), precision=precision)
         return st
 
-    # one training model resident at a time: features first (for the standardisation),
-    # then the converged rows
-    feats = []
-    for sd in seeds:
-        st = model(sd)
-        feats.append(st.features())
-        st.close()
-    mean, std = warmstart.feature_norm(feats)
     rows = []
-    for sd in seeds:
-        st = model(sd)
-        X, T, _ = warmstart.converged_rows(st, mean, std, tol=1e-6, sample=args.train_sample)
-        rows.append((X, T))
-        st.close()
+    if args.workload == "disc10":
+        # million-point discs, one resident at a time and each set up once: the first one's
+        # features standardise every row, and the training ALIs run in the FP32 form
+        mean = std = None
+        for k, sd in enumerate(seeds):
+            t1 = time.perf_counter()
+            st = model(sd, "fp32")
+            if mean is None:
+                mean, std = warmstart.feature_norm([st.features()])
+            X, T, rep = warmstart.converged_rows(st, mean, std, tol=1e-6, sample=args.train_sample)
+            rows.append((X, T))
+            st.close()
+            log(f"training model {k + 1}/{len(seeds)} (seed {sd}): {rep['iterations']} iterations, "
+                f"{time.perf_counter() - t1:.1f} s")
+    else:
+        # one training model resident at a time: features first (for the standardisation),
+        # then the converged rows
+        feats = []
+        for sd in seeds:
+            st = model(sd)
+            feats.append(st.features())
+            st.close()
+        mean, std = warmstart.feature_norm(feats)
+        for k, sd in enumerate(seeds):
+            st = model(sd)
+            X, T, rep = warmstart.converged_rows(st, mean, std, tol=1e-6, sample=args.train_sample)
+            rows.append((X, T))
+            st.close()
+            log(f"training model {k + 1}/{len(seeds)} (seed {sd}): {rep['iterations']} iterations")
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
     curve = warmstart.train(s, rows, mean, std, [(6000, 2e-3), (4000, 2e-4), (4000, 5e-5)], batch=4096, seed=1)
