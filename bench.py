@@ -189,7 +189,7 @@ def train_warm_start(s, w, make, args, dev):
             log(f"training model {k + 1}/{len(seeds)} (seed {sd}): {rep['iterations']} iterations")
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
-    curve = warmstart.train(s, rows, mean, std, [(6000, 2e-3), (4000, 2e-4), (4000, 5e-5)], batch=4096, seed=1)
+    curve = warmstart.train(s, rows, mean, std, warmstart.SCHEDULE, batch=4096, seed=1)
     t_train = time.perf_counter() - t0
     n_rows = sum(int(r[0].shape[0]) for r in rows)
     s._bench_rows = rows   # kept for the kernel timing of training steps

@@ -374,8 +374,10 @@ nlte_status nlte_image_dev(nlte_ctx *ctx, const double *d_pops, int ray, int lin
  *   |v_m - v_p| / |x_m - x_p| (floored at 1e-30 s^-1); 3..7 log10 of the minimum, lower
  *   quartile, median, upper quartile and maximum over all rays of the H2 column from the
  *   point to the end of its cached walk (Sec. 3.2; trapezoid in the projected distance,
- *   floored at 1 cm^-2; quantiles interpolate linearly between order statistics at
- *   position q (n_rays - 1)).
+ *   at least half a cell's column n_H2 d/2, d the mean distance to the point's
+ *   neighbours, which a walk without cells at the model's edge takes, and at least
+ *   1 cm^-2; quantiles interpolate linearly between order statistics at position
+ *   q (n_rays - 1)).
  * Network: 8 standardised inputs -> 128 -> 128 -> 128 -> n_out, erf GELU after each
  * hidden layer; output i is the departure of level i from LTE, log10 (f_i / f_i^LTE),
  * with f_i = n_i / (abundance n_H2) and f_i^LTE the Boltzmann fraction at the point's

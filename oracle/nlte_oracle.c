@@ -777,11 +777,13 @@ static int cmp_double(const void *a, const void *b)
  *   0  log10 n_H2,   1  log10 T,
  *   2  log10 max(g, 1e-30) with g the mean over p's valid neighbours m of
  *      |v_m - v_p| / |x_m - x_p| (0 without neighbours),
- *   3..7  log10 max(N, 1) of the minimum, lower quartile, median, upper quartile and
- *      maximum over all rays of the H2 column N from p to the end of its walk (Sec. 3.2):
- *      the trapezoid sum of n_H2 over the projected distances between consecutive
- *      cells, starting at p with projection 0.  A quantile at q is the linear
- *      interpolation between order statistics at position q (n_rays - 1). */
+ *   3..7  log10 of the minimum, lower quartile, median, upper quartile and maximum over
+ *      all rays of the H2 column N from p to the end of its walk (Sec. 3.2): the
+ *      trapezoid sum of n_H2 over the projected distances between consecutive cells,
+ *      starting at p with projection 0, and at least half a cell's column,
+ *      n_H2(p) d / 2 with d the mean distance to p's valid neighbours (a walk with no
+ *      cell, at the model's edge, takes that), and at least 1 cm^-2.  A quantile at q
+ *      is the linear interpolation between order statistics at position q (n_rays - 1). */
 void or_features(const or_ctx *c, double *F)
 {
     const int R = c->n_rays;
@@ -790,7 +792,7 @@ void or_features(const or_ctx *c, double *F)
         double *f = F + 8 * p;
         f[0] = log10(c->nh2[p]);
         f[1] = log10(c->T[p]);
-        double gsum = 0.0;
+        double gsum = 0.0, dsum = 0.0;
         int gcount = 0;
         for (int s = 0; s < c->k; ++s) {
             int32_t m = c->nbr[p * c->k + s];
@@ -803,10 +805,13 @@ void or_features(const or_ctx *c, double *F)
             double nv = sqrt((dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2]);
             double nx = sqrt((dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]);
             gsum += nv / nx;
+            dsum += nx;
             ++gcount;
         }
         double g = gcount > 0 ? gsum / gcount : 0.0;
         f[2] = log10(g > 1e-30 ? g : 1e-30);
+        double half_cell = gcount > 0 ? 0.5 * c->nh2[p] * (dsum / gcount) : 0.0;
+        double floor_col = half_cell > 1.0 ? half_cell : 1.0;
 
         double *col = malloc(sizeof(double) * R);
         for (int r = 0; r < R; ++r) {
@@ -821,7 +826,7 @@ void or_features(const or_ctx *c, double *F)
                 n_prev = n_i;
                 z_prev = Zs[i];
             }
-            col[r] = N;
+            col[r] = N > floor_col ? N : floor_col;
             free(cells);
             free(Zs);
         }
@@ -832,7 +837,7 @@ void or_features(const or_ctx *c, double *F)
             int i = (int)floor(h);
             double v = col[i];
             if (i + 1 < R) v = col[i] + (h - i) * (col[i + 1] - col[i]);
-            f[3 + j] = log10(v > 1.0 ? v : 1.0);
+            f[3 + j] = log10(v);
         }
         free(col);
     }

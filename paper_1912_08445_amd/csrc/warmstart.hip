@@ -102,6 +102,19 @@ __global__ __launch_bounds__(64) void k_features(const CellRec *__restrict__ cel
     const int lane = threadIdx.x;
     if (p >= P) return;
     const double ox = cell[p].px, oy = cell[p].py, oz = cell[p].pz;
+    // half a cell's column, the least a ray's column is taken to be (a walk with no cell
+    // lies at the model's edge): n_H2 times half the mean distance to the neighbours
+    double dsum = 0.0;
+    int dcount = 0;
+    for (int s = 0; s < k; ++s) {
+        const int32_t m = nbr[p * k + s];
+        if (m < 0) continue;
+        const double dx = cell[m].px - ox, dy = cell[m].py - oy, dz = cell[m].pz - oz;
+        dsum += sqrt((dx * dx + dy * dy) + dz * dz);
+        ++dcount;
+    }
+    const double half_cell = dcount > 0 ? 0.5 * nh2[p] * (dsum / dcount) : 0.0;
+    const double floor_col = half_cell > 1.0 ? half_cell : 1.0;
 
     for (int r = lane; r < R; r += 64) {
         const double nx = dir[3 * r], ny = dir[3 * r + 1], nz = dir[3 * r + 2];
@@ -116,7 +129,7 @@ __global__ __launch_bounds__(64) void k_features(const CellRec *__restrict__ cel
             n_prev = n_i;
             z_prev = Z;
         }
-        col[r] = N;
+        col[r] = N > floor_col ? N : floor_col;
     }
     __syncthreads();
     // order statistics: rank by value, equal values by ray index
@@ -154,7 +167,7 @@ __global__ __launch_bounds__(64) void k_features(const CellRec *__restrict__ cel
         const int i = (int)floor(h);
         double v = srt[i];
         if (i + 1 < R) v = srt[i] + (h - i) * (srt[i + 1] - srt[i]);
-        f[3 + j] = log10(v > 1.0 ? v : 1.0);
+        f[3 + j] = log10(v);
     }
 }
 

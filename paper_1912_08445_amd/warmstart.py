@@ -41,7 +41,13 @@ def converged_rows(solver, mean, std, tol=1e-6, max_iter=200, sample=None, seed=
     return X, T, rep
 
 
-def train(solver, rows, mean, std, phases, batch=4096, seed=0, init_seed=0):
+# Training phases [(steps, learning rate), ...] at batch 4096: a long phase at 2e-3, then
+# two annealing phases.  The last, low-rate phase trims the largest prediction errors,
+# which decide the first iterations' maximum change.
+SCHEDULE = ((12000, 2e-3), (8000, 2e-4), (4000, 2e-5))
+
+
+def train(solver, rows, mean, std, phases=SCHEDULE, batch=4096, seed=0, init_seed=0):
     """Fresh network on `solver` with the rows' standardisation, trained on the
     concatenated, shuffled rows [(X, T), ...] in phases [(steps, lr), ...] (the Adam
     state carries over between phases); returns the per-step loss curve (host)."""

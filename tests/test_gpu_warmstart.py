@@ -241,7 +241,7 @@ def test_warm_start_gain_on_held_out_disc():
     rows = [warmstart.converged_rows(t, mean, std, tol=1e-6)[:2] for t in train]
     held_w = _disc(200, n_points)
     held = solver_for(held_w)
-    curve = warmstart.train(held, rows, mean, std, [(6000, 2e-3), (4000, 2e-4)], batch=4096, seed=1)
+    curve = warmstart.train(held, rows, mean, std, warmstart.SCHEDULE, batch=4096, seed=1)
     assert curve[-50:].mean() < 0.05 * curve[:5].mean()
 
     dev = torch.device("cuda:0")

@@ -25,6 +25,15 @@ def _workload(model, rays, sp=None):
 
 # ------------------------------------------------------------------ features
 
+def _floor(m, p):
+    """Half a cell's column at p: n_H2(p) times half the mean distance to its valid
+    neighbours (at least 1 cm^-2)."""
+    nb = m.nbr[p][m.nbr[p] >= 0]
+    if nb.size == 0:
+        return 1.0
+    return max(0.5 * m.n_h2[p] * np.mean(np.linalg.norm(m.pos[nb] - m.pos[p], axis=1)), 1.0)
+
+
 def test_features_chain_linear_density_and_hubble_gradient():
     # Points on a line with uneven spacing, n_H2 linear in x, Hubble flow v = H x:
     # the trapezoid column is exact for a linear density, and every neighbour has
@@ -40,16 +49,17 @@ def test_features_chain_linear_density_and_hubble_gradient():
     x0, x1 = x[0], x[-1]
     col = lambda lo, hi: a * (hi - lo) + 0.5 * b * (hi * hi - lo * lo)
     for p in range(40):
-        cols = np.sort([col(x[p], x1), col(x0, x[p])])
+        cols = np.sort(np.maximum([col(x[p], x1), col(x0, x[p])], _floor(m, p)))
         q = [cols[0], cols[0] + 0.25 * (cols[1] - cols[0]), 0.5 * (cols[0] + cols[1]),
              cols[0] + 0.75 * (cols[1] - cols[0]), cols[1]]
-        expect = np.log10(np.maximum(q, 1.0))
+        expect = np.log10(q)
         assert np.allclose(F[p, 3:], expect, rtol=1e-12, atol=1e-12), p
         assert abs(F[p, 0] - np.log10(n[p])) < 1e-13
         assert abs(F[p, 1] - np.log10(T[p])) < 1e-13
         assert abs(F[p, 2] - np.log10(H)) < 1e-12
-    # the end points see an empty column on their outward ray: floored at 1 cm^-2
-    assert F[0, 3] == 0.0 and F[-1, 3] == 0.0
+    # the end points see an empty column on their outward ray: half a cell's column
+    assert abs(F[0, 3] - np.log10(0.5 * n[0] * (x[1] - x[0]))) < 1e-12
+    assert abs(F[-1, 3] - np.log10(0.5 * n[-1] * (x[-1] - x[-2]))) < 1e-12
 
 
 def test_features_lattice_axis_rays_match_numpy_quantiles():
@@ -65,8 +75,9 @@ def test_features_lattice_axis_rays_match_numpy_quantiles():
     for p in range(mm ** 3):
         cols = nval * d * np.array([mm - 1 - I[p], I[p], mm - 1 - J[p], J[p], mm - 1 - K[p], K[p]],
                                    float)
+        cols = np.maximum(cols, 0.5 * nval * d)   # face neighbours at distance d: half a cell
         q = np.quantile(cols, [0.0, 0.25, 0.5, 0.75, 1.0])   # linear interpolation
-        assert np.allclose(F[p, 3:], np.log10(np.maximum(q, 1.0)), rtol=1e-12, atol=1e-12)
+        assert np.allclose(F[p, 3:], np.log10(q), rtol=1e-12, atol=1e-12)
     assert np.all(F[:, 2] == -30.0)   # static: gradient floored at 1e-30 s^-1
 
 
@@ -85,8 +96,8 @@ def test_features_columns_from_walks_on_sphere():
             nn = np.concatenate([[m.n_h2[p]], m.n_h2[cells]])
             zz = np.concatenate([[0.0], Z])
             cols.append(np.sum(0.5 * (nn[1:] + nn[:-1]) * np.diff(zz)))
-        q = np.quantile(cols, [0.0, 0.25, 0.5, 0.75, 1.0])
-        assert np.allclose(F[p, 3:], np.log10(np.maximum(q, 1.0)), rtol=1e-12, atol=1e-12)
+        q = np.quantile(np.maximum(cols, _floor(m, p)), [0.0, 0.25, 0.5, 0.75, 1.0])
+        assert np.allclose(F[p, 3:], np.log10(q), rtol=1e-12, atol=1e-12)
         nb = m.nbr[p][m.nbr[p] >= 0]
         g = np.mean(np.linalg.norm(m.vel[nb] - m.vel[p], axis=1) / np.linalg.norm(m.pos[nb] - m.pos[p], axis=1))
         assert abs(F[p, 2] - np.log10(g)) < 1e-12
