@@ -291,10 +291,56 @@ def line_centre_opacity(s, w):
     return np.median(kchi / (np.sqrt(np.pi) * nu * vw[:, None] / c), axis=0)
 
 
+def image_timing(s, w, pops, n_ch=64, runs=3):
+    """Channel images (Sec. 3.5) of the line with index 0 along the first ray, from the
+    populations `pops` (device), at n_ch channel velocities over +-(largest speed + 4 largest
+    line widths). The work unit is the elimination step of one channel along the pair
+    through a point; the steps of that pair over all points come from a solver traced with
+    this direction and its antipode only (the walks depend only on the direction and the
+    neighbours, so they are the same walks)."""
+    import copy
+
+    import numpy as np
+    import torch
+    from paper_1912_08445_amd.binding import Solver
+    dirs = s.get_rays()
+    rb = int(np.argmin(np.abs(dirs + dirs[0]).sum(axis=1)))
+    w2 = copy.copy(w)
+    w2.rays = dirs[[0, rb]].copy()
+    s2 = Solver(0)
+    s2.setup(w2)
+    steps = s2.trace_stats()[2]
+    s2.close()
+    vmax = float(np.sqrt((w.model.vel ** 2).sum(axis=1)).max() + 4.0 * s.line_width_speed().max())
+    v_ch = np.linspace(-vmax, vmax, n_ch)
+    I = torch.empty((w.n_points, n_ch), dtype=torch.float64, device=pops.device)
+    xy = torch.empty((w.n_points, 2), dtype=torch.float64, device=pops.device)
+    s.image_dev(pops, 0, 0, v_ch, I, xy)
+    torch.cuda.synchronize()
+    s.set_params(profile=1)
+    s.reset_kernel_stats()
+    for _ in range(runs):
+        s.image_dev(pops, 0, 0, v_ch, I, xy)
+    torch.cuda.synchronize()
+    s.set_params(profile=0)
+    ms, n = s.kernel_stats("image")
+    ms /= n
+    node_ch = steps * n_ch
+    tf = node_ch * FLOPS_PER_STEP / (ms * 1e-3) / 1e12
+    r = {"channels": n_ch, "v_max_cm_s": vmax, "ray": 0, "line": 0, "kernel": "k_image", "kernel_ms": ms,
+         "node_channel_per_launch": node_ch, "point_channel_per_s": w.n_points * n_ch / (ms * 1e-3),
+         "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                      "frac": tf / PEAK_FP64_TFLOPS, "flops_per_node_channel": FLOPS_PER_STEP}}
+    log(f"image: {n_ch} channels, k_image {ms:.3f} ms, {node_ch} node*channel steps, {tf:.1f} TFLOP/s "
+        f"({100 * tf / PEAK_FP64_TFLOPS:.1f}% of FP64 peak)")
+    return r
+
+
 def ali_variants(s, w, out, ref, ntot, runs):
     """FP64 from LTE with Ng acceleration (M = 4) and with the band ALO, against the same
-    reference; and the ALI with a grey scattering opacity of half the median line-centre
-    opacity (different physics: its own iterations, wall time and formal-solve time)."""
+    reference; the ALI with a grey scattering opacity of half the median line-centre
+    opacity (different physics: its own iterations, wall time and formal-solve time); and
+    channel images of the converged reference populations."""
     import numpy as np
     import torch
     res = {}
@@ -326,6 +372,8 @@ def ali_variants(s, w, out, ref, ntot, runs):
                                   "max_change": [float(c) for c in r["max_change"]]}
     log(f"ALI with scattering: {r['iterations']} iterations, {wall * 1e3:.1f} ms, formal solve "
         f"{f_ms / f_n:.1f} ms per sweep")
+    out.copy_(torch.from_numpy(ref).to(out.device))
+    res["image"] = image_timing(s, w, out)
     return res
 
 
@@ -378,7 +426,7 @@ def main():
     ap.add_argument("--ali-runs", type=int, default=3,
                     help="runs per ALI form, the fastest reported (the first also captures the graphs)")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the Ng, band-ALO and scattering ALI forms")
+                    help="skip the Ng, band-ALO and scattering ALI forms and the image timing")
     ap.add_argument("--train-models", type=int, default=None,
                     help="other seeds of the workload whose converged populations train the warm start "
                          "(0: no warm start; default 48 for discs, else 8)")

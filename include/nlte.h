@@ -452,8 +452,9 @@ nlte_status nlte_run_ali_warm_dev(nlte_ctx *ctx, double *d_pops_out, nlte_ali_re
 
 /* With params.profile = 1: accumulated HIP-event time [ms] and launch count of kernel
  * `name` since the last reset: "line_coef", "formal_solve", "stateq", "lte", "trace",
- * "features", "mlp_forward", "mlp_train" (forward, loss and backward of one batch) and
- * "mlp_update" (gradient reduction, Adam and operand packing of one step). */
+ * "features", "mlp_forward", "mlp_train" (forward, loss and backward of one batch),
+ * "mlp_update" (gradient reduction, Adam and operand packing of one step) and "image"
+ * (the emergent-intensity elimination of nlte_image, without the image-plane positions). */
 nlte_status nlte_kernel_stats(nlte_ctx *ctx, const char *name, double *ms, int64_t *launches);
 nlte_status nlte_reset_kernel_stats(nlte_ctx *ctx);
 

@@ -1717,6 +1717,7 @@ nlte_status nlte_kernel_stats(nlte_ctx *c, const char *name, double *ms, int64_t
     else if (!strcmp(name, "mlp_forward")) k = &c->st_mlp_forward;
     else if (!strcmp(name, "mlp_train")) k = &c->st_mlp_train;
     else if (!strcmp(name, "mlp_update")) k = &c->st_mlp_update;
+    else if (!strcmp(name, "image")) k = &c->st_image;
     if (!k) return fail(c, NLTE_E_INVALID_ARG, "unknown kernel name");
     if (ms) *ms = k->ms;
     if (launches) *launches = k->launches;
@@ -1727,7 +1728,7 @@ nlte_status nlte_reset_kernel_stats(nlte_ctx *c)
 {
     if (!c) return NLTE_E_INVALID_ARG;
     c->st_line_coef = c->st_formal = c->st_stateq = c->st_lte = c->st_trace = KernelStat{};
-    c->st_features = c->st_mlp_forward = c->st_mlp_train = c->st_mlp_update = KernelStat{};
+    c->st_features = c->st_mlp_forward = c->st_mlp_train = c->st_mlp_update = c->st_image = KernelStat{};
     return NLTE_OK;
 }
 
@@ -2177,8 +2178,7 @@ nlte_status nlte_image_dev(nlte_ctx *c, const double *d_pops, int ray, int line,
     a.ray = ray;
     a.n_ch = n_ch;
     // image-plane basis: e1 = (z x n)/|z x n| (x-axis instead of z when |n_z| > 0.9), e2 = n x e1
-    std::vector<double> dir(3 * (size_t)c->n_rays);
-    HIPCHK(c, hipMemcpy(dir.data(), c->d_dir, sizeof(double) * dir.size(), hipMemcpyDeviceToHost));
+    const double *dir = c->dir_host.data();
     const double n0 = dir[3 * ray], n1 = dir[3 * ray + 1], n2 = dir[3 * ray + 2];
     double r0 = 0.0, r1 = 0.0, r2 = 1.0;
     if (fabs(n2) > 0.9) {
@@ -2192,7 +2192,8 @@ nlte_status nlte_image_dev(nlte_ctx *c, const double *d_pops, int ray, int line,
     e1z /= en;
     const double3 e1 = make_double3(e1x, e1y, e1z);
     const double3 e2 = make_double3(n1 * e1z - n2 * e1y, n2 * e1x - n0 * e1z, n0 * e1y - n1 * e1x);
-    HIPCHK(c, launch_image(a, e1, e2, d_xy, s));
+    HIPCHK(c, timed(c, c->st_image, s, [&] { return launch_image(a, s); }));
+    if (d_xy) HIPCHK(c, launch_image_plane(c->d_cell, e1, e2, c->P, d_xy, s));
     return NLTE_OK;
 }
 

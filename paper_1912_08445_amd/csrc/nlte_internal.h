@@ -329,7 +329,7 @@ struct nlte_ctx {
     // profiling
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     nlte::KernelStat st_line_coef, st_formal, st_stateq, st_lte, st_trace;
-    nlte::KernelStat st_features, st_mlp_forward, st_mlp_train, st_mlp_update;
+    nlte::KernelStat st_features, st_mlp_forward, st_mlp_train, st_mlp_update, st_image;
 };
 
 namespace nlte {
@@ -401,7 +401,8 @@ hipError_t launch_band_finish(const double *x, const double *local, const uint8_
                               unsigned long long *model_change, hipStream_t s);
 
 // imaging
-hipError_t launch_image(const ImageArgs &a, double3 e1, double3 e2, double *xy, hipStream_t s);
+hipError_t launch_image(const ImageArgs &a, hipStream_t s);
+hipError_t launch_image_plane(const CellRec *cell, double3 e1, double3 e2, int64_t P, double *xy, hipStream_t s);
 hipError_t launch_formal_solve_scat(const ScatArgs &a, hipStream_t s);
 hipError_t launch_jnu_start(const double *ibdy, int64_t P, int n_lines, int n_q, double *jnu, hipStream_t s);
 

@@ -20,7 +20,16 @@ def _cases():
         ("outflow", configs.outflow5(n_points=1500, seed=4, nside=1), 2, [0, 7, 11],
          np.linspace(-2.5e6, 2.5e6, 70)),                                  # two channel blocks
         ("disc", disc, 4, [1, 6], np.linspace(-1.2e6, 1.2e6, 9)),
+        # pairs of more than 64 nodes (several staging chunks) through the innermost points,
+        # and channels so far out that the profile vanishes and is evaluated directly
+        ("outflow_long", configs.outflow5(n_points=30000, seed=5, nside=1), 1, [3],
+         np.concatenate([np.linspace(-2.5e6, 2.5e6, 62), [-5e8, 5e8]])),
     ]
+
+
+def _anti(s, r):
+    d = s.get_rays()
+    return int(np.argmin(np.abs(d + d[r]).sum(axis=1)))
 
 
 @pytest.mark.parametrize("name,w,line,rays,v", _cases(), ids=[c[0] for c in _cases()])
@@ -32,6 +41,11 @@ def test_image_matches_oracle(name, w, line, rays, v):
         J, Je, L = s.formal_solve(pops)
         pops, _ = s.stateq(pops, J, Je, L)
     sel = np.random.default_rng(1).choice(w.n_points, 40, replace=False)
+    if name == "outflow_long":
+        inner = np.argsort(np.linalg.norm(w.model.pos, axis=1))[:24]
+        sel = np.unique(np.concatenate([inner, sel[:16]]))
+        assert max(len(s.get_ray(p, r)) + len(s.get_ray(p, _anti(s, r)))
+                   for p in inner for r in rays) >= 64
     for r in rays:
         I, xy = s.image(pops, r, line, v)
         Io, xyo = o.image(pops, r, line, v, points=sel)

@@ -79,6 +79,11 @@ def test_single_point_model():
     assert rel(Js, J).max() < 1e-14 and rel(Jn, Jnu0).max() < 1e-14
     pa, ra = s.run_ali()
     s.set_scattering(None)
+    # an image through a point with empty walks, at the channel limit: the background
+    v = np.linspace(-1e6, 1e6, 1024)
+    I, _ = s.image(pops, 0, 1, v)
+    assert rel(I, I_in[1]).max() < 1e-14
+    assert rel(I, o.image(pops, 0, 1, v, points=[0])[0]).max() <= 1e-12
     pb, rb = s.run_ali()
     assert ra["iterations"] == rb["iterations"] == 5
     assert rel(pa, pb).max() < 1e-13
