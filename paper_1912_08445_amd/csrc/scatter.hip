@@ -20,8 +20,13 @@
 // one lane per frequency (n_q <= 256 lanes).  Each lane
 // eliminates both halves of every ray pair from the far ends toward the origin in the
 // division-free scaled state of the line formal solve (n, d, y~ with node coefficients
-// chi dz/(2 sqrt 2)), FP64 with a direct exponential at every node, and combines them at
-// the origin.  Besides J, L* (times chi_line/chi_t) and Jeff it returns J_nu at the
+// chi dz/(2 sqrt 2)) in FP64, and combines them at the origin.  The block stages up to 24
+// nodes of a half ray at a time in LDS (cell records, the lines' coefficients, their J_nu
+// rows, and the sub-step segments between them).  Inside a sub-step segment the line
+// profile follows the multiplicative recurrence of the line formal solve (exact restarts
+// after at most 16 widths of travel) and, on an evenly spaced quadrature, the position
+// of +-y advances by a constant; the state is renormalised at every cell node and every
+// fourth sub-step.  Besides J, L* (times chi_line/chi_t) and Jeff it returns J_nu at the
 // quadrature offsets from u and the flux-like v at the origin: I(n, x) = u(x) + v(x) and
 // I(-n, x) = u(-x) - v(-x) for the pair representative n.
 #include "nlte_internal.h"
@@ -32,27 +37,20 @@ namespace nlte {
 namespace {
 
 constexpr int kScatMaxQ = 256;
+constexpr int kChunk = 24;   // nodes staged per round
 constexpr double kSq2 = 1.41421356237309504880;
 constexpr double kISq2 = 0.70710678118654752440;
 
-// Position of offset y on the quadrature: J(y) = row[i0] + t (row[i1] - row[i0]) with
-// qx[i0] <= y < qx[i1], or i0 = i1 at the outermost offset beyond which J is constant.
+// Position of offset y on an arbitrary ascending quadrature: J(y) = row[i0] + t (row[i1] -
+// row[i0]) with qx[i0] <= y < qx[i1], or i0 = i1 at the outermost offset beyond which J is
+// constant (bisection).
 struct QPos {
     int i0, i1;
     double t;
 };
 
-struct QGrid {
-    const double *qx;   // in LDS
-    int nq;
-    bool uniform;       // evenly spaced: direct index, then at most a step of fix-up
-    double x0, inv_h;
-};
-
-__device__ inline QPos locate(const QGrid &g, double y)
+__device__ inline QPos locate(const double *qx, int nq, double y)
 {
-    const double *qx = g.qx;
-    const int nq = g.nq;
     QPos p;
     if (!(y > qx[0])) {   // also a NaN offset: no read outside the row
         p.i0 = p.i1 = 0;
@@ -64,72 +62,127 @@ __device__ inline QPos locate(const QGrid &g, double y)
         p.t = 0.0;
         return p;
     }
-    int lo;
-    if (g.uniform) {
-        lo = (int)floor((y - g.x0) * g.inv_h);
-        lo = lo < 0 ? 0 : (lo > nq - 2 ? nq - 2 : lo);
-        while (lo > 0 && qx[lo] > y) --lo;
-        while (lo < nq - 2 && qx[lo + 1] <= y) ++lo;
-    } else {
-        lo = 0;
-        int hi = nq - 1;   // qx[lo] <= y < qx[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (qx[mid] <= y)
-                lo = mid;
-            else
-                hi = mid;
-        }
+    int lo = 0, hi = nq - 1;   // qx[lo] <= y < qx[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (qx[mid] <= y)
+            lo = mid;
+        else
+            hi = mid;
     }
     p.i0 = lo;
     p.i1 = lo + 1;
-    p.t = g.uniform ? (y - qx[lo]) * g.inv_h : (y - qx[lo]) / (qx[lo + 1] - qx[lo]);
+    p.t = (y - qx[lo]) / (qx[lo + 1] - qx[lo]);
     return p;
 }
 
-__device__ inline double j_at(const double *__restrict__ row, const QPos &p)
+__device__ __forceinline__ double j_at(const double *__restrict__ row, const QPos &p)
 {
     const double r0 = row[p.i0];
     return r0 + p.t * (row[p.i1] - r0);
 }
 
-// Base node of a half sweep in the walk frame of its ray.
-struct Base {
-    double Z, s, vw, a, b, kap, S, cs;
-    const double *jrow;
+// Evenly spaced quadrature (n_q >= 2): u = (y - x_0)/h in grid steps, clamped to
+// [0, n_q - 1]; J(y) = row[i] + (u - i)(row[i+1] - row[i]) with i = min(floor u, n_q - 2).
+// The offset -y sits at n_q - 1 - u on the symmetric grid.
+struct UPair {
+    int ip, im;
+    double tp, tm;
 };
 
-__device__ inline Base base_node(const ScatArgs &a, const CellRec &cO, int64_t c, double nx, double ny, double nz,
-                                 int line)
+__device__ __forceinline__ UPair upos(double u, double top, int lo_max)
 {
-    const CellRec cc = a.cell[c];
-    Base d;
-    const double dx = cc.px - cO.px, dy = cc.py - cO.py, dz = cc.pz - cO.pz;
-    d.Z = (dx * nx + dy * ny) + dz * nz;
-    const double dvx = cc.vx - cO.vx, dvy = cc.vy - cO.vy, dvz = cc.vz - cO.vz;
-    d.s = (dvx * nx + dvy * ny) + dvz * nz;
-    d.vw = cc.vw;
-    d.a = cO.vw / cc.vw;
-    d.b = d.s / cc.vw;
-    const double2 lc = reinterpret_cast<const double2 *>(a.lc)[c * a.n_lines + line];
-    d.kap = lc.x;
-    d.S = lc.y;
-    d.cs = a.chi_sca[c * a.n_lines + line];
-    d.jrow = a.Jin + (c * a.n_lines + line) * a.n_q;
-    return d;
+    double uc = u > 0.0 ? u : 0.0;   // also a NaN position: no read outside the row
+    uc = uc < top ? uc : top;
+    UPair q;
+    q.ip = min((int)uc, lo_max);
+    q.tp = uc - (double)q.ip;
+    const double um = top - uc;
+    q.im = min((int)um, lo_max);
+    q.tm = um - (double)q.im;
+    return q;
 }
+
+__device__ __forceinline__ double j_u(const double *__restrict__ row, int i, double t)
+{
+    const double r0 = row[i];
+    return r0 + t * (row[i + 1] - r0);
+}
+
+// Quadrature geometry for the lookups.
+struct QGeo {
+    const double *qx;   // in LDS
+    int nq, lo_max;
+    double top, x0, inv_h;
+};
+
+// J(y) and J(-y) of one row.
+template <bool UNI>
+__device__ __forceinline__ void j_node(const QGeo &g, const double *row, double y, double &jp, double &jm)
+{
+    if constexpr (UNI) {
+        const UPair q = upos((y - g.x0) * g.inv_h, g.top, g.lo_max);
+        jp = j_u(row, q.ip, q.tp);
+        jm = j_u(row, q.im, q.tm);
+    } else {
+        jp = j_at(row, locate(g.qx, g.nq, y));
+        jm = j_at(row, locate(g.qx, g.nq, -y));
+    }
+}
+
+// J(y) and J(-y) at a sub-step node: the two end cells' rows at the node's own offset,
+// interpolated linearly at fraction tt of the segment.
+template <bool UNI>
+__device__ __forceinline__ void j_sub(const QGeo &g, const double *rp, const double *rq, double y, double tt,
+                                      double &jp, double &jm)
+{
+    double ap, bp, am, bm;
+    if constexpr (UNI) {
+        const UPair q = upos((y - g.x0) * g.inv_h, g.top, g.lo_max);
+        ap = j_u(rp, q.ip, q.tp);
+        bp = j_u(rq, q.ip, q.tp);
+        am = j_u(rp, q.im, q.tm);
+        bm = j_u(rq, q.im, q.tm);
+    } else {
+        const QPos lp = locate(g.qx, g.nq, y), lm = locate(g.qx, g.nq, -y);
+        ap = j_at(rp, lp);
+        bp = j_at(rq, lp);
+        am = j_at(rp, lm);
+        bm = j_at(rq, lm);
+    }
+    jp = ap + tt * (bp - ap);
+    jm = am + tt * (bm - am);
+}
+
+// Staged node of a half ray in sweep order (far end first, O last): projection Z, projected
+// velocity s and line-width speed relative to O, Doppler coefficients y = a x - b, and per
+// line slot the line-centre opacity, source function, scattering opacity and J_nu row.
+struct SNode {
+    double Z, s, vw, a, b;
+    double kap[2], S[2], cs[2];
+    const double *jrow[2];
+};
+
+// Segment from a staged node to the next: m sub-intervals of optical-depth weight
+// hz = (Z - Z_next)/(2 sqrt 2 m), per sub-interval increments of the Doppler coefficients
+// and of kappa, S and chi_s; maxdx bounds |dy| over the quadrature, K is the restart
+// interval of the profile recurrence (0: direct evaluation).
+struct SSeg {
+    double hz, da, db, im, maxdx;
+    double dk[2], dS[2], dcs[2];
+    int m, K;
+};
 
 // Node quantities at the lane's frequency: total opacity, S+ and sigma~.
 struct NodeVal {
-    double Z, chit, Sp, sg;
+    double chit, Sp, sg;
 };
 
 // S+ = S + r (Jbar - S) and sigma~ = r (J(-y) - J(y))/2 with r = chi_s/chi_t, the
-// scattering share (one division, safe for denormal far-wing opacities).
-__device__ inline NodeVal node_val(double Z, double cl, double cs, double S, double jp, double jm)
+// scattering share (safe for denormal far-wing opacities).
+__device__ __forceinline__ NodeVal node_val(double cl, double cs, double S, double jp, double jm)
 {
     NodeVal v;
-    v.Z = Z;
     v.chit = cl + cs;
     const double r = cs > 0.0 ? cs * rcp_refined(v.chit) : 0.0;   // chit >= cs > 0
     v.Sp = v.chit > 0.0 ? S + r * (0.5 * (jp + jm) - S) : 0.0;
@@ -137,100 +190,281 @@ __device__ inline NodeVal node_val(double Z, double cl, double cs, double S, dou
     return v;
 }
 
-__device__ inline NodeVal eval_base(const Base &d, double x, const QGrid &g)
-{
-    const double y = d.a * x - d.b;
-    const double cl = d.kap * exp(-(y * y));
-    const double jp = j_at(d.jrow, locate(g, y)), jm = j_at(d.jrow, locate(g, -y));
-    return node_val(d.Z, cl, d.cs, d.S, jp, jm);
-}
+// e^{-y^2}, clamped where the result is 0 in FP64 anyway.
+__device__ __forceinline__ double profile(double y) { return exp_le700(fmax(-(y * y), -800.0)); }
 
-// Sub-step node at fraction t from base p toward base q.
-__device__ inline NodeVal eval_sub(const Base &p, const Base &q, double t, double x, const QGrid &g)
-{
-    const double aa = p.a + t * (q.a - p.a), bb = p.b + t * (q.b - p.b);
-    const double y = aa * x - bb;
-    const double cl = (p.kap + t * (q.kap - p.kap)) * exp(-(y * y));
-    const double cs = (1.0 - t) * p.cs + t * q.cs;
-    const double S = p.S + t * (q.S - p.S);
-    const QPos lp = locate(g, y), lm = locate(g, -y);
-    const double jp = (1.0 - t) * j_at(p.jrow, lp) + t * j_at(q.jrow, lp);
-    const double jm = (1.0 - t) * j_at(p.jrow, lm) + t * j_at(q.jrow, lm);
-    return node_val(p.Z + t * (q.Z - p.Z), cl, cs, S, jp, jm);
-}
-
-// Elimination state of a half sweep; `prev` is the last node reached.
+// Elimination state of a half sweep and the last node reached (chit, Sp, sg), with sg_pp
+// the sigma~ of the node before it (a virtual -sigma~ at the far end).
 struct HalfState {
     double n, d, y, Pm;
-    NodeVal prev;
-    double sg_pp;   // sigma~ of the node before prev (virtual -sigma~ at the far end)
+    double chit, Sp, sg, sg_pp;
 };
 
-__device__ inline void start(HalfState &h, const NodeVal &first, double I_in)
+__device__ __forceinline__ void start(HalfState &h, const NodeVal &first, double I_in)
 {
     h.n = kSq2;
     h.d = 1.0;
     h.y = kSq2 * I_in;
     h.Pm = 0.0;
-    h.prev = first;
+    h.chit = first.chit;
+    h.Sp = first.Sp;
+    h.sg = first.sg;
     h.sg_pp = -first.sg;
 }
 
-// Eliminate h.prev, stepping to node cur.
-__device__ inline void step(HalfState &h, const NodeVal &cur)
+// Eliminate the last node, stepping to node v over a sub-interval of weight hz.
+template <bool RENORM>
+__device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
 {
-    const double P = 0.5 * (h.prev.chit + cur.chit) * (h.prev.Z - cur.Z) * kISq2;
+    const double P = (h.chit + v.chit) * hz;
     const double hd = (h.Pm + P) * h.d;
     h.n += hd;
-    h.y = h.y + h.prev.Sp * hd - (cur.sg - h.sg_pp) * h.d * kISq2;
+    h.y = h.y + h.Sp * hd - (v.sg - h.sg_pp) * h.d * kISq2;
     h.d = fma(P, h.n, h.d);
     h.Pm = P;
-    const int ex = __builtin_amdgcn_frexp_exp(h.d);
-    h.n = ldexp(h.n, -ex);
-    h.d = ldexp(h.d, -ex);
-    h.y = ldexp(h.y, -ex);
-    h.sg_pp = h.prev.sg;
-    h.prev = cur;
+    h.sg_pp = h.sg;
+    h.chit = v.chit;
+    h.Sp = v.Sp;
+    h.sg = v.sg;
+    if (RENORM) {
+        const int ex = __builtin_amdgcn_frexp_exp(h.d);
+        h.n = ldexp(h.n, -ex);
+        h.d = ldexp(h.d, -ex);
+        h.y = ldexp(h.y, -ex);
+    }
 }
 
-// Half sweep along `ray` (lane offset x in that ray's frame) from the far end of its
-// walk to O; on return h.prev is O's node.
-__device__ inline void half(const ScatArgs &a, const QGrid &g, int64_t O, const CellRec &cO, int ray, double x,
-                            int line, double I_in, HalfState &h)
+// Running values of a lane inside a recurrence segment.
+struct SubRun {
+    double g, r, kq, cs, S, y, tt;
+};
+
+template <bool UNI, bool RENORM>
+__device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, double dk, double dcs, double dS,
+                                         double dy, double im, const QGeo &qg, const double *rp, const double *rq,
+                                         double hz)
 {
+    w.g *= w.r;
+    w.r *= c;
+    w.kq += dk;
+    w.cs += dcs;
+    w.S += dS;
+    w.y += dy;
+    w.tt += im;
+    double jp, jm;
+    j_sub<UNI>(qg, rp, rq, w.y, w.tt, jp, jm);
+    step<RENORM>(h, node_val(w.kq * w.g, w.cs, w.S, jp, jm), hz);
+}
+
+// Half sweep along `ray` (lane offset x in that ray's frame, line slot gs of the `per`
+// staged lines line0 ..) from the far end of its walk to O; on return h holds O's node.
+// jr receives the staged nodes' J_nu rows, [node][slot][n_q].
+template <bool UNI>
+__device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, double *jr, int per, int64_t O,
+                     const CellRec &cO, int ray, double x, int line0, int gs, double I_in, double xq_max,
+                     HalfState &h)
+{
+    const int t = threadIdx.x;
     const double nx = a.dir[3 * ray], ny = a.dir[3 * ray + 1], nz = a.dir[3 * ray + 2];
-    const int64_t beg = a.roff[O * a.n_rays + ray], end = a.roff[O * a.n_rays + ray + 1];
-    Base prev = base_node(a, cO, end > beg ? (int64_t)a.rcells[end - 1] : O, nx, ny, nz, line);
-    start(h, eval_base(prev, x, g), I_in);
-    for (int64_t i = end - 1; i >= beg; --i) {
-        const Base cur = base_node(a, cO, i > beg ? (int64_t)a.rcells[i - 1] : O, nx, ny, nz, line);
-        // velocity sub-steps (Sec. 3.2): split when the projected velocity changes by more
-        // than f_sub of the smaller line-width speed
-        const double ds = fabs(cur.s - prev.s);
-        const double thr = a.f_sub * fmin(prev.vw, cur.vw);
-        int m = 1;
-        if (ds > thr) {
-            const double mr = ceil(ds / thr);
-            m = mr < (double)kMaxSub ? (int)mr : kMaxSub;
+    const int64_t beg = a.roff[O * a.n_rays + ray];
+    const int L = (int)(a.roff[O * a.n_rays + ray + 1] - beg);   // cells; nodes 0 .. L (O)
+    const double2 *lc = reinterpret_cast<const double2 *>(a.lc);
+    double y_cur = 0.0, g_cur = 0.0, kap_cur = 0.0, cs_cur = 0.0, S_cur = 0.0, travel = 0.0;
+    const double *row_cur = nullptr;
+    for (int b0 = 0;; b0 += kChunk - 1) {
+        __syncthreads();
+        // ---- stage nodes b0 .. b0 + kChunk - 1
+        const int sidx = b0 + t;
+        if (t < kChunk && sidx <= L) {
+            const int64_t c = sidx < L ? (int64_t)a.rcells[beg + (L - 1 - sidx)] : O;
+            const CellRec cc = a.cell[c];
+            SNode v;
+            const double dx = cc.px - cO.px, dy = cc.py - cO.py, dz = cc.pz - cO.pz;
+            v.Z = (dx * nx + dy * ny) + dz * nz;
+            const double dvx = cc.vx - cO.vx, dvy = cc.vy - cO.vy, dvz = cc.vz - cO.vz;
+            v.s = (dvx * nx + dvy * ny) + dvz * nz;
+            v.vw = cc.vw;
+            v.a = cO.vw / cc.vw;
+            v.b = v.s / cc.vw;
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const int ln = min(line0 + l, a.n_lines - 1);
+                const double2 k = lc[c * a.n_lines + ln];
+                v.kap[l] = k.x;
+                v.S[l] = k.y;
+                v.cs[l] = a.chi_sca[c * a.n_lines + ln];
+                v.jrow[l] = a.Jin + (c * a.n_lines + ln) * a.n_q;
+            }
+            nd[t] = v;
         }
-        if (m > 1) {
-            const double inv_m = 1.0 / (double)m;
-            for (int j = 1; j < m; ++j) step(h, eval_sub(prev, cur, (double)j * inv_m, x, g));
+        __syncthreads();
+        if (t < kChunk - 1 && sidx < L) {
+            const SNode &p = nd[t], &q = nd[t + 1];
+            // velocity sub-steps (Sec. 3.2): split when the projected velocity changes by
+            // more than f_sub of the smaller line-width speed
+            const double ds = fabs(q.s - p.s);
+            const double thr = a.f_sub * fmin(p.vw, q.vw);
+            int m = 1;
+            if (ds > thr) {
+                const double mr = ceil(ds / thr);
+                m = mr < (double)kMaxSub ? (int)mr : kMaxSub;
+            }
+            SSeg e;
+            e.m = m;
+            e.im = 1.0 / (double)m;
+            e.hz = 0.5 * kISq2 * (p.Z - q.Z) * e.im;
+            e.da = (q.a - p.a) * e.im;
+            e.db = (q.b - p.b) * e.im;
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                e.dk[l] = (q.kap[l] - p.kap[l]) * e.im;
+                e.dS[l] = (q.S[l] - p.S[l]) * e.im;
+                e.dcs[l] = (q.cs[l] - p.cs[l]) * e.im;
+            }
+            e.maxdx = (fabs(q.a - p.a) * xq_max + fabs(q.b - p.b)) * e.im;
+            e.K = e.maxdx > 4.0 ? 0 : (e.maxdx > 0.25 ? (int)(16.0 / e.maxdx) : 64);
+            sgm[t] = e;
         }
-        step(h, eval_base(cur, x, g));
-        prev = cur;
+        {
+            // the staged nodes' J_nu rows, read row by row
+            const int nst = min(kChunk, L - b0 + 1);
+            const int rl = per * a.n_q;
+            for (int idx = t; idx < nst * rl; idx += (int)blockDim.x) {
+                const int node = idx / rl;
+                const int rest = idx - node * rl;
+                const int slot = rest / a.n_q;
+                jr[idx] = nd[node].jrow[slot][rest - slot * a.n_q];
+            }
+        }
+        __syncthreads();
+        // ---- sweep the staged segments
+        row_cur = jr + gs * a.n_q;   // node 0 of the chunk
+        if (b0 == 0) {
+            y_cur = nd[0].a * x - nd[0].b;
+            g_cur = profile(y_cur);
+            kap_cur = nd[0].kap[gs];
+            cs_cur = nd[0].cs[gs];
+            S_cur = nd[0].S[gs];
+            double jp, jm;
+            j_node<UNI>(qg, row_cur, y_cur, jp, jm);
+            start(h, node_val(kap_cur * g_cur, cs_cur, S_cur, jp, jm), I_in);
+        }
+        const int nseg = min(kChunk - 1, L - b0);
+        for (int i = 0; i < nseg; ++i) {
+            const int m = sgm[i].m;
+            const double hz = sgm[i].hz;
+            const double kap_n = nd[i + 1].kap[gs], cs_n = nd[i + 1].cs[gs], S_n = nd[i + 1].S[gs];
+            const double *row_n = jr + ((i + 1) * per + gs) * a.n_q;
+            const double y_n = nd[i + 1].a * x - nd[i + 1].b;
+            double g_n;
+            if (m == 1) {
+                g_n = profile(y_n);
+                travel = 0.0;
+            } else {
+                const double dy = sgm[i].da * x - sgm[i].db;
+                const double dk = sgm[i].dk[gs], dS = sgm[i].dS[gs], dcs = sgm[i].dcs[gs], im = sgm[i].im;
+                const double mdx = sgm[i].maxdx;
+                const int K = sgm[i].K;
+                if (K == 0 || m == 2) {
+                    for (int j = 1; j < m; ++j) {
+                        const double fj = (double)j;
+                        const double yj = fma(fj, dy, y_cur);
+                        double jp, jm;
+                        j_sub<UNI>(qg, row_cur, row_n, yj, fj * im, jp, jm);
+                        step<true>(h, node_val(fma(fj, dk, kap_cur) * profile(yj), fma(fj, dcs, cs_cur),
+                                               fma(fj, dS, S_cur), jp, jm), hz);
+                    }
+                    g_n = profile(y_n);
+                    travel = 0.0;
+                } else {
+                    // g_{j+1} = g_j r_j, r_{j+1} = r_j c with r_j = e^{-2 y_j dy - dy^2} and
+                    // c = e^{-2 dy^2}; exact values again whenever y may have moved by more
+                    // than 16 widths since the last exact one, so that an underflowed value
+                    // (|y| > 27) cannot hide a profile above e^{-121}
+                    const double u2 = 2.0 * dy * dy;
+                    const double c = mdx <= 0.5 ? exp_neg_small(u2) : exp_le700(-u2);
+                    SubRun w;
+                    w.g = g_cur;
+                    w.r = exp_le700(fmax(fmin(-(2.0 * y_cur + dy) * dy, 700.0), -800.0));
+                    w.kq = kap_cur;
+                    w.cs = cs_cur;
+                    w.S = S_cur;
+                    w.y = y_cur;
+                    w.tt = 0.0;
+                    int budget = K;
+                    if (mdx > 0.0) budget = (int)fmin((16.0 - travel) / mdx, (double)K);
+                    if (budget < 1) {
+                        w.g = profile(y_cur);
+                        travel = 0.0;
+                        budget = K;
+                    }
+                    int j = 0;
+                    for (;;) {
+                        const int jend = min(j + budget, m);
+                        const int jint = min(jend, m - 1);
+                        int jj = j;
+                        for (; jj + 3 < jint; jj += 4) {
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, true>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                        }
+                        // the last 0-3 steps; the cell node's step that follows renormalises,
+                        // so at most seven steps pass between renormalisations
+                        const int rem = jint - jj;
+                        if (rem >= 2) {
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                        }
+                        if (rem & 1) sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                        travel += mdx * (double)(jint - j);
+                        j = jint;
+                        if (jend == m) {
+                            w.g *= w.r;   // the cell node at the end of the segment
+                            travel += mdx;
+                            break;
+                        }
+                        const double fj = (double)j;
+                        w.y = fma(fj, dy, y_cur);
+                        w.g = profile(w.y);
+                        w.r = exp_le700(fmax(fmin(-(2.0 * w.y + dy) * dy, 700.0), -800.0));
+                        w.kq = fma(fj, dk, kap_cur);
+                        w.cs = fma(fj, dcs, cs_cur);
+                        w.S = fma(fj, dS, S_cur);
+                        w.tt = fj * im;
+                        travel = 0.0;
+                        budget = K;
+                    }
+                    g_n = w.g;
+                }
+            }
+            double jp, jm;
+            j_node<UNI>(qg, row_n, y_n, jp, jm);
+            step<true>(h, node_val(kap_n * g_n, cs_n, S_n, jp, jm), hz);
+            y_cur = y_n;
+            g_cur = g_n;
+            kap_cur = kap_n;
+            cs_cur = cs_n;
+            S_cur = S_n;
+            row_cur = row_n;
+        }
+        if (b0 + kChunk - 1 >= L) break;
     }
 }
 
 }  // namespace
 
+template <bool UNI>
 __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
 {
-    __shared__ double s_qx[kScatMaxQ];
-    __shared__ double s_red[3][kScatMaxQ];
-    __shared__ double s_jp[kScatMaxQ], s_jm[kScatMaxQ];
+    extern __shared__ double smem[];
     // lanes: with n_q <= 32 two lines per wave (lanes 32 g + frequency), else one line
-    const int nq = a.n_q, t = threadIdx.x;
+    const int nq = a.n_q, t = threadIdx.x, nt = blockDim.x;
+    double *s_qx = smem;
+    SNode *nd = reinterpret_cast<SNode *>(smem + nq);
+    SSeg *sgm = reinterpret_cast<SSeg *>(nd + kChunk);
+    double *jr = reinterpret_cast<double *>(sgm + kChunk);   // [kChunk][per][n_q]
+    double *s_red = smem + nq;   // after the sweeps: [5][nt] over the staging area
     const int per = nq <= 32 ? 2 : 1;
     const int groups = (a.n_lines + per - 1) / per;
     const int64_t O = blockIdx.x / groups;
@@ -248,12 +482,14 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
     }
     if (t < nq) s_qx[t] = a.qx[t];
     __syncthreads();
-    QGrid qg;
+    QGeo qg;
     qg.qx = s_qx;
     qg.nq = nq;
-    qg.uniform = a.q_uniform != 0;
+    qg.lo_max = nq - 2;
+    qg.top = (double)(nq - 1);
     qg.x0 = s_qx[0];
     qg.inv_h = a.q_inv_h;
+    const double xq_max = fmax(fabs(s_qx[0]), fabs(s_qx[nq - 1]));
     const double x = fi < nq ? s_qx[fi] : 0.0;
     const double w = act ? a.qw[fi] : 0.0;
     const CellRec cO = a.cell[O];
@@ -263,48 +499,49 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
     for (int p = 0; p < a.n_pairs; ++p) {
         const int r = a.pair_r[p], rb = a.anti[r];
         HalfState f, b;
-        half(a, qg, O, cO, r, x, lc_line, I_in, f);
-        half(a, qg, O, cO, rb, -x, lc_line, I_in, b);
+        half<UNI>(a, qg, nd, sgm, jr, per, O, cO, r, x, line0, g, I_in, xq_max, f);
+        half<UNI>(a, qg, nd, sgm, jr, per, O, cO, rb, -x, line0, g, I_in, xq_max, b);
         // combine at O: h u + (Q_f u - y_f) + (Q_b u - y_b) = h R_O (scaled rows)
         const double idf = 1.0 / f.d, idb = 1.0 / b.d;
         const double h = f.Pm + b.Pm;
         const double yy = f.y * idf + b.y * idb;
         const double sgO = (f.sg_pp + b.sg_pp) * kISq2;
         const double inv = 1.0 / (h + f.n * idf + b.n * idb);
-        const double u = (h * f.prev.Sp + yy + sgO) * inv;
+        const double u = (h * f.Sp + yy + sgO) * inv;
         // line part of O's own source, for L* and Jeff (Eq. ALO)
         const double clO = lcO.x * exp_le700(-(x * x));
-        const double ratio = f.prev.chit > 0.0 ? clO / f.prev.chit : 1.0;   // all of it without opacity
+        const double ratio = f.chit > 0.0 ? clO / f.chit : 1.0;   // all of it without opacity
         accJ += w * u;
         accL += w * (h * inv) * ratio;
-        accE += w * ((h * (f.prev.Sp - ratio * lcO.y) + yy + sgO) * inv);
+        accE += w * ((h * (f.Sp - ratio * lcO.y) + yy + sgO) * inv);
         // v along n = ray r: the half-node fluxes (u_O - u_nb)/dtau on each side from the
         // elimination state, with sigma at the half nodes, interpolated in tau to O
-        const double fl_f = (f.n * u - f.y) * idf * kISq2 - 0.5 * (f.sg_pp + f.prev.sg);
-        const double fl_b = (b.n * u - b.y) * idb * kISq2 - 0.5 * (b.sg_pp + b.prev.sg);
+        const double fl_f = (f.n * u - f.y) * idf * kISq2 - 0.5 * (f.sg_pp + f.sg);
+        const double fl_b = (b.n * u - b.y) * idb * kISq2 - 0.5 * (b.sg_pp + b.sg);
         const double v = h > 0.0 ? (b.Pm * fl_f - f.Pm * fl_b) / h : 0.5 * (fl_f - fl_b);
         jp += u + v;
         jm += u - v;
     }
-    s_red[0][t] = act ? accJ : 0.0;
-    s_red[1][t] = act ? accL : 0.0;
-    s_red[2][t] = act ? accE : 0.0;
-    s_jp[t] = jp;
-    s_jm[t] = jm;
+    __syncthreads();   // the staging area becomes the reduction area
+    s_red[t] = act ? accJ : 0.0;
+    s_red[nt + t] = act ? accL : 0.0;
+    s_red[2 * nt + t] = act ? accE : 0.0;
+    s_red[3 * nt + t] = jp;
+    s_red[4 * nt + t] = jm;
     __syncthreads();
     const int base = 32 * g;
     if (fi == 0 && line < a.n_lines) {
         double sJ = 0.0, sL = 0.0, sE = 0.0;
         for (int i = 0; i < nq; ++i) {
-            sJ += s_red[0][base + i];
-            sL += s_red[1][base + i];
-            sE += s_red[2][base + i];
+            sJ += s_red[base + i];
+            sL += s_red[nt + base + i];
+            sE += s_red[2 * nt + base + i];
         }
         a.J[row] = a.norm * sJ;
         a.L[row] = a.norm * sL;
         a.Jeff[row] = a.norm * sE;
     }
-    if (act) a.Jout[row * nq + fi] = (s_jp[t] + s_jm[base + nq - 1 - fi]) * a.inv_rays;
+    if (act) a.Jout[row * nq + fi] = (s_red[3 * nt + t] + s_red[4 * nt + base + nq - 1 - fi]) * a.inv_rays;
 }
 
 // J_nu of the first scattering iteration: the boundary intensity of each line everywhere.
@@ -327,10 +564,17 @@ hipError_t launch_formal_solve_scat(const ScatArgs &a, hipStream_t s)
 {
     if (a.P == 0) return hipSuccess;
     if (a.n_q < 1 || a.n_q > kScatMaxQ) return hipErrorInvalidValue;
+    if (a.q_uniform && a.n_q < 2) return hipErrorInvalidValue;
     const int per = a.n_q <= 32 ? 2 : 1;
     const int threads = per == 2 ? kWave : (a.n_q + kWave - 1) / kWave * kWave;
     const int64_t groups = (a.n_lines + per - 1) / per;
-    hipLaunchKernelGGL(k_formal_solve_scat, dim3((unsigned)(a.P * groups)), dim3(threads), 0, s, a);
+    const size_t stage = kChunk * (sizeof(SNode) + sizeof(SSeg) + sizeof(double) * (size_t)per * a.n_q);
+    const size_t red = 5 * sizeof(double) * (size_t)threads;
+    const size_t shmem = sizeof(double) * (size_t)a.n_q + (stage > red ? stage : red);
+    if (a.q_uniform)
+        hipLaunchKernelGGL(k_formal_solve_scat<true>, dim3((unsigned)(a.P * groups)), dim3(threads), shmem, s, a);
+    else
+        hipLaunchKernelGGL(k_formal_solve_scat<false>, dim3((unsigned)(a.P * groups)), dim3(threads), shmem, s, a);
     return hipGetLastError();
 }
 
