@@ -83,8 +83,10 @@ __device__ __forceinline__ double j_at(const double *__restrict__ row, const QPo
 }
 
 // Evenly spaced quadrature (n_q >= 2): u = (y - x_0)/h in grid steps, clamped to
-// [0, n_q - 1]; J(y) = row[i] + (u - i)(row[i+1] - row[i]) with i = min(floor u, n_q - 2).
-// The offset -y sits at n_q - 1 - u on the symmetric grid.
+// [0, n_q - 1]; J(y) = row[i] + t (row[i+1] - row[i]) with i = min(floor u, n_q - 2) and
+// t = u - i.  On the symmetric grid -y sits at n_q - 1 - u, which is interval n_q - 2 - i
+// at fraction 1 - t (the same value as its own floor at a knot, where the interpolant is
+// continuous, and the grid's end values at the clamped ends).
 struct UPair {
     int ip, im;
     double tp, tm;
@@ -92,14 +94,12 @@ struct UPair {
 
 __device__ __forceinline__ UPair upos(double u, double top, int lo_max)
 {
-    double uc = u > 0.0 ? u : 0.0;   // also a NaN position: no read outside the row
-    uc = uc < top ? uc : top;
+    const double uc = fmin(fmax(u, 0.0), top);   // a NaN position becomes 0: no read outside the row
     UPair q;
     q.ip = min((int)uc, lo_max);
     q.tp = uc - (double)q.ip;
-    const double um = top - uc;
-    q.im = min((int)um, lo_max);
-    q.tm = um - (double)q.im;
+    q.im = lo_max - q.ip;
+    q.tm = 1.0 - q.tp;
     return q;
 }
 
