@@ -1231,14 +1231,14 @@ nlte_status nlte_set_quadrature(nlte_ctx *c, int n_q, const double *x, const dou
     c->q_ascending = true;
     for (int n = 0; n + 1 < n_q; ++n)
         if (!(x[n] < x[n + 1])) c->q_ascending = false;
-    // evenly spaced offsets let the scattering solve index the grid directly (it then
-    // checks the interval against the offsets themselves)
+    // offsets evenly spaced to 1e-12 of the spacing let the scattering solve locate an
+    // offset by its arithmetic position on the grid; other grids are searched by bisection
     c->q_uniform = false;
     if (c->q_ascending && n_q > 1) {
         const double h = (x[n_q - 1] - x[0]) / (double)(n_q - 1);
         bool even = true;
         for (int n = 0; n < n_q; ++n)
-            if (fabs(x[n] - (x[0] + n * h)) > 1e-9 * h) even = false;
+            if (fabs(x[n] - (x[0] + n * h)) > 1e-12 * h) even = false;
         c->q_uniform = even;
         c->q_inv_h = 1.0 / h;
     }
