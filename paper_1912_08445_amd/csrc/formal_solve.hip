@@ -132,6 +132,13 @@ __device__ __forceinline__ float profile(float x)
     return __builtin_amdgcn_exp2f(-(x * x) * 1.44269504088896340736f);
 }
 
+// e^{-x^2} at a node of a wave's sweep (uniform control flow).  Beyond x^2 = 746 the FP64
+// value above is exactly 0, so where every lane of the wave is that far in the wing the
+// exponential is skipped without changing any result.  (The FP32 exponential is cheaper
+// than the vote and branch, measured.)
+__device__ __forceinline__ double profile_far(double x) { return __all(x * x > 746.0) ? 0.0 : profile(x); }
+__device__ __forceinline__ float profile_far(float x) { return profile(x); }
+
 // One elimination step.  The Rybicki-Hummer update with h = (D_- + D_+)/2 (mean of the
 // trapezoid optical depths D_-, D_+ on either side of the node)
 //   T = h + Q,  E = 1/(1 + D_+ T),  Q' = T E,  y' = (S h + y) E
@@ -314,7 +321,7 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
             }
             T gn;
             if (m == 1) {
-                gn = profile(xn);
+                gn = profile_far(xn);
                 travel = 0.0;
             } else {
                 const T im = rec[i].inv_m;
@@ -332,13 +339,13 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                     }
                     for (int j = 1; j < m; ++j) {
                         const T tj = (T)j;
-                        const T gq = profile(x_cur + tj * dx) * dzq;
+                        const T gq = profile_far(x_cur + tj * dx) * dzq;
 #pragma unroll
                         for (int l = 0; l < LPL; ++l)
                             elim_step<F32, true, TRACK>((ls.k_cur[l] + tj * dk[l]) * gq, S0[l] + tj * dS[l], a_prev[l],
                                                  ls.S_e[l], ls.st[l]);
                     }
-                    gn = profile(xn);
+                    gn = profile_far(xn);
                     travel = 0.0;
                 } else {
                     // x is linear in the sub-step index j, so g_j = e^{-x_j^2} obeys
