@@ -12,9 +12,10 @@
 // and the interior rows of the second-order system gain -d sigma/dtau as the central
 // difference over the two neighbours; the boundary rows gain the half-node value of sigma.
 // J(y) is linear in y between the quadrature offsets (constant beyond them; the offset is
-// located once for both end cells of a sub-step segment, by direct index on an evenly
-// spaced quadrature and by bisection otherwise); velocity
+// located once for both end cells of a sub-step segment, by its arithmetic position on an
+// evenly spaced quadrature, where -y mirrors +y, and by bisection otherwise); velocity
 // sub-steps interpolate chi_s and the end cells' J linearly in t at their own offset.
+// The elimination carries sigma~ / sqrt 2, the form in which it enters the scaled rows.
 //
 // One workgroup per point and line (two lines, in lanes 0-31 and 32-63, when n_q <= 32),
 // one lane per frequency (n_q <= 256 lanes).  Each lane
@@ -79,7 +80,7 @@ __device__ inline QPos locate(const double *qx, int nq, double y)
 __device__ __forceinline__ double j_at(const double *__restrict__ row, const QPos &p)
 {
     const double r0 = row[p.i0];
-    return r0 + p.t * (row[p.i1] - r0);
+    return fma(p.t, row[p.i1] - r0, r0);
 }
 
 // Evenly spaced quadrature (n_q >= 2): u = (y - x_0)/h in grid steps, clamped to
@@ -106,52 +107,64 @@ __device__ __forceinline__ UPair upos(double u, double top, int lo_max)
 __device__ __forceinline__ double j_u(const double *__restrict__ row, int i, double t)
 {
     const double r0 = row[i];
-    return r0 + t * (row[i + 1] - r0);
+    return fma(t, row[i + 1] - r0, r0);
 }
 
 // Quadrature geometry for the lookups.
 struct QGeo {
     const double *qx;   // in LDS
     int nq, lo_max;
-    double top, x0, inv_h;
+    double top, inv_h;
+    double mx0;         // -x_0 / h
 };
 
-// J(y) and J(-y) of one row.
+// Where an offset y is looked up: its grid position u on an evenly spaced quadrature,
+// else y itself (bisection).
 template <bool UNI>
-__device__ __forceinline__ void j_node(const QGeo &g, const double *row, double y, double &jp, double &jm)
+__device__ __forceinline__ double qpos(const QGeo &g, double y)
+{
+    if constexpr (UNI)
+        return fma(y, g.inv_h, g.mx0);
+    else
+        return y;
+}
+
+// J(y) and J(-y) of one row at lookup position pos = qpos(y).
+template <bool UNI>
+__device__ __forceinline__ void j_node(const QGeo &g, const double *row, double pos, double &jp, double &jm)
 {
     if constexpr (UNI) {
-        const UPair q = upos((y - g.x0) * g.inv_h, g.top, g.lo_max);
+        const UPair q = upos(pos, g.top, g.lo_max);
         jp = j_u(row, q.ip, q.tp);
         jm = j_u(row, q.im, q.tm);
     } else {
-        jp = j_at(row, locate(g.qx, g.nq, y));
-        jm = j_at(row, locate(g.qx, g.nq, -y));
+        jp = j_at(row, locate(g.qx, g.nq, pos));
+        jm = j_at(row, locate(g.qx, g.nq, -pos));
     }
 }
 
-// J(y) and J(-y) at a sub-step node: the two end cells' rows at the node's own offset,
-// interpolated linearly at fraction tt of the segment.
+// J(y) and J(-y) at a sub-step node (lookup position pos = qpos(y)): the two end cells'
+// rows at the node's own offset, interpolated linearly at fraction tt of the segment.
 template <bool UNI>
-__device__ __forceinline__ void j_sub(const QGeo &g, const double *rp, const double *rq, double y, double tt,
+__device__ __forceinline__ void j_sub(const QGeo &g, const double *rp, const double *rq, double pos, double tt,
                                       double &jp, double &jm)
 {
     double ap, bp, am, bm;
     if constexpr (UNI) {
-        const UPair q = upos((y - g.x0) * g.inv_h, g.top, g.lo_max);
+        const UPair q = upos(pos, g.top, g.lo_max);
         ap = j_u(rp, q.ip, q.tp);
         bp = j_u(rq, q.ip, q.tp);
         am = j_u(rp, q.im, q.tm);
         bm = j_u(rq, q.im, q.tm);
     } else {
-        const QPos lp = locate(g.qx, g.nq, y), lm = locate(g.qx, g.nq, -y);
+        const QPos lp = locate(g.qx, g.nq, pos), lm = locate(g.qx, g.nq, -pos);
         ap = j_at(rp, lp);
         bp = j_at(rq, lp);
         am = j_at(rp, lm);
         bm = j_at(rq, lm);
     }
-    jp = ap + tt * (bp - ap);
-    jm = am + tt * (bm - am);
+    jp = fma(tt, bp - ap, ap);
+    jm = fma(tt, bm - am, am);
 }
 
 // Staged node of a half ray in sweep order (far end first, O last): projection Z, projected
@@ -173,9 +186,9 @@ struct SSeg {
     int m, K;
 };
 
-// Node quantities at the lane's frequency: total opacity, S+ and sigma~.
+// Node quantities at the lane's frequency: total opacity, S+ and sq = sigma~ / sqrt 2.
 struct NodeVal {
-    double chit, Sp, sg;
+    double chit, Sp, sq;
 };
 
 // S+ = S + r (Jbar - S) and sigma~ = r (J(-y) - J(y))/2 with r = chi_s/chi_t, the
@@ -185,19 +198,19 @@ __device__ __forceinline__ NodeVal node_val(double cl, double cs, double S, doub
     NodeVal v;
     v.chit = cl + cs;
     const double r = cs > 0.0 ? cs * rcp_refined(v.chit) : 0.0;   // chit >= cs > 0
-    v.Sp = v.chit > 0.0 ? S + r * (0.5 * (jp + jm) - S) : 0.0;
-    v.sg = r * 0.5 * (jm - jp);
+    v.Sp = v.chit > 0.0 ? fma(0.5 * r, jp + jm, fma(-r, S, S)) : 0.0;
+    v.sq = (0.5 * kISq2 * r) * (jm - jp);
     return v;
 }
 
 // e^{-y^2}, clamped where the result is 0 in FP64 anyway.
 __device__ __forceinline__ double profile(double y) { return exp_le700(fmax(-(y * y), -800.0)); }
 
-// Elimination state of a half sweep and the last node reached (chit, Sp, sg), with sg_pp
-// the sigma~ of the node before it (a virtual -sigma~ at the far end).
+// Elimination state of a half sweep and the last node reached (chit, Sp, sq), with sq_pp
+// the sq of the node before it (a virtual -sq at the far end).
 struct HalfState {
     double n, d, y, Pm;
-    double chit, Sp, sg, sg_pp;
+    double chit, Sp, sq, sq_pp;
 };
 
 __device__ __forceinline__ void start(HalfState &h, const NodeVal &first, double I_in)
@@ -208,8 +221,8 @@ __device__ __forceinline__ void start(HalfState &h, const NodeVal &first, double
     h.Pm = 0.0;
     h.chit = first.chit;
     h.Sp = first.Sp;
-    h.sg = first.sg;
-    h.sg_pp = -first.sg;
+    h.sq = first.sq;
+    h.sq_pp = -first.sq;
 }
 
 // Eliminate the last node, stepping to node v over a sub-interval of weight hz.
@@ -219,13 +232,13 @@ __device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
     const double P = (h.chit + v.chit) * hz;
     const double hd = (h.Pm + P) * h.d;
     h.n += hd;
-    h.y = h.y + h.Sp * hd - (v.sg - h.sg_pp) * h.d * kISq2;
+    h.y = fma(h.sq_pp - v.sq, h.d, fma(h.Sp, hd, h.y));   // y + S+ h d - (sigma~ - sigma~_pp) d / sqrt 2
     h.d = fma(P, h.n, h.d);
     h.Pm = P;
-    h.sg_pp = h.sg;
+    h.sq_pp = h.sq;
     h.chit = v.chit;
     h.Sp = v.Sp;
-    h.sg = v.sg;
+    h.sq = v.sq;
     if (RENORM) {
         const int ex = __builtin_amdgcn_frexp_exp(h.d);
         h.n = ldexp(h.n, -ex);
@@ -234,14 +247,14 @@ __device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
     }
 }
 
-// Running values of a lane inside a recurrence segment.
+// Running values of a lane inside a recurrence segment (pos: the lookup position).
 struct SubRun {
-    double g, r, kq, cs, S, y, tt;
+    double g, r, kq, cs, S, pos, tt;
 };
 
 template <bool UNI, bool RENORM>
 __device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, double dk, double dcs, double dS,
-                                         double dy, double im, const QGeo &qg, const double *rp, const double *rq,
+                                         double dpos, double im, const QGeo &qg, const double *rp, const double *rq,
                                          double hz)
 {
     w.g *= w.r;
@@ -249,10 +262,10 @@ __device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, doub
     w.kq += dk;
     w.cs += dcs;
     w.S += dS;
-    w.y += dy;
+    w.pos += dpos;
     w.tt += im;
     double jp, jm;
-    j_sub<UNI>(qg, rp, rq, w.y, w.tt, jp, jm);
+    j_sub<UNI>(qg, rp, rq, w.pos, w.tt, jp, jm);
     step<RENORM>(h, node_val(w.kq * w.g, w.cs, w.S, jp, jm), hz);
 }
 
@@ -346,7 +359,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
             cs_cur = nd[0].cs[gs];
             S_cur = nd[0].S[gs];
             double jp, jm;
-            j_node<UNI>(qg, row_cur, y_cur, jp, jm);
+            j_node<UNI>(qg, row_cur, qpos<UNI>(qg, y_cur), jp, jm);
             start(h, node_val(kap_cur * g_cur, cs_cur, S_cur, jp, jm), I_in);
         }
         const int nseg = min(kChunk - 1, L - b0);
@@ -370,7 +383,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                         const double fj = (double)j;
                         const double yj = fma(fj, dy, y_cur);
                         double jp, jm;
-                        j_sub<UNI>(qg, row_cur, row_n, yj, fj * im, jp, jm);
+                        j_sub<UNI>(qg, row_cur, row_n, qpos<UNI>(qg, yj), fj * im, jp, jm);
                         step<true>(h, node_val(fma(fj, dk, kap_cur) * profile(yj), fma(fj, dcs, cs_cur),
                                                fma(fj, dS, S_cur), jp, jm), hz);
                     }
@@ -389,8 +402,9 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                     w.kq = kap_cur;
                     w.cs = cs_cur;
                     w.S = S_cur;
-                    w.y = y_cur;
+                    w.pos = qpos<UNI>(qg, y_cur);
                     w.tt = 0.0;
+                    const double dpos = UNI ? dy * qg.inv_h : dy;
                     int budget = K;
                     if (mdx > 0.0) budget = (int)fmin((16.0 - travel) / mdx, (double)K);
                     if (budget < 1) {
@@ -404,19 +418,19 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                         const int jint = min(jend, m - 1);
                         int jj = j;
                         for (; jj + 3 < jint; jj += 4) {
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, true>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, true>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
                         }
                         // the last 0-3 steps; the cell node's step that follows renormalises,
                         // so at most seven steps pass between renormalisations
                         const int rem = jint - jj;
                         if (rem >= 2) {
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
                         }
-                        if (rem & 1) sub_step<UNI, false>(h, w, c, dk, dcs, dS, dy, im, qg, row_cur, row_n, hz);
+                        if (rem & 1) sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
                         travel += mdx * (double)(jint - j);
                         j = jint;
                         if (jend == m) {
@@ -425,9 +439,10 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                             break;
                         }
                         const double fj = (double)j;
-                        w.y = fma(fj, dy, y_cur);
-                        w.g = profile(w.y);
-                        w.r = exp_le700(fmax(fmin(-(2.0 * w.y + dy) * dy, 700.0), -800.0));
+                        const double yj = fma(fj, dy, y_cur);
+                        w.pos = qpos<UNI>(qg, yj);
+                        w.g = profile(yj);
+                        w.r = exp_le700(fmax(fmin(-(2.0 * yj + dy) * dy, 700.0), -800.0));
                         w.kq = fma(fj, dk, kap_cur);
                         w.cs = fma(fj, dcs, cs_cur);
                         w.S = fma(fj, dS, S_cur);
@@ -439,7 +454,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                 }
             }
             double jp, jm;
-            j_node<UNI>(qg, row_n, y_n, jp, jm);
+            j_node<UNI>(qg, row_n, qpos<UNI>(qg, y_n), jp, jm);
             step<true>(h, node_val(kap_n * g_n, cs_n, S_n, jp, jm), hz);
             y_cur = y_n;
             g_cur = g_n;
@@ -487,8 +502,8 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
     qg.nq = nq;
     qg.lo_max = nq - 2;
     qg.top = (double)(nq - 1);
-    qg.x0 = s_qx[0];
     qg.inv_h = a.q_inv_h;
+    qg.mx0 = -s_qx[0] * a.q_inv_h;
     const double xq_max = fmax(fabs(s_qx[0]), fabs(s_qx[nq - 1]));
     const double x = fi < nq ? s_qx[fi] : 0.0;
     const double w = act ? a.qw[fi] : 0.0;
@@ -505,7 +520,7 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
         const double idf = 1.0 / f.d, idb = 1.0 / b.d;
         const double h = f.Pm + b.Pm;
         const double yy = f.y * idf + b.y * idb;
-        const double sgO = (f.sg_pp + b.sg_pp) * kISq2;
+        const double sgO = f.sq_pp + b.sq_pp;
         const double inv = 1.0 / (h + f.n * idf + b.n * idb);
         const double u = (h * f.Sp + yy + sgO) * inv;
         // line part of O's own source, for L* and Jeff (Eq. ALO)
@@ -516,8 +531,8 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
         accE += w * ((h * (f.Sp - ratio * lcO.y) + yy + sgO) * inv);
         // v along n = ray r: the half-node fluxes (u_O - u_nb)/dtau on each side from the
         // elimination state, with sigma at the half nodes, interpolated in tau to O
-        const double fl_f = (f.n * u - f.y) * idf * kISq2 - 0.5 * (f.sg_pp + f.sg);
-        const double fl_b = (b.n * u - b.y) * idb * kISq2 - 0.5 * (b.sg_pp + b.sg);
+        const double fl_f = ((f.n * u - f.y) * idf - (f.sq_pp + f.sq)) * kISq2;
+        const double fl_b = ((b.n * u - b.y) * idb - (b.sq_pp + b.sq)) * kISq2;
         const double v = h > 0.0 ? (b.Pm * fl_f - f.Pm * fl_b) / h : 0.5 * (fl_f - fl_b);
         jp += u + v;
         jm += u - v;
