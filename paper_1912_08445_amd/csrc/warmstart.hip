@@ -84,8 +84,11 @@ __device__ inline Frag load_frag(const Frag *base, int idx, int lane) { return b
 // One wave per point.  F[p][0..7]: log10 n_H2, log10 T, log10 of the mean velocity
 // gradient to the neighbours (floored at 1e-30 s^-1), and log10 of the minimum, quartiles
 // and maximum over the rays of the H2 column along the cached walk (trapezoid in the
-// projected distance, floored at 1 cm^-2).  Quantiles interpolate linearly between order
-// statistics at position q (n_rays - 1).
+// projected distance, at least half a cell's column and 1 cm^-2).  Quantiles interpolate
+// linearly between order statistics at position q (n_rays - 1).  The lanes take a ray's
+// cells 64 at a time (coalesced reads of the walk cache), each forms its cell's trapezoid
+// term with the previous cell's values from its neighbour lane, and the wave sums the
+// terms.
 __global__ __launch_bounds__(64) void k_features(const CellRec *__restrict__ cell,
                                                  const double *__restrict__ nh2,
                                                  const double *__restrict__ T,
@@ -116,20 +119,33 @@ __global__ __launch_bounds__(64) void k_features(const CellRec *__restrict__ cel
     const double half_cell = dcount > 0 ? 0.5 * nh2[p] * (dsum / dcount) : 0.0;
     const double floor_col = half_cell > 1.0 ? half_cell : 1.0;
 
-    for (int r = lane; r < R; r += 64) {
+    const double n_O = nh2[p];
+    for (int r = 0; r < R; ++r) {
         const double nx = dir[3 * r], ny = dir[3 * r + 1], nz = dir[3 * r + 2];
-        const int64_t b = roff[p * R + r], e = roff[p * R + r + 1];
-        double N = 0.0, n_prev = nh2[p], z_prev = 0.0;
-        for (int64_t i = b; i < e; ++i) {
-            const int32_t c = rcells[i];
-            const double dx = cell[c].px - ox, dy = cell[c].py - oy, dz = cell[c].pz - oz;
-            const double Z = (dx * nx + dy * ny) + dz * nz;
-            const double n_i = nh2[c];
-            N += 0.5 * (n_prev + n_i) * (Z - z_prev);
-            n_prev = n_i;
-            z_prev = Z;
+        const int64_t b = roff[p * R + r];
+        const int L = (int)(roff[p * R + r + 1] - b);
+        // trapezoid terms 0.5 (n_{i-1} + n_i)(Z_i - Z_{i-1}) from the point (n_O, Z = 0) on
+        double acc = 0.0, n_carry = n_O, z_carry = 0.0;
+        for (int i0 = 0; i0 < L; i0 += 64) {
+            const int i = i0 + lane;
+            double Z = 0.0, n_i = 0.0;
+            if (i < L) {
+                const int32_t c = rcells[b + i];
+                const double dx = cell[c].px - ox, dy = cell[c].py - oy, dz = cell[c].pz - oz;
+                Z = (dx * nx + dy * ny) + dz * nz;
+                n_i = nh2[c];
+            }
+            double n_prev = __shfl_up(n_i, 1), z_prev = __shfl_up(Z, 1);
+            if (lane == 0) {
+                n_prev = n_carry;
+                z_prev = z_carry;
+            }
+            if (i < L) acc += 0.5 * (n_prev + n_i) * (Z - z_prev);
+            n_carry = __shfl(n_i, 63);
+            z_carry = __shfl(Z, 63);
         }
-        col[r] = N > floor_col ? N : floor_col;
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) col[r] = acc > floor_col ? acc : floor_col;
     }
     __syncthreads();
     // order statistics: rank by value, equal values by ray index

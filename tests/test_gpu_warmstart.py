@@ -48,7 +48,8 @@ def test_features_match_oracle(name, w):
     R = oracle_for(w).features()
     assert F.shape == R.shape
     assert np.all(np.isfinite(F))
-    # same operations in the same order; only log10 / sqrt may differ in the last bit
+    # the same trapezoid terms; the GPU sums each ray's terms in a tree order, and log10 / sqrt
+    # may differ in the last bit
     assert np.max(np.abs(F - R) / np.maximum(1.0, np.abs(R))) < 1e-13
 
 
