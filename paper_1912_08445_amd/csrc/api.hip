@@ -1277,7 +1277,14 @@ nlte_status nlte_trace(nlte_ctx *c)
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemsetAsync(c->d_roff, 0, sizeof(int64_t), s));
     auto t0 = std::chrono::steady_clock::now();
-    HIPCHK(c, launch_walk_count(c->d_cell, c->d_nbr, c->k, c->d_bnd, c->d_dir, c->n_rays, c->P,
+    // neighbour slots with their positions, for the walks only (freed on every return)
+    struct TabGuard {
+        NbrEntry *p = nullptr;
+        ~TabGuard() { dfree(p); }
+    } tab;
+    if ((st = dalloc(c, &tab.p, (size_t)(c->P * c->k)))) return st;
+    HIPCHK(c, launch_nbr_table(c->d_cell, c->d_nbr, c->k, c->P, tab.p, s));
+    HIPCHK(c, launch_walk_count(c->d_cell, tab.p, c->k, c->d_bnd, c->d_dir, c->n_rays, c->P,
                                 c->d_roff + 1, s));
     size_t tmp_bytes = 0;
     HIPCHK(c, scan_lengths(c->d_roff, n, nullptr, &tmp_bytes, s));
@@ -1290,9 +1297,10 @@ nlte_status nlte_trace(nlte_ctx *c)
     int64_t total = 0;
     HIPCHK(c, hipMemcpy(&total, c->d_roff + n, sizeof(int64_t), hipMemcpyDeviceToHost));
     if ((st = dalloc(c, &c->d_rcells, (size_t)total))) return st;
-    HIPCHK(c, launch_walk_fill(c->d_cell, c->d_nbr, c->k, c->d_bnd, c->d_dir, c->n_rays, c->P,
+    HIPCHK(c, launch_walk_fill(c->d_cell, tab.p, c->k, c->d_bnd, c->d_dir, c->n_rays, c->P,
                                c->d_roff, c->d_rcells, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    dfree(tab.p);
     auto t1 = std::chrono::steady_clock::now();
     c->st_trace.ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
     c->st_trace.launches += 1;

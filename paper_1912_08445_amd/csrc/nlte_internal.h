@@ -351,10 +351,18 @@ hipError_t launch_setup_points(const double *pos, const double *vel, const doubl
                                double mass, int64_t P, CellRec *cell, hipStream_t s);
 hipError_t launch_lte(const SpeciesDev &sp, const CellRec *cell, const double *T, int64_t P,
                       double *pops, hipStream_t s);
-hipError_t launch_walk_count(const CellRec *cell, const int32_t *nbr, int k, const uint8_t *bnd,
+// Neighbour slot of a point for the ray walk: the neighbour's position and index (m < 0:
+// an unused slot), k slots per point back to back.
+struct __align__(32) NbrEntry {
+    double x, y, z;
+    int32_t m, pad;
+};
+hipError_t launch_nbr_table(const CellRec *cell, const int32_t *nbr, int k, int64_t P, NbrEntry *tab,
+                            hipStream_t s);
+hipError_t launch_walk_count(const CellRec *cell, const NbrEntry *tab, int k, const uint8_t *bnd,
                              const double *dir, int n_rays, int64_t P, int64_t *len,
                              hipStream_t s);
-hipError_t launch_walk_fill(const CellRec *cell, const int32_t *nbr, int k, const uint8_t *bnd,
+hipError_t launch_walk_fill(const CellRec *cell, const NbrEntry *tab, int k, const uint8_t *bnd,
                             const double *dir, int n_rays, int64_t P, const int64_t *off,
                             int32_t *cells, hipStream_t s);
 hipError_t scan_lengths(int64_t *len_then_off, int64_t n, void *tmp, size_t *tmp_bytes,

@@ -69,9 +69,11 @@ hipError_t launch_lte(const SpeciesDev &sp, const CellRec *cell, const double *T
 // walk moves to the neighbour whose projection Z on the ray exceeds the current one and
 // whose squared distance q to the line through the origin is smallest (ties: lower
 // index), and stops when no neighbour lies farther along the ray or at a flagged
-// boundary point.  Z strictly increases, so at most P steps are taken.
+// boundary point.  Z strictly increases, so at most P steps are taken.  A step reads the
+// current cell's neighbour slots from the table (positions and indices side by side)
+// rather than gathering each neighbour's record.
 template <bool FILL>
-__global__ void k_walk(const CellRec *__restrict__ cell, const int32_t *__restrict__ nbr, int k,
+__global__ void k_walk(const CellRec *__restrict__ cell, const NbrEntry *__restrict__ tab, int k,
                        const uint8_t *__restrict__ bnd, const double *__restrict__ dir, int n_rays,
                        int64_t P, int64_t *__restrict__ len_out, const int64_t *__restrict__ off,
                        int32_t *__restrict__ cells_out)
@@ -91,11 +93,12 @@ __global__ void k_walk(const CellRec *__restrict__ cell, const int32_t *__restri
         int64_t best = -1;
         double bq = 0.0, bz = 0.0;
         for (int s = 0; s < k; ++s) {
-            int32_t m = nbr[cur * k + s];
+            const NbrEntry e = tab[cur * k + s];
+            const int32_t m = e.m;
             if (m < 0) continue;
-            double dx = cell[m].px - ox;
-            double dy = cell[m].py - oy;
-            double dz = cell[m].pz - oz;
+            double dx = e.x - ox;
+            double dy = e.y - oy;
+            double dz = e.z - oz;
             double Z = (dx * nx + dy * ny) + dz * nz;
             if (!(Z > zcur)) continue;
             double qx = dx - Z * nx, qy = dy - Z * ny, qz = dz - Z * nz;
@@ -115,23 +118,46 @@ __global__ void k_walk(const CellRec *__restrict__ cell, const int32_t *__restri
     if (!FILL) len_out[q] = len;
 }
 
-hipError_t launch_walk_count(const CellRec *cell, const int32_t *nbr, int k, const uint8_t *bnd,
+__global__ void k_nbr_table(const CellRec *__restrict__ cell, const int32_t *__restrict__ nbr, int64_t n,
+                            NbrEntry *__restrict__ tab)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t m = nbr[i];
+    NbrEntry e;
+    e.m = m;
+    e.pad = 0;
+    e.x = m >= 0 ? cell[m].px : 0.0;
+    e.y = m >= 0 ? cell[m].py : 0.0;
+    e.z = m >= 0 ? cell[m].pz : 0.0;
+    tab[i] = e;
+}
+
+hipError_t launch_nbr_table(const CellRec *cell, const int32_t *nbr, int k, int64_t P, NbrEntry *tab, hipStream_t s)
+{
+    const int64_t n = P * k;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nbr_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell, nbr, n, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_count(const CellRec *cell, const NbrEntry *tab, int k, const uint8_t *bnd,
                              const double *dir, int n_rays, int64_t P, int64_t *len, hipStream_t s)
 {
     int64_t n = P * n_rays;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell, nbr,
+    hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell, tab,
                        k, bnd, dir, n_rays, P, len, nullptr, nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_walk_fill(const CellRec *cell, const int32_t *nbr, int k, const uint8_t *bnd,
+hipError_t launch_walk_fill(const CellRec *cell, const NbrEntry *tab, int k, const uint8_t *bnd,
                             const double *dir, int n_rays, int64_t P, const int64_t *off,
                             int32_t *cells, hipStream_t s)
 {
     int64_t n = P * n_rays;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell, nbr,
+    hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cell, tab,
                        k, bnd, dir, n_rays, P, nullptr, off, cells);
     return hipGetLastError();
 }
