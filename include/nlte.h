@@ -15,7 +15,10 @@
  *     retains or frees a caller pointer.  Host-pointer calls copy in and out and return
  *     when the results are in the caller's buffers.  *_dev calls take device pointers
  *     and a hipStream_t (passed as void*, NULL = the context's own stream); they only
- *     enqueue work, so the caller synchronises that stream before reading results.
+ *     enqueue work, so the caller synchronises that stream before reading results.  The
+ *     context's own stream is a blocking stream: it is ordered with the legacy default
+ *     (null) stream both ways, so work that a caller enqueues on the null stream before
+ *     or after a call with NULL is ordered with that call's work.
  *   - Return codes: NLTE_OK (0); errors are negative, warnings positive.  After any
  *     non-zero code nlte_last_error() describes it.  No C++ exception crosses the ABI.
  *   - A context is bound to one HIP device and is not thread-safe: use one context per
@@ -105,7 +108,9 @@ typedef struct {
 
 /* Create a context on HIP device `hip_device`.  *out receives the handle. */
 nlte_status nlte_create(nlte_ctx **out, int hip_device);
-/* Free the context and every device buffer it owns.  NULL is allowed. */
+/* Free the context and every device buffer it owns.  NULL is allowed.  Waits first for
+ * all work on the context's device, so that work which a *_dev call enqueued on a caller's
+ * stream and which reads the context's buffers has finished before they are freed. */
 void nlte_destroy(nlte_ctx *ctx);
 /* Text of the last error or warning on this context (valid until the next call). */
 const char *nlte_last_error(const nlte_ctx *ctx);

@@ -781,7 +781,8 @@ nlte_status nlte_create(nlte_ctx **out, int hip_device)
     c->device = hip_device;
     nlte_default_params(&c->params);
     if (hipSetDevice(hip_device) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        // blocking: ordered with the null stream, which callers (torch's default stream) use
+        hipStreamCreateWithFlags(&c->stream, hipStreamDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipMalloc((void **)&c->d_maser, sizeof(int64_t)) != hipSuccess ||
         hipMalloc((void **)&c->d_conv, sizeof(ConvResult) * 1025) != hipSuccess ||
@@ -807,7 +808,8 @@ void nlte_destroy(nlte_ctx *c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    // *_dev calls enqueue work on the caller's streams that reads the context's buffers
+    (void)hipDeviceSynchronize();
     dfree(c->d_species_mem);
     dfree(c->d_cell);
     dfree(c->d_nh2);

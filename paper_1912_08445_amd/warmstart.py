@@ -38,6 +38,7 @@ def converged_rows(solver, mean, std, tol=1e-6, max_iter=200, sample=None, seed=
         g = torch.Generator(device="cpu").manual_seed(seed)
         idx = torch.randperm(solver.P, generator=g)[:sample].to(dev)
         X, T = X[idx].contiguous(), T[idx].contiguous()
+    torch.cuda.synchronize()   # the rows are complete before the caller may release the solver
     return X, T, rep
 
 
