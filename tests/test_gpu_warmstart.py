@@ -267,3 +267,24 @@ def test_warm_start_gain_on_held_out_disc():
     assert err(pred).max() < 0.1 * err(lte0).max()
     assert warm_rep["iterations"] < lte_rep["iterations"]
     assert err(warm_pops).max() <= max(err(lte_pops).max(), 1e-5)
+
+
+def test_default_stream_work_is_ordered_with_torch():
+    # A *_dev call given torch's default stream (handle 0) runs on the context's stream,
+    # which is ordered with the null stream: a torch op issued right after the call reads
+    # complete rows.  Two models back to back, so stale rows of the first would show.
+    import torch
+    from paper_1912_08445_amd import warmstart
+    dev = torch.device("cuda:0")
+    solvers = [solver_for(configs.outflow5(n_points=3000, seed=sd, nside=1)) for sd in (31, 32)]
+    mean, std = warmstart.feature_norm([s.features() for s in solvers])
+    for s in solvers:
+        s.mlp_set_norm(mean, std)
+        pops = torch.tensor(s.lte(), device=dev)
+        X = torch.empty((s.P, 8), dtype=torch.float32, device=dev)
+        T = torch.empty((s.P, s.n_lev), dtype=torch.float32, device=dev)
+        s.mlp_rows_dev(pops, X, T)
+        picked = X[torch.arange(0, s.P, 7, device=dev)].cpu().numpy()
+        ref = ((s.features() - mean) / std).astype(np.float32)[::7]
+        assert np.allclose(picked, ref, rtol=1e-6, atol=1e-6)
+        s.close()
