@@ -31,6 +31,8 @@ template <typename T>
 nlte_status dalloc(nlte_ctx *c, T **p, size_t count)
 {
     if (*p) {
+        // work that *_dev calls enqueued on a caller's stream may still read the old buffer
+        (void)hipDeviceSynchronize();
         (void)hipFree(*p);
         *p = nullptr;
     }
@@ -46,7 +48,10 @@ nlte_status dalloc(nlte_ctx *c, T **p, size_t count)
 template <typename T>
 void dfree(T *&p)
 {
-    if (p) (void)hipFree(p);
+    if (p) {
+        (void)hipDeviceSynchronize();   // as in dalloc: caller-stream work may still read it
+        (void)hipFree(p);
+    }
     p = nullptr;
 }
 
