@@ -507,8 +507,9 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
-    # timed region: HIP events on torch's current stream, which is the stream every
-    # library call above is launched on; per-kernel HIP events inside the library
+    # timed region: HIP events on torch's current (default) stream; the library calls
+    # above get that stream's handle 0 and run on the context's stream, which is ordered
+    # with the default stream both ways; per-kernel HIP events inside the library
     s.set_params(profile=1)
     s.reset_kernel_stats()
     stream = torch.cuda.current_stream()
