@@ -1,8 +1,8 @@
 // Warm start of the accelerated Lambda iteration: per-point features of the local
 // conditions and a small multilayer perceptron that maps them to starting level
 // populations, predicted as departures from LTE.  This is not part of the paper's method, which only needs some initial
-// populations for its iteration (Sec. 2.2.1, 3.4); the iteration itself remains the
-// judge of the result.
+// populations for its iteration (Sec. 2.2.1, 3.4); the iteration itself still decides
+// the result.
 //
 // Network: 8 -> 128 -> 128 -> 128 -> n_out (n_out <= 16), erf GELU after each hidden
 // layer.  Parameters are one flat FP32 vector (master copy), matrices row-major
