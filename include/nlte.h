@@ -461,6 +461,13 @@ nlte_status nlte_run_ali_warm_dev(nlte_ctx *ctx, double *d_pops_out, nlte_ali_re
  * "mlp_update" (gradient reduction, Adam and operand packing of one step) and "image"
  * (the emergent-intensity elimination of nlte_image, without the image-plane positions). */
 nlte_status nlte_kernel_stats(nlte_ctx *ctx, const char *name, double *ms, int64_t *launches);
+/* With params.profile = 1: the node-frequency elimination steps (one step of one line at one
+ * frequency) that the line formal-solve kernels executed since the last
+ * nlte_reset_kernel_stats.  A velocity sub-step segment whose nodes all lie beyond the
+ * range of the line profile for every frequency of a wave has zero opacity throughout
+ * and is eliminated in one step, which counts as one; the method's own count of steps is
+ * the third output of nlte_trace_stats times n_lines times n_q. */
+nlte_status nlte_executed_steps(nlte_ctx *ctx, int64_t *node_freq);
 nlte_status nlte_reset_kernel_stats(nlte_ctx *ctx);
 
 #ifdef __cplusplus

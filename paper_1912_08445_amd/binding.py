@@ -35,7 +35,7 @@ EXPORTS = (
     "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_rays_healpix", "nlte_get_rays", "nlte_set_scattering", "nlte_formal_solve_scat",
     "nlte_formal_solve_scat_dev", "nlte_scattering_field",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
-    "nlte_kernel_stats", "nlte_reset_kernel_stats",
+    "nlte_kernel_stats", "nlte_reset_kernel_stats", "nlte_executed_steps",
     "nlte_default_train_params", "nlte_mlp_param_count", "nlte_features", "nlte_features_dev",
     "nlte_mlp_init", "nlte_mlp_set_weights", "nlte_mlp_get_weights", "nlte_mlp_set_norm",
     "nlte_mlp_forward", "nlte_mlp_loss_grad", "nlte_mlp_train", "nlte_mlp_train_dev",
@@ -127,6 +127,7 @@ def load():
     L.nlte_autotune.argtypes = [vp, C.c_char_p, C.c_int, C.c_char_p, C.c_int]
     L.nlte_kernel_stats.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.nlte_reset_kernel_stats.argtypes = [vp]
+    L.nlte_executed_steps.argtypes = [vp, C.POINTER(i64)]
     L.nlte_default_train_params.argtypes = [C.POINTER(TrainParams)]
     L.nlte_default_train_params.restype = None
     L.nlte_mlp_param_count.argtypes = [C.c_int]
@@ -533,6 +534,13 @@ class Solver:
         self._chk(self.L.nlte_kernel_stats(self.h, name.encode(), C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+
+    def executed_steps(self):
+        """Node-frequency elimination steps the formal-solve kernels executed while
+        profiling, since the last reset (a collapsed far-wing segment counts as one)."""
+        n = C.c_int64()
+        self._chk(self.L.nlte_executed_steps(self.h, C.byref(n)))
+        return n.value
     def reset_kernel_stats(self):
         self._chk(self.L.nlte_reset_kernel_stats(self.h))
 

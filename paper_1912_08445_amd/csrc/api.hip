@@ -144,6 +144,7 @@ SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
     a.f_sub = c->params.f_sub;
     a.xq_max = c->xq_max;
     a.norm = 2.0 / (double)c->n_rays;
+    a.exec_steps = c->params.profile ? c->d_exec : nullptr;
     a.P = c->P;
     a.n_rays = c->n_rays;
     a.n_pairs = c->n_pairs;
@@ -794,7 +795,10 @@ nlte_status nlte_create(nlte_ctx **out, int hip_device)
         hipHostMalloc((void **)&c->h_conv, sizeof(ConvResult) * 1025, 0) != hipSuccess ||
         hipMalloc((void **)&c->d_active, sizeof(int32_t)) != hipSuccess ||
         hipHostMalloc((void **)&c->h_active, sizeof(int32_t), 0) != hipSuccess ||
-        hipMalloc((void **)&c->d_work_counter, sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc((void **)&c->d_work_counter, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&c->d_exec, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->d_exec, 0, sizeof(unsigned long long)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
         nlte_destroy(c);
         return NLTE_E_HIP;
     }
@@ -815,6 +819,7 @@ void nlte_destroy(nlte_ctx *c)
     (void)hipSetDevice(c->device);
     // *_dev calls enqueue work on the caller's streams that reads the context's buffers
     (void)hipDeviceSynchronize();
+    dfree(c->d_exec);
     dfree(c->d_species_mem);
     dfree(c->d_cell);
     dfree(c->d_nh2);
@@ -1744,6 +1749,23 @@ nlte_status nlte_reset_kernel_stats(nlte_ctx *c)
     if (!c) return NLTE_E_INVALID_ARG;
     c->st_line_coef = c->st_formal = c->st_stateq = c->st_lte = c->st_trace = KernelStat{};
     c->st_features = c->st_mlp_forward = c->st_mlp_train = c->st_mlp_update = c->st_image = KernelStat{};
+    if (c->d_exec) {
+        (void)hipSetDevice(c->device);
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipMemset(c->d_exec, 0, sizeof(unsigned long long)));
+        HIPCHK(c, hipDeviceSynchronize());
+    }
+    return NLTE_OK;
+}
+
+nlte_status nlte_executed_steps(nlte_ctx *c, int64_t *node_freq)
+{
+    if (!c || !node_freq) return NLTE_E_INVALID_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    unsigned long long v = 0;
+    HIPCHK(c, hipMemcpy(&v, c->d_exec, sizeof(v), hipMemcpyDeviceToHost));
+    *node_freq = (int64_t)v;
     return NLTE_OK;
 }
 

@@ -205,10 +205,13 @@ __device__ __forceinline__ void recur_step(double &g, double &r, double c, doubl
 
 // Half-sweep along ray `ray` from its far end to O for Doppler offset xq of this lane.
 // The result is left in ls.st (one HalfState per line of the lane).
+// nexec counts the elimination steps the wave executes (a collapsed far-wing segment
+// counts as one).
 template <bool F32, int LPL, bool TRACK = false>
 __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 * LPL> *rec, int64_t O,
                            const CellRec &cO, int ray, typename Bulk<F32>::T xq, int grp, int line0,
-                           int nlw, const double (&ib)[LPL], LineState<typename Bulk<F32>::T, LPL> &ls)
+                           int nlw, const double (&ib)[LPL], LineState<typename Bulk<F32>::T, LPL> &ls,
+                           int64_t &nexec)
 {
     using T = typename Bulk<F32>::T;
     using T2 = typename Bulk<F32>::T2;
@@ -319,6 +322,32 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                 Sn[l] = rec[i + 1].S[grp * LPL + l];
                 a_prev[l] = ls.chi_cur[l] * dzq;
             }
+            if (!TRACK) {
+                // Far wing: every lane beyond the range of its profile (exactly 0 past
+                // x^2 = 750 in FP64, 105 in FP32) at both ends of the segment, on one side
+                // of the line centre, and zero opacity at its first node.  Then every node of
+                // the segment has zero opacity, the elimination steps after the first change
+                // nothing, and one step with zero opacity and the end node's source leaves
+                // the same state.
+                const T far2 = F32 ? (T)105 : (T)750;
+                bool far = ((x_cur > (T)0) == (xn > (T)0)) && x_cur * x_cur > far2 && xn * xn > far2;
+#pragma unroll
+                for (int l = 0; l < LPL; ++l) far = far && ls.chi_cur[l] == (T)0;
+                if (__all(far)) {
+#pragma unroll
+                    for (int l = 0; l < LPL; ++l) {
+                        elim_step<F32, true, TRACK>((T)0, Sn[l], a_prev[l], ls.S_e[l], ls.st[l]);
+                        ls.k_cur[l] = kn[l];
+                        ls.chi_cur[l] = (T)0;
+                    }
+                    x_cur = xn;
+                    g_cur = (T)0;
+                    travel = 0.0;
+                    ++nexec;
+                    continue;
+                }
+            }
+            nexec += m;
             T gn;
             if (m == 1) {
                 gn = profile_far(xn);
@@ -477,6 +506,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
         accB[l] = accD[l] = 0.0;
     }
     LineState<T, LPL> ls;
+    unsigned long long my_exec = 0;   // executed node-frequency steps of this lane
     for (int p = 0; p < a.n_pairs; ++p) {
         const int r = a.pair_r[p], rb = a.anti[r];
         for (int c = 0; c < a.fchunks; ++c) {
@@ -485,7 +515,8 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
             const double xq = act ? a.qx[nidx] : 0.0;
             const double wq = act ? a.qw[nidx] : 0.0;
             // u pairs I(n, x) with I(-n, -x): the antipode sweeps at the mirrored offset
-            half_sweep<F32, LPL, BAND>(a, rec, O, cO, r, (T)xq, grp, line0, nlw, ib, ls);
+            int64_t nex = 0;
+            half_sweep<F32, LPL, BAND>(a, rec, O, cO, r, (T)xq, grp, line0, nlw, ib, ls, nex);
             double Qf[LPL], yf[LPL], Hf[LPL], hdf[LPL], Sf[LPL];
             const int mf = BAND ? ls.m_last : 1;
 #pragma unroll
@@ -497,7 +528,13 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
                 hdf[l] = ls.st[l].hd * id;
                 Sf[l] = ls.st[l].Sl;
             }
-            half_sweep<F32, LPL, BAND>(a, rec, O, cO, rb, (T)(-xq), grp, line0, nlw, ib, ls);
+            half_sweep<F32, LPL, BAND>(a, rec, O, cO, rb, (T)(-xq), grp, line0, nlw, ib, ls, nex);
+            if (a.exec_steps != nullptr) {
+                int nact = 0;
+#pragma unroll
+                for (int l = 0; l < LPL; ++l) nact += (lact[l] && act) ? 1 : 0;
+                my_exec += (unsigned long long)nex * (unsigned long long)nact;
+            }
             double nbf[LPL], nbb[LPL];
 #pragma unroll
             for (int l = 0; l < LPL; ++l) {
@@ -550,6 +587,10 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
                 __syncthreads();
             }
         }
+    }
+    if (a.exec_steps != nullptr) {
+        for (int o = kWave / 2; o > 0; o >>= 1) my_exec += __shfl_xor(my_exec, o);
+        if (lane == 0) atomicAdd(a.exec_steps, my_exec);
     }
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {

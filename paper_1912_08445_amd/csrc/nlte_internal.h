@@ -87,6 +87,8 @@ struct SolveArgs {
     // persistent form: item order (points by decreasing cost) and the work counter
     const int32_t *order;
     unsigned long long *work_counter;
+    // profile mode: executed node-frequency elimination steps (null: not counted)
+    unsigned long long *exec_steps;
 };
 
 // Coupled statistical equilibrium of the band ALO (see band.hip).
@@ -259,6 +261,7 @@ struct nlte_ctx {
     // ray cache, per-point costs and the decreasing-cost order
     int32_t *d_order = nullptr;                 // [P]
     unsigned long long *d_work_counter = nullptr;
+    unsigned long long *d_exec = nullptr;   // executed formal-solve steps (profile mode)
     bool traced = false;
     int64_t *d_roff = nullptr;
     int32_t *d_rcells = nullptr;
