@@ -322,13 +322,13 @@ __device__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 
                 Sn[l] = rec[i + 1].S[grp * LPL + l];
                 a_prev[l] = ls.chi_cur[l] * dzq;
             }
-            if (!TRACK) {
+            if (!TRACK && m > 1) {
                 // Far wing: every lane beyond the range of its profile (exactly 0 past
                 // x^2 = 750 in FP64, 105 in FP32) at both ends of the segment, on one side
                 // of the line centre, and zero opacity at its first node.  Then every node of
                 // the segment has zero opacity, the elimination steps after the first change
                 // nothing, and one step with zero opacity and the end node's source leaves
-                // the same state.
+                // the same state.  (A segment without sub-steps is one step anyway.)
                 const T far2 = F32 ? (T)105 : (T)750;
                 bool far = ((x_cur > (T)0) == (xn > (T)0)) && x_cur * x_cur > far2 && xn * xn > far2;
 #pragma unroll
