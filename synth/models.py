@@ -118,6 +118,36 @@ def keplerian_disc(seed: int, n: int, r_min_au: float = 10.0, r_max_au: float = 
                  nbr=knn(pos, k))
 
 
+def shell_sphere(seed: int, radii: np.ndarray, counts: np.ndarray, k: int = 12) -> Model:
+    """Points on concentric spheres (the paper maps each grid point of a 1-D model to a
+    shell of points spread over a sphere, Sec. 4.1.1-4.1.2): counts[s] points on the
+    sphere of radius radii[s], spread by a golden-angle spiral (equal-area rings in z)
+    and turned by a seeded random rotation per shell, with exact k-NN neighbours.  The
+    physical fields are left for the caller (zero velocity, unit density and
+    temperature, no turbulence, unit abundance)."""
+    st = Stream(seed, "shells")
+    golden = np.pi * (3.0 - np.sqrt(5.0))
+    pts = []
+    for rad, m in zip(np.asarray(radii, dtype=np.float64), np.asarray(counts, dtype=np.int64)):
+        i = np.arange(m, dtype=np.float64) + 0.5
+        z = 1.0 - 2.0 * i / m
+        s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+        ph = golden * np.arange(m)
+        p = np.stack([s * np.cos(ph), s * np.sin(ph), z], axis=1)
+        # rotation from a unit quaternion with Gaussian components
+        q = st.normal(4)
+        q = q / np.sqrt((q * q).sum())
+        a, b, c, d = q
+        rot = np.array([[a * a + b * b - c * c - d * d, 2 * (b * c - a * d), 2 * (b * d + a * c)],
+                        [2 * (b * c + a * d), a * a - b * b + c * c - d * d, 2 * (c * d - a * b)],
+                        [2 * (b * d - a * c), 2 * (c * d + a * b), a * a - b * b - c * c + d * d]])
+        pts.append(rad * (p @ rot.T))
+    pos = np.concatenate(pts)
+    n = pos.shape[0]
+    return Model(pos=pos, vel=np.zeros((n, 3)), n_h2=np.ones(n), temperature=np.ones(n),
+                 v_turb=np.zeros(n), abundance=np.ones(n), nbr=knn(pos, k))
+
+
 def chain_1d(x: np.ndarray, vel_x: np.ndarray, n_h2, temperature, v_turb, abundance) -> Model:
     """Points on the x axis with chain neighbours (left, right)."""
     n = x.shape[0]
