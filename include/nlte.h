@@ -232,6 +232,22 @@ nlte_status nlte_formal_solve_dev(nlte_ctx *ctx, const double *d_pops, double *d
                                   double *d_Jeff, double *d_Lstar, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): nlte_formal_solve_dev with the same
+ * arguments, results and kernels, which allocates nothing.  Its scratch (the per-(point,
+ * line) opacity and source staging and the work-queue counter) lives in a fixed array of
+ * 64 MiB in the library's device code, one per GPU, held until the process ends, instead
+ * of the context's buffers.  It takes P * n_lines <= 4,194,288 in FP64 (8,388,576 in the
+ * FP32 form); larger models get NLTE_E_INVALID_ARG (use nlte_formal_solve_dev).  Every
+ * call on one GPU shares that GPU's array, from any context: calls that overlap on one GPU
+ * (two streams, two threads) race and must be ordered by the caller.  The counter is
+ * cleared by a kernel on `stream` at each call (no memset node), so the call can be
+ * captured.  No kernel timing or step counting (params.profile is ignored).
+ */
+nlte_status nlte_formal_solve_noalloc_dev(nlte_ctx *ctx, const double *d_pops, double *d_J,
+                                          double *d_Jeff, double *d_Lstar, void *stream);
+
+/*
  * Statistical equilibrium (Eq. ourALI with the diagonal ALO): per point the rates
  * u->l = A(1 - L*) + B_ul Jeff + C_ul and l->u = B_lu Jeff + C_lu, the first level's
  * equation replaced by sum_i n_i = abundance * n_h2, solved by Gaussian elimination

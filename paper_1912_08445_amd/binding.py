@@ -31,7 +31,7 @@ EXPORTS = (
     "nlte_default_params", "nlte_create", "nlte_destroy", "nlte_last_error", "nlte_set_species",
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
     "nlte_get_ray", "nlte_get_order", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
-    "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_stateq", "nlte_stateq_dev",
+    "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_formal_solve_noalloc_dev", "nlte_stateq", "nlte_stateq_dev",
     "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_rays_healpix", "nlte_get_rays", "nlte_set_scattering", "nlte_formal_solve_scat",
     "nlte_formal_solve_scat_dev", "nlte_scattering_field",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
@@ -111,6 +111,7 @@ def load():
     L.nlte_lte_dev.argtypes = [vp, vp, vp]
     L.nlte_formal_solve.argtypes = [vp, vp, vp, vp, vp]
     L.nlte_formal_solve_dev.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.nlte_formal_solve_noalloc_dev.argtypes = [vp, vp, vp, vp, vp, vp]
     L.nlte_stateq.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.nlte_stateq_dev.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.nlte_formal_solve_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -393,6 +394,11 @@ class Solver:
     def formal_solve_dev(self, pops, J, Jeff, L, stream=None):
         self._chk(self.L.nlte_formal_solve_dev(self.h, _tp(pops), _tp(J), _tp(Jeff), _tp(L),
                                                _stream(stream)))
+
+    def formal_solve_noalloc_dev(self, pops, J, Jeff, L, stream=None):
+        """formal_solve_dev with the library's fixed per-GPU scratch (allocates nothing)."""
+        self._chk(self.L.nlte_formal_solve_noalloc_dev(self.h, _tp(pops), _tp(J), _tp(Jeff), _tp(L),
+                                                       _stream(stream)))
 
     def stateq_dev(self, pops_old, J, Jeff, L, pops_new, flags=None, stream=None):
         self._chk(self.L.nlte_stateq_dev(self.h, _tp(pops_old), _tp(J), _tp(Jeff), _tp(L),

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 
 #include "nlte_internal.h"
@@ -53,6 +54,35 @@ void dfree(T *&p)
         (void)hipFree(p);
     }
     p = nullptr;
+}
+
+// Scratch of the allocation-free formal solve (nlte_formal_solve_noalloc_dev): the
+// work-queue counter (first kScratchHead bytes) and the line-coefficient staging, in the
+// code object's global memory, one copy per device, alive until the process ends.  Host
+// code never names the array after set-up: it uses the device address that
+// hipGetSymbolAddress returned for that device (scratch_ptr).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr size_t kScratchHead = 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_rc[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device with that
+// device current; the return code of the lookup is kept for the entry point's error.
+void scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    g_scratch_rc[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
 }
 
 bool finite_all(const double *a, int64_t n)
@@ -195,15 +225,30 @@ void drop_graphs(nlte_ctx *c)
 
 // Line coefficients and the formal solve.  ali: skip points of converged models.
 // capture: enqueue only (no per-kernel event timing, which would synchronise).
+// sc (nullable): caller-provided staging and counter in place of the context's buffers;
+// then nothing is timed, counted or allocated.
+struct FsScratch {
+    void *lc;
+    unsigned long long *counter;
+};
+
 nlte_status formal_solve_impl(nlte_ctx *c, const double *d_pops, double *d_J, double *d_Jeff,
-                              double *d_L, hipStream_t s, bool ali = false, bool capture = false)
+                              double *d_L, hipStream_t s, bool ali = false, bool capture = false,
+                              const FsScratch *sc = nullptr)
 {
     const int fp32 = c->params.precision == NLTE_PREC_FP32_BULK;
-    auto lc = [&] { return launch_line_coef(c->sp, c->d_cell, d_pops, c->P, fp32, c->d_lc, c->d_maser, s); };
+    void *lcbuf = sc ? sc->lc : c->d_lc;
+    int64_t *maser = sc ? nullptr : c->d_maser;
+    auto lc = [&] { return launch_line_coef(c->sp, c->d_cell, d_pops, c->P, fp32, lcbuf, maser, s); };
     HIPCHK(c, capture ? lc() : timed(c, c->st_line_coef, s, lc));
     SolveArgs a = solve_args(c, d_J, d_Jeff, d_L);
+    if (sc) {
+        a.lc = sc->lc;
+        a.work_counter = sc->counter;
+        a.exec_steps = nullptr;
+    }
     if (ali) a.model_done = c->d_model_done;
-    if (c->cfg.persistent) HIPCHK(c, launch_fill_u64(c->d_work_counter, 1, 0ull, s));
+    if (c->cfg.persistent) HIPCHK(c, launch_fill_u64(a.work_counter, 1, 0ull, s));
     auto fs = [&] { return launch_formal_solve(a, c->cfg, fp32, s); };
     HIPCHK(c, capture ? fs() : timed(c, c->st_formal, s, fs));
     return NLTE_OK;
@@ -802,6 +847,7 @@ nlte_status nlte_create(nlte_ctx **out, int hip_device)
         nlte_destroy(c);
         return NLTE_E_HIP;
     }
+    scratch_setup(hip_device);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) {
         c->n_cu = prop.multiProcessorCount;
@@ -1429,6 +1475,31 @@ nlte_status nlte_formal_solve_dev(nlte_ctx *c, const double *d_pops, double *d_J
     // a fill kernel, not a memset node: callers may capture this stream in a graph
     HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long *>(c->d_maser), 1, 0ull, s));
     return formal_solve_impl(c, d_pops, d_J, d_Jeff, d_L, s);
+}
+
+nlte_status nlte_formal_solve_noalloc_dev(nlte_ctx *c, const double *d_pops, double *d_J, double *d_Jeff,
+                                          double *d_L, void *stream)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!d_pops || !d_J || !d_Jeff || !d_L) return fail(c, NLTE_E_INVALID_ARG, "null buffer");
+    if (c->device < 0 || c->device >= kMaxDevices) return fail(c, NLTE_E_HIP, "device index beyond the scratch table");
+    void *base = g_scratch_ptr[c->device];
+    if (!base)
+        return fail(c, NLTE_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(g_scratch_rc[c->device]));
+    const size_t elem = c->params.precision == NLTE_PREC_FP32_BULK ? sizeof(float2) : sizeof(double2);
+    const size_t need_bytes = (size_t)c->P * (size_t)c->n_lines * elem;
+    if (need_bytes > kScratchBytes - kScratchHead)
+        return fail(c, NLTE_E_INVALID_ARG,
+                    "nlte_formal_solve_noalloc_dev: " + std::to_string(c->P) + " points x " +
+                        std::to_string(c->n_lines) + " lines need " + std::to_string(need_bytes) +
+                        " bytes of line-coefficient staging; the fixed scratch holds " +
+                        std::to_string(kScratchBytes - kScratchHead) + " (use nlte_formal_solve_dev)");
+    (void)hipSetDevice(c->device);
+    hipStream_t s = pick(c, stream);
+    FsScratch sc{static_cast<unsigned char *>(base) + kScratchHead, static_cast<unsigned long long *>(base)};
+    // enqueue only: no event timing (which would synchronise), no step counting
+    return formal_solve_impl(c, d_pops, d_J, d_Jeff, d_L, s, false, true, &sc);
 }
 
 nlte_status nlte_formal_solve(nlte_ctx *c, const double *pops, double *J, double *Jeff, double *L)
