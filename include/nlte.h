@@ -64,9 +64,12 @@ typedef struct {
     int profile;      /* 1: time every kernel with HIP events (nlte_kernel_stats); the ALI
                          then launches kernels one by one instead of replaying a graph */
     int use_graph;    /* 1: capture one ALI iteration as a hipGraph and replay it.  1 */
-    int lines_per_lane; /* formal-solve lines per lane: 0 = by rule, 1 or 2 (or 3 in the FP32
-                           form); lines of a lane share its profile evaluations.  0 */
-    int high_occupancy; /* 1: formal-solve kernels built for 3-4 waves per SIMD.  1 */
+    int lines_per_lane; /* formal-solve lines per lane, 1..5 (0 = by rule: the fewest waves per
+                           point, then the fewest lines per lane); the lines of a lane share
+                           its profile evaluations.  0 */
+    int waves_per_simd; /* formal-solve register budget: 1, 2 or 3 waves per SIMD (1: the whole
+                           register file, 512 with the accumulation registers; 3: 168);
+                           0 = by rule (3 up to two lines per lane, else 2).  0 */
     int persistent;   /* 1: persistent formal solve taking points from a work queue in
                          decreasing order of their cached step counts.  0 */
     int ng_every;     /* Ng acceleration (Sec. 3.4): after every ng_every regular ALI
@@ -81,10 +84,20 @@ typedef struct {
                          not all positive takes the local (diagonal) solve (Sec. 6.1).
                          FP64 formal solve whatever the precision; no graph replay.  Needs
                          use_alo.  0 */
+    int long_segments; /* velocity sub-step segments (Sec. 3.2) in the formal solve: 1 = long
+                         segments: along a segment's sub-steps the line profile follows a
+                         multiplicative recurrence, and a segment that lies beyond the
+                         profile's range for every frequency of a wave is eliminated in one
+                         step (it has no opacity); 0 = short segments: every sub-step node
+                         evaluates its profile; -1 = by the trace (long when the cached walks
+                         average more than two elimination steps per cell).  The two agree
+                         to rounding.  -1 */
+    int stage_nodes;  /* ray nodes a formal-solve wave stages in LDS at a time, 2..64 (0 = by
+                         rule: the most that keep the register budget's occupancy).  0 */
 } nlte_params;
 
 /* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0, ng_every 0,
- * alo_band 0. */
+ * alo_band 0, long_segments -1, stage_nodes 0. */
 void nlte_default_params(nlte_params *p);
 
 typedef struct {
@@ -352,14 +365,24 @@ nlte_status nlte_run_ali_dev(nlte_ctx *ctx, const double *d_pops_init, double *d
 nlte_status nlte_get_model_status(nlte_ctx *ctx, int32_t *iterations, uint8_t *converged,
                                   double *last_change);
 
+/* The formal-solve launch the current parameters resolve to (after the rules for the
+ * choices left at 0 or -1): lines per lane, waves per SIMD of the register budget, long
+ * segments (0/1), ray nodes staged per round, persistent (0/1); any pointer may be NULL.
+ * Needs nlte_trace (the collapse rule reads the trace). */
+nlte_status nlte_get_launch(nlte_ctx *ctx, int *lines_per_lane, int *waves_per_simd, int *long_segments,
+                            int *stage_nodes, int *persistent);
+
 /*
- * Time the formal-solve launch variants (lines per lane 1/2, or up to 3 in the FP32 form,
- * occupancy hint on/off, grid or persistent work queue) on the current model with LTE
- * populations, `trials` launches each (after one warm-up), and keep the fastest (median)
- * in the context's parameters.
- * cache_path (nullable): text file of earlier choices keyed by device, model size, ray,
- * line and frequency counts, step count and precision; a hit skips the timing, a miss
- * appends the new choice.  choice (nullable, cap bytes) receives a description.
+ * Time formal-solve launch choices on the current model with LTE populations and keep the
+ * fastest in the context's parameters: starting from the rule's choice, one dimension at
+ * a time (lines per lane, register budget of 1, 2 or 3 waves per SIMD, long or short
+ * segments, nodes staged per round, grid or persistent work queue), each candidate timed
+ * over `trials` launches after one warm-up (median), the best of each dimension kept
+ * before the next.
+ * cache_path (nullable): text file of earlier choices keyed by device, library build,
+ * model size, ray, line and frequency counts, step count and precision; a hit skips the
+ * timing, a miss appends the new choice.  choice (nullable, cap bytes) receives a
+ * description.
  */
 nlte_status nlte_autotune(nlte_ctx *ctx, const char *cache_path, int trials, char *choice, int cap);
 

@@ -34,7 +34,7 @@ EXPORTS = (
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_formal_solve_noalloc_dev", "nlte_stateq", "nlte_stateq_dev",
     "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_rays_healpix", "nlte_get_rays", "nlte_set_scattering", "nlte_formal_solve_scat",
     "nlte_formal_solve_scat_dev", "nlte_scattering_field",
-    "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune",
+    "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune", "nlte_get_launch",
     "nlte_kernel_stats", "nlte_reset_kernel_stats", "nlte_executed_steps",
     "nlte_default_train_params", "nlte_mlp_param_count", "nlte_features", "nlte_features_dev",
     "nlte_mlp_init", "nlte_mlp_set_weights", "nlte_mlp_get_weights", "nlte_mlp_set_norm",
@@ -50,8 +50,8 @@ class Params(C.Structure):
     _fields_ = [("t_cmb", C.c_double), ("f_sub", C.c_double), ("tol", C.c_double),
                 ("max_iter", C.c_int), ("use_alo", C.c_int), ("precision", C.c_int),
                 ("profile", C.c_int), ("use_graph", C.c_int), ("lines_per_lane", C.c_int),
-                ("high_occupancy", C.c_int), ("persistent", C.c_int), ("ng_every", C.c_int),
-                ("alo_band", C.c_int)]
+                ("waves_per_simd", C.c_int), ("persistent", C.c_int), ("ng_every", C.c_int),
+                ("alo_band", C.c_int), ("long_segments", C.c_int), ("stage_nodes", C.c_int)]
 
 
 class AliReport(C.Structure):
@@ -126,6 +126,7 @@ def load():
     L.nlte_run_ali_dev.argtypes = [vp, vp, vp, C.POINTER(AliReport), vp]
     L.nlte_get_model_status.argtypes = [vp, vp, vp, vp]
     L.nlte_autotune.argtypes = [vp, C.c_char_p, C.c_int, C.c_char_p, C.c_int]
+    L.nlte_get_launch.argtypes = [vp] + [C.POINTER(C.c_int)] * 5
     L.nlte_kernel_stats.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.nlte_reset_kernel_stats.argtypes = [vp]
     L.nlte_executed_steps.argtypes = [vp, C.POINTER(i64)]
@@ -418,6 +419,14 @@ class Solver:
         self._chk(self.L.nlte_get_model_status(self.h, _p(it), _p(cv), _p(ch)))
         return it, cv.astype(bool), ch
 
+    def launch(self):
+        """The formal-solve launch the parameters resolve to: dict of lines_per_lane,
+        waves_per_simd, long_segments, stage_nodes, persistent."""
+        v = [C.c_int() for _ in range(5)]
+        self._chk(self.L.nlte_get_launch(self.h, *[C.byref(x) for x in v]))
+        return dict(zip(("lines_per_lane", "waves_per_simd", "long_segments", "stage_nodes", "persistent"),
+                        (x.value for x in v)))
+
     def autotune(self, cache_path=None, trials=3):
         """Time the formal-solve launch variants and keep the fastest (see nlte_autotune)."""
         buf = C.create_string_buffer(256)
@@ -426,7 +435,9 @@ class Solver:
         choice = buf.value.decode()
         fields = dict(kv.split("=") for kv in choice.split() if "=" in kv)
         self.params.lines_per_lane = int(fields["lpl"])
-        self.params.high_occupancy = int(fields["high"])
+        self.params.waves_per_simd = int(fields["waves"])
+        self.params.long_segments = int(fields["long"])
+        self.params.stage_nodes = int(fields["ns"])
         self.params.persistent = int(fields["persistent"])
         return choice
 

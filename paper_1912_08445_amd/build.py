@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -32,9 +33,15 @@ def build(verbose: bool = False) -> str:
     from concurrent.futures import ThreadPoolExecutor
 
     objdir = os.path.join(PKG, "_build")
+    # identity of the kernel sources, compiled in (keys the autotuner's cache)
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(PKG, "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
+    build_id = h.hexdigest()[:16]
     os.makedirs(objdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
-    cflags = [f for f in FLAGS if f != "-shared"]
+    cflags = [f for f in FLAGS if f != "-shared"] + [f'-DNLTE_BUILD_ID="{build_id}"']
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")

@@ -158,6 +158,28 @@ nlte_status ensure_work(nlte_ctx *c)
     return NLTE_OK;
 }
 
+// Register budget (waves per SIMD), far-wing collapse, LDS staging depth and work
+// distribution of a formal-solve launch with a.lines_per_wave / a.ngrp lines per lane.
+void set_launch_shape(nlte_ctx *c, SolveArgs &a, bool fp32)
+{
+    const int lpl = a.lines_per_wave / a.ngrp;
+    // by rule: 3 waves per SIMD up to two lines per lane, else 2 (measured on the disc: the
+    // whole register file for one wave removes the spills of five FP64 lines per lane but
+    // leaves too little to hide latency)
+    a.waves = (c->cfg.waves >= 1 && c->cfg.waves <= 3) ? c->cfg.waves : (lpl <= 2 ? 3 : 2);
+    // long-segment mode (profile recurrence, far-wing collapse) where sub-step segments are
+    // long: more than two elimination steps per cached cell on average
+    a.collapse = c->cfg.long_seg >= 0 ? c->cfg.long_seg : (c->total_steps > 2 * c->total_cells ? 1 : 0);
+    // the most staged nodes whose LDS keeps the register budget's occupancy (160 KiB per CU)
+    const size_t budget = (size_t)160 * 1024 / (size_t)(4 * a.waves);
+    auto lds = [&](int n) { return fp32 ? formal_solve_lds_f32(lpl, n) : formal_solve_lds_f64(lpl, n); };
+    int ns = kWave;
+    while (ns > 16 && lds(ns) > budget) ns -= 8;
+    if (c->cfg.ns >= 2 && c->cfg.ns <= kWave) ns = c->cfg.ns;
+    a.ns = ns;
+    a.persistent = c->cfg.persistent;
+}
+
 SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
 {
     SolveArgs a{};
@@ -181,27 +203,19 @@ SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
     a.n_q = c->n_q;
     a.n_lines = c->n_lines;
     // A wave takes one or two groups of n_q lanes (one frequency each) and LPL lines per
-    // group: 1 or 2, or 3 in the FP32 form (more exceed the register budget of the sweep).
-    // By rule LPL minimises an estimate of the work per point: 12 units per line slot
-    // (elimination) plus 18 per lane group (one shared profile evaluation), over the waves
-    // the point needs.
+    // group.  By rule: the fewest waves per point (each wave stages the point's rays and
+    // evaluates the profile once per node and frequency for all its lines), then the
+    // fewest lines per lane that keep that count (the least register state per lane).
     const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
+    a.ngrp = ngrp;
     a.fchunks = (c->n_q <= kWave) ? 1 : (c->n_q + kWave - 1) / kWave;
-    const int lpl_max = c->params.precision == NLTE_PREC_FP32_BULK ? 3 : 2;
-    int lpl = 1, best_cost = INT32_MAX;
-    for (int l = 1; l <= lpl_max; ++l) {
-        const int waves = (c->n_lines + ngrp * l - 1) / (ngrp * l);
-        const int cost = waves * ngrp * (12 * l + 18);
-        if (cost < best_cost) {
-            best_cost = cost;
-            lpl = l;
-        }
-        if (ngrp * l >= c->n_lines) break;   // one wave already holds every line
-    }
+    const int waves_min = (c->n_lines + ngrp * kMaxLpl - 1) / (ngrp * kMaxLpl);
+    int lpl = (c->n_lines + ngrp * waves_min - 1) / (ngrp * waves_min);
     // an explicit choice, capped at the lines one lane group can need
-    if (c->cfg.lpl >= 1 && c->cfg.lpl <= lpl_max) lpl = std::min(c->cfg.lpl, (c->n_lines + ngrp - 1) / ngrp);
+    if (c->cfg.lpl >= 1 && c->cfg.lpl <= kMaxLpl) lpl = std::min(c->cfg.lpl, (c->n_lines + ngrp - 1) / ngrp);
     a.lines_per_wave = ngrp * lpl;
     a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
+    set_launch_shape(c, a, c->params.precision == NLTE_PREC_FP32_BULK);
     a.n_blocks = c->P * a.groups;
     a.J = J;
     a.Jeff = Jeff;
@@ -248,7 +262,7 @@ nlte_status formal_solve_impl(nlte_ctx *c, const double *d_pops, double *d_J, do
         a.exec_steps = nullptr;
     }
     if (ali) a.model_done = c->d_model_done;
-    if (c->cfg.persistent) HIPCHK(c, launch_fill_u64(a.work_counter, 1, 0ull, s));
+    if (a.persistent) HIPCHK(c, launch_fill_u64(a.work_counter, 1, 0ull, s));
     auto fs = [&] { return launch_formal_solve(a, c->cfg, fp32, s); };
     HIPCHK(c, capture ? fs() : timed(c, c->st_formal, s, fs));
     return NLTE_OK;
@@ -553,11 +567,17 @@ nlte_status formal_solve_band_impl(nlte_ctx *c, const double *d_pops, double *d_
 {
     HIPCHK(c, launch_line_coef(c->sp, c->d_cell, d_pops, c->P, 0, c->d_lc, c->d_maser, s));
     SolveArgs a = solve_args(c, d_J, d_Jeff, d_L);
-    const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
-    if (a.lines_per_wave / ngrp > 2) {   // the band kernel takes one or two lines per lane
-        a.lines_per_wave = ngrp * 2;
+    if (a.lines_per_wave / a.ngrp > 2) {   // the band kernel takes one or two lines per lane
+        a.lines_per_wave = a.ngrp * 2;
         a.groups = (c->n_lines + a.lines_per_wave - 1) / a.lines_per_wave;
         a.n_blocks = c->P * a.groups;
+    }
+    {   // its own launch: FP64, a budget of two waves per SIMD, the same segment mode
+        const SolveConfig keep = c->cfg;
+        c->cfg.waves = 2;
+        set_launch_shape(c, a, false);
+        c->cfg = keep;
+        a.persistent = 0;
     }
     if (ali) a.model_done = c->d_model_done;
     a.Jb = c->d_Jb;
@@ -815,7 +835,9 @@ void nlte_default_params(nlte_params *p)
     p->profile = 0;
     p->use_graph = 1;
     p->lines_per_lane = 0;
-    p->high_occupancy = 1;
+    p->waves_per_simd = 0;
+    p->long_segments = -1;
+    p->stage_nodes = 0;
     p->persistent = 0;
     p->ng_every = 0;
     p->alo_band = 0;
@@ -1311,15 +1333,20 @@ nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
     if (!c || !p) return NLTE_E_INVALID_ARG;
     if (!(p->t_cmb > 0.0) || !(p->f_sub > 0.0) || !(p->tol >= 0.0) || p->max_iter < 1 ||
         p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
-        p->lines_per_lane < 0 || p->lines_per_lane > (p->precision == NLTE_PREC_FP32_BULK ? 3 : 2) ||
+        p->lines_per_lane < 0 || p->lines_per_lane > kMaxLpl || p->waves_per_simd < 0 ||
+        p->waves_per_simd > 3 || p->long_segments < -1 || p->long_segments > 1 ||
+        !(p->stage_nodes == 0 || (p->stage_nodes >= 2 && p->stage_nodes <= kWave)) ||
         !(p->ng_every == 0 || (p->ng_every >= 3 && p->ng_every <= kNgMaxM)) ||
         !(p->alo_band == 0 || (p->alo_band == 1 && p->use_alo)))
         return fail(c, NLTE_E_INVALID_ARG,
-                    "parameter out of range (lines_per_lane: 0..2, 0..3 in the FP32 form; ng_every: 0 or 3..8; "
+                    "parameter out of range (lines_per_lane: 0..5; waves_per_simd: 0..3; long_segments: -1..1; "
+                    "stage_nodes: 0 or 2..64; ng_every: 0 or 3..8; "
                     "alo_band: 0, or 1 with use_alo)");
     c->params = *p;
     c->cfg.lpl = p->lines_per_lane;
-    c->cfg.high_occupancy = p->high_occupancy ? 1 : 0;
+    c->cfg.waves = p->waves_per_simd;
+    c->cfg.long_seg = p->long_segments;
+    c->cfg.ns = p->stage_nodes;
     c->cfg.persistent = p->persistent ? 1 : 0;
     drop_graphs(c);
     return upload_ibdy(c);
@@ -1703,6 +1730,31 @@ nlte_status nlte_get_model_status(nlte_ctx *c, int32_t *iterations, uint8_t *con
     return NLTE_OK;
 }
 
+#ifndef NLTE_BUILD_ID
+#define NLTE_BUILD_ID "unknown"
+#endif
+
+// Median time of `trials` formal-solve launches (after one warm-up) with launch choice k.
+nlte_status time_choice(nlte_ctx *c, const SolveConfig &k, int trials, double *ms_out)
+{
+    hipStream_t s = c->stream;
+    c->cfg = k;
+    std::vector<float> t;
+    for (int i = 0; i <= trials; ++i) {
+        HIPCHK(c, hipEventRecord(c->ev0, s));
+        nlte_status st = formal_solve_impl(c, c->d_pops_a, c->d_J, c->d_Jeff, c->d_L, s);
+        if (st) return st;
+        HIPCHK(c, hipEventRecord(c->ev1, s));
+        HIPCHK(c, hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        if (i > 0) t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    *ms_out = t[t.size() / 2];
+    return NLTE_OK;
+}
+
 nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char *choice, int cap)
 {
     nlte_status st = need(c, true);
@@ -1710,9 +1762,11 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
     if (trials < 1) trials = 3;
     (void)hipSetDevice(c->device);
     hipStream_t s = c->stream;
+    // the library build is part of the key: choices timed on other kernels are not reused
     char key[512];
-    snprintf(key, sizeof key, "%s|P=%lld|rays=%d|lines=%d|nq=%d|steps=%lld|prec=%d", c->device_name.c_str(),
-             (long long)c->P, c->n_rays, c->n_lines, c->n_q, (long long)c->total_steps, c->params.precision);
+    snprintf(key, sizeof key, "%s|build=%s|P=%lld|rays=%d|lines=%d|nq=%d|steps=%lld|prec=%d",
+             c->device_name.c_str(), NLTE_BUILD_ID, (long long)c->P, c->n_rays, c->n_lines, c->n_q,
+             (long long)c->total_steps, c->params.precision);
     SolveConfig best = c->cfg;
     double best_ms = -1.0;
     bool cached = false;
@@ -1722,12 +1776,15 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
             char line[1024];
             while (fgets(line, sizeof line, f)) {
                 char k2[512];
-                int lpl, hi, pe;
+                int lpl, wv, far, ns, pe;
                 double ms;
-                if (sscanf(line, "%511s lpl=%d high=%d persistent=%d ms=%lf", k2, &lpl, &hi, &pe, &ms) == 5 &&
+                if (sscanf(line, "%511s lpl=%d waves=%d long=%d ns=%d persistent=%d ms=%lf", k2, &lpl, &wv, &far, &ns,
+                           &pe, &ms) == 7 &&
                     strcmp(k2, key) == 0) {
                     best.lpl = lpl;
-                    best.high_occupancy = hi;
+                    best.waves = wv;
+                    best.long_seg = far;
+                    best.ns = ns;
                     best.persistent = pe;
                     best_ms = ms;
                     cached = true;
@@ -1737,61 +1794,95 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
         }
     }
     if (!cached) {
-        // time every launch variant on the current model with LTE populations
         HIPCHK(c, launch_lte(c->sp, c->d_cell, c->d_T, c->P, c->d_pops_a, s));
         const int saved_profile = c->params.profile;
         c->params.profile = 0;
         const SolveConfig saved = c->cfg;
-        const int lpl_max = c->params.precision == NLTE_PREC_FP32_BULK ? 3 : 2;
-        const int ngrp = (2 * c->n_q <= kWave) ? 2 : 1;
-        for (int lpl = 1; lpl <= lpl_max; ++lpl)
-            for (int hi = 0; hi <= 1; ++hi)
-                for (int pe = 0; pe <= 1; ++pe) {
-                    c->cfg.lpl = lpl;
-                    c->cfg.high_occupancy = hi;
-                    c->cfg.persistent = pe;
-                    if (lpl > (c->n_lines + ngrp - 1) / ngrp) continue;   // same as a smaller lpl
-                    std::vector<float> t;
-                    for (int k = 0; k <= trials; ++k) {
-                        HIPCHK(c, hipEventRecord(c->ev0, s));
-                        if ((st = formal_solve_impl(c, c->d_pops_a, c->d_J, c->d_Jeff, c->d_L, s))) {
-                            c->cfg = saved;
-                            c->params.profile = saved_profile;
-                            return st;
-                        }
-                        HIPCHK(c, hipEventRecord(c->ev1, s));
-                        HIPCHK(c, hipEventSynchronize(c->ev1));
-                        float ms = 0.f;
-                        HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-                        if (k > 0) t.push_back(ms);   // the first launch is a warm-up
-                    }
-                    std::sort(t.begin(), t.end());
-                    const double med = t[t.size() / 2];
-                    if (best_ms < 0 || med < best_ms) {
-                        best_ms = med;
-                        best = c->cfg;
-                    }
+        // the rule's choice, made explicit, is the starting point
+        SolveArgs a0 = solve_args(c, nullptr, nullptr, nullptr);
+        SolveConfig cur = saved;
+        cur.lpl = a0.lines_per_wave / a0.ngrp;
+        cur.waves = a0.waves;
+        cur.long_seg = a0.collapse;
+        cur.ns = a0.ns;
+        auto restore = [&](nlte_status code) {
+            c->cfg = saved;
+            c->params.profile = saved_profile;
+            return code;
+        };
+        if ((st = time_choice(c, cur, trials, &best_ms))) return restore(st);
+        best = cur;
+        const int lpl_cap = std::min(kMaxLpl, (c->n_lines + a0.ngrp - 1) / a0.ngrp);
+        for (int dim = 0; dim < 5; ++dim) {
+            std::vector<int> cand;
+            if (dim == 0)
+                for (int v = 1; v <= lpl_cap; ++v) cand.push_back(v);
+            else if (dim == 1)
+                cand = {1, 2, 3};
+            else if (dim == 2)
+                cand = {0, 1};
+            else if (dim == 3)
+                cand = {16, 32, 48, 64};
+            else
+                cand = {0, 1};
+            for (int v : cand) {
+                SolveConfig k = best;
+                int *field = dim == 0 ? &k.lpl : dim == 1 ? &k.waves : dim == 2 ? &k.long_seg : dim == 3 ? &k.ns
+                                                                                                     : &k.persistent;
+                if (*field == v) continue;
+                *field = v;
+                if (dim == 0) k.ns = 0;   // a new line count takes the rule's staging depth
+                double ms = 0.0;
+                if ((st = time_choice(c, k, trials, &ms))) return restore(st);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = k;
                 }
-        c->params.profile = saved_profile;
+            }
+            if (dim == 0 && best.ns == 0) {   // make the staging depth explicit again
+                c->cfg = best;
+                SolveArgs ab = solve_args(c, nullptr, nullptr, nullptr);
+                best.ns = ab.ns;
+            }
+        }
+        restore(NLTE_OK);
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s lpl=%d high=%d persistent=%d ms=%.4f\n", key, best.lpl, best.high_occupancy,
-                        best.persistent, best_ms);
+                fprintf(f, "%s lpl=%d waves=%d long=%d ns=%d persistent=%d ms=%.4f\n", key, best.lpl, best.waves,
+                        best.long_seg, best.ns, best.persistent, best_ms);
                 fclose(f);
             }
         }
     }
     c->cfg.lpl = best.lpl;
-    c->cfg.high_occupancy = best.high_occupancy;
+    c->cfg.waves = best.waves;
+    c->cfg.long_seg = best.long_seg;
+    c->cfg.ns = best.ns;
     c->cfg.persistent = best.persistent;
     c->params.lines_per_lane = best.lpl;
-    c->params.high_occupancy = best.high_occupancy;
+    c->params.waves_per_simd = best.waves;
+    c->params.long_segments = best.long_seg;
+    c->params.stage_nodes = best.ns;
     c->params.persistent = best.persistent;
     drop_graphs(c);
     if (choice && cap > 0)
-        snprintf(choice, cap, "lpl=%d high=%d persistent=%d ms=%.4f%s", best.lpl, best.high_occupancy,
-                 best.persistent, best_ms, cached ? " (cached)" : "");
+        snprintf(choice, cap, "lpl=%d waves=%d long=%d ns=%d persistent=%d ms=%.4f%s", best.lpl, best.waves,
+                 best.long_seg, best.ns, best.persistent, best_ms, cached ? " (cached)" : "");
+    return NLTE_OK;
+}
+
+nlte_status nlte_get_launch(nlte_ctx *c, int *lines_per_lane, int *waves_per_simd, int *long_segments, int *stage_nodes,
+                            int *persistent)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    const SolveArgs a = solve_args(c, nullptr, nullptr, nullptr);
+    if (lines_per_lane) *lines_per_lane = a.lines_per_wave / a.ngrp;
+    if (waves_per_simd) *waves_per_simd = a.waves;
+    if (long_segments) *long_segments = a.collapse;
+    if (stage_nodes) *stage_nodes = a.ns;
+    if (persistent) *persistent = a.persistent;
     return NLTE_OK;
 }
 

@@ -76,7 +76,12 @@ struct SolveArgs {
     int n_rays, n_pairs, n_q, n_lines;
     int groups;              // waves per point
     int lines_per_wave;      // lines one wave serves (lane groups x lines per lane)
+    int ngrp;                // lane groups per wave (2 when 2 n_q <= 64, else 1)
     int fchunks;             // frequency chunks per wave (n_q > 64), else 1
+    int ns;                  // ray nodes a wave stages in LDS per round (2..64)
+    int waves;               // register budget of the launch: 2 or 3 waves per SIMD
+    int collapse;            // 1: long-segment mode (profile recurrence, far-wing collapse)
+    int persistent;          // 1: items from the work counter in decreasing-cost order
     int64_t n_blocks;        // work items (P * groups)
     double *J, *Jeff, *L;    // [P][n_lines]
     double *Jb, *Ld;         // band operator: J without the band's share, its diagonal [P][n_lines]
@@ -161,9 +166,12 @@ struct NgHist {
 };
 
 // Launch choices of the formal solve (picked by rule or by the autotuner).
+constexpr int kMaxLpl = 5;    // lines per lane
 struct SolveConfig {
-    int lpl = 0;              // lines per lane (1 or 2; 0 = by rule)
-    int high_occupancy = 1;   // 1: ask for 3-4 waves per SIMD
+    int lpl = 0;              // lines per lane (1..kMaxLpl; 0 = by rule)
+    int waves = 0;            // register budget for 2 or 3 waves per SIMD (0 = by rule)
+    int long_seg = -1;        // long-segment mode: 1 on, 0 off, -1 by the trace's steps per cell
+    int ns = 0;               // ray nodes staged per round (2..64; 0 = by rule)
     int persistent = 0;       // 1: work-queue kernel in decreasing-cost order
     int n_wg = 0;             // workgroups of the persistent kernel
 };
@@ -373,6 +381,11 @@ hipError_t scan_lengths(int64_t *len_then_off, int64_t n, void *tmp, size_t *tmp
 hipError_t launch_line_coef(const SpeciesDev &sp, const CellRec *cell, const double *pops,
                             int64_t P, int fp32, void *lc, int64_t *maser_count, hipStream_t s);
 hipError_t launch_formal_solve(const SolveArgs &a, const SolveConfig &cfg, int fp32, hipStream_t s);
+hipError_t launch_formal_solve_f64(const SolveArgs &a, const SolveConfig &cfg, hipStream_t s);
+hipError_t launch_formal_solve_f32(const SolveArgs &a, const SolveConfig &cfg, hipStream_t s);
+// dynamic LDS bytes of one formal-solve workgroup with lpl lines per lane and ns staged nodes
+size_t formal_solve_lds_f64(int lpl, int ns);
+size_t formal_solve_lds_f32(int lpl, int ns);
 hipError_t launch_formal_solve_band(const SolveArgs &a, hipStream_t s);
 hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, unsigned long long *point_cost,
                               hipStream_t s);

@@ -76,8 +76,8 @@ def test_graph_replay_matches_eager():
     assert np.array_equal(pg, pg2)
 
 
-@pytest.mark.parametrize("kw", [dict(persistent=1), dict(lines_per_lane=1), dict(high_occupancy=0),
-                                dict(persistent=1, lines_per_lane=1, high_occupancy=0)])
+@pytest.mark.parametrize("kw", [dict(persistent=1), dict(lines_per_lane=1), dict(waves_per_simd=2),
+                                dict(persistent=1, lines_per_lane=1, waves_per_simd=1)])
 def test_launch_variants_identical(kw):
     w = configs.outflow5(n_points=3000, seed=13)
     base = solver_for(w)
@@ -99,8 +99,8 @@ def test_autotune_choice_and_cache():
         c1 = s.autotune(cache, trials=2)
         assert "lpl=" in c1 and "(cached)" not in c1
         out = s.formal_solve(pops)
-        for a, b in zip(ref, out):
-            assert rel(a, b).max() <= 1e-14
+        for a, b in zip(ref, out):   # (long and short segment modes agree to rounding)
+            assert rel(a, b).max() <= 1e-12
         s2 = solver_for(w)
         c2 = s2.autotune(cache, trials=2)
         assert c2.endswith("(cached)") and c2.split()[:3] == c1.split()[:3]

@@ -31,8 +31,9 @@ def _config(seed):
                           (np.array([0.0]), np.array([1.0])))
     w.rays = [directions.axis_pair(), directions.healpix_ring(1), directions.healpix_ring(2)][int(rng.integers(0, 3))]
     w.f_sub = float(rng.choice([0.1, 0.25, 0.5]))
-    launch = dict(lines_per_lane=int(rng.choice([0, 1, 2])), high_occupancy=int(rng.integers(0, 2)),
-                  persistent=int(rng.integers(0, 2)))
+    launch = dict(lines_per_lane=int(rng.choice([0, 1, 2, 3, 4, 5])), waves_per_simd=int(rng.integers(0, 4)),
+                  persistent=int(rng.integers(0, 2)), long_segments=int(rng.integers(-1, 2)),
+                  stage_nodes=int(rng.choice([0, 2, 9, 24, 64])))
     desc = f"seed {seed}: {w.name} n={n} lev={nlev} q={q} rays={w.rays.shape[0]} f_sub={w.f_sub} {launch}"
     return w, launch, desc, rng
 
