@@ -21,10 +21,10 @@ namespace nlte {
 constexpr double kSqrt2 = 1.41421356237309504880;
 constexpr double kInv2Sqrt2 = 0.35355339059327376220;  // 1 / (2 sqrt 2)
 // The elimination state only grows (see elim_step); it is rescaled by a power of two once
-// any line's D passes 2^500, which leaves room for a step with D_+ up to about 2^250
-// before the FP64 range ends.  Power-of-two rescaling is exact, so when it happens does
-// not change any result.
-constexpr double kRenormAbove = 3.2733906078961419e150;   // 2^500
+// any line's D passes 2^300, checked after every node and at least every fourth sub-step,
+// which leaves room for steps with D_+ up to about 2^70 before the FP64 range ends.
+// Power-of-two rescaling is exact, so when it happens does not change any result.
+constexpr double kRenormAbove = 2.0370359763344861e90;   // 2^300
 
 template <bool F32>
 struct Bulk {
@@ -275,9 +275,11 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
             }
         }
         for (int i = 0; i < nseg; ++i) {
-            if (rec[i].m == 1) {
+            if (!F32 && !COLLAPSE && rec[i].m == 1) {
                 // a run of segments without sub-steps (most of a disc's rays): one step per
-                // node with the profile evaluated there, in a loop of its own
+                // node with the profile evaluated there, in a loop of its own (FP64 short-
+                // segment mode; the FP32 form, whose exponential is one instruction, and the
+                // long-segment mode measured faster without it)
                 do {
                     const T dzq = rec[i].dzq;
                     const T xn = rec[i + 1].a * xq - rec[i + 1].b;
@@ -345,8 +347,8 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                 const T dx = rec[i].da * xq - rec[i].db;
                 const int K = rec[i].K;
                 // direct evaluation where the recurrence would not pay for its two
-                // exponentials (one sub-step node) or cannot be used (K == 0)
-                if (F32 || !COLLAPSE || K == 0 || m == 2) {
+                // exponentials (no or one sub-step node) or cannot be used (K == 0)
+                if (F32 || !COLLAPSE || K == 0 || m <= 2) {
                     T S0[LPL], dk[LPL], dS[LPL];
 #pragma unroll
                     for (int l = 0; l < LPL; ++l) {
@@ -361,7 +363,7 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                         for (int l = 0; l < LPL; ++l)
                             elim_step<F32, false, TRACK>((ls.k_cur[l] + tj * dk[l]) * gq, S0[l] + tj * dS[l],
                                                          a_prev[l], ls.S_e[l], ls.st[l]);
-                        rescale_if_big<LPL, TRACK>(ls);
+                        if ((j & 3) == 0) rescale_if_big<LPL, TRACK>(ls);   // (the end node checks too)
                     }
                     gn = profile_far(xn, tab);
                     travel = 0.0;
@@ -654,24 +656,28 @@ __global__ __launch_bounds__(64, W) void k_formal_solve(SolveArgs a)
         if (threadIdx.x < 16) tab[threadIdx.x] = kExp2Sixteenths[threadIdx.x];
         __syncthreads();
     }
+    // one call site for both forms (the sweep is compiled once): a grid workgroup takes
+    // its own item and stops
+    __shared__ unsigned long long item_s;
+    int64_t item;
     if (a.persistent) {
-        __shared__ unsigned long long item_s;
-        for (;;) {
-            __syncthreads();
-            if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1ull);
-            __syncthreads();
-            const int64_t item = (int64_t)item_s;
-            if (item >= a.n_blocks) break;
-            const int64_t rank = item / a.groups;
-            solve_item<F32, LPL, COLLAPSE>(a, (int64_t)a.order[rank], (int)(item - rank * a.groups), rec, red, tab);
-        }
-        return;
+        if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1ull);
+        __syncthreads();
+        item = (int64_t)item_s;
+    } else {
+        const int64_t nb8 = (a.n_blocks + 7) / 8;
+        item = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
     }
-    const int64_t nb8 = (a.n_blocks + 7) / 8;
-    const int64_t lb = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
-    if (lb >= a.n_blocks) return;
-    const int64_t O = lb / a.groups;
-    solve_item<F32, LPL, COLLAPSE>(a, O, (int)(lb - O * a.groups), rec, red, tab);
+    while (item < a.n_blocks) {
+        const int64_t rank = item / a.groups;
+        const int64_t O = a.persistent ? (int64_t)a.order[rank] : rank;
+        solve_item<F32, LPL, COLLAPSE>(a, O, (int)(item - rank * a.groups), rec, red, tab);
+        if (!a.persistent) break;
+        __syncthreads();
+        if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1ull);
+        __syncthreads();
+        item = (int64_t)item_s;
+    }
 }
 
 template <bool F32, int LPL, int W, bool COLLAPSE>
