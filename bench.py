@@ -5,8 +5,10 @@ resident in HBM: line coefficients, the ray-pair formal solve with J / L* / Jeff
 accumulation, and the statistical-equilibrium update.  The ray walks are traced once
 before timing (they depend only on the geometry).
 
-Workload (default): outflow5 -- 50,000 points in a sphere, 48 HEALPix rays, 5-level
-linear rotor (4 lines x 31 frequencies), radial outflow of 15 km/s.
+Workload (default): disc10 -- a Keplerian disc of 1,000,000 points, 192 HEALPix rays,
+10-level linear rotor (9 lines x 31 frequencies), FP64 (the largest single-GPU
+configuration); --workload outflow5 selects the 50,000-point outflow sphere, which also
+times the Ng, band-ALO and scattering ALI forms and the channel images.
 
 Prints one JSON line.  `value` is formal-solve throughput in point*ray*frequency per
 second of step time; `roofline` covers the formal-solve kernel, which is bound by VALU
@@ -15,7 +17,11 @@ optical depth: add, multiply; Rybicki-Hummer step: h, T, 1 + D T, reciprocal, Q,
 an FMA counted as 2, the exponential and the reciprocal as 1 each), counted on the steps the
 kernel executes (a far-wing segment with zero opacity throughout is one step), against the
 78.6 TFLOP/s FP64 vector peak; `cpu_baseline` is the FP64 CPU oracle timed on a bounded
-sample of origin points on this host.
+sample of origin points on this host.  Beside the FP64 line: the FP32-bulk form's sweep,
+the ALI forms (iterations and wall time to a relative change of 1e-4 against FP64
+populations converged to 1e-9) and, on the disc family, the learned warm start on five
+held-out seeds with the combined fast form (FP32 bulk, batched, learned start) against
+plain FP64 from LTE.
 """
 from __future__ import annotations
 
@@ -49,9 +55,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("formal_solve.hip", "formal_solve_kernels.h", "fs_fp64.hip", "fs_fp32.hip", "device_math.h")
+
+
 def kernel_source_hash():
-    p = os.path.join(ROOT, "paper_1912_08445_amd", "csrc", "formal_solve.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1912_08445_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(workload_name, precision, launch_steps):
@@ -114,9 +125,11 @@ def cpu_baseline(w, target_s=15.0):
     except OSError:
         pass
     return {"value": units / dt, "unit": "point*ray*freq/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} random origin points of {w.n_points} (all {w.rays.shape[0]} rays, "
+            "sample": f"{n} seeded random origin points of {w.n_points} (all {w.rays.shape[0]} rays, "
                       f"{w.species.n_lines} lines x {w.quad_x.shape[0]} frequencies), LTE "
-                      f"populations, formal solve only, {dt:.1f} s wall",
+                      f"populations, formal solve only, {dt:.1f} s wall; the rate is per origin, so the "
+                      f"whole sweep is a linear extrapolation of the sample",
+            "full_sweep_s_extrapolated": w.n_points * per_point / (units / dt),
             "cpu_model": cpu, "value_1_thread": n1 * per_point / dt1,
             "sample_1_thread": f"the first {n1} of those points, {dt1:.1f} s wall"}
 
@@ -129,14 +142,124 @@ def _rel_err(p, ref, ntot):
     return float(np.max(2 * np.abs(a - b) / (np.abs(a) + np.abs(b))))
 
 
+HELD_OUT_SEEDS = (200, 201, 202, 203, 204)
+
+
+def held_out_discs(args, dev):
+    """The learned warm start on the disc family (discs of args.disc_points points): a
+    network trained on converged populations of args.train_models training seeds
+    (100, 101, ...), evaluated on the five held-out seeds 200..204 -- per seed the plain
+    FP64 ALI from LTE and the FP64 ALI from the learned start, each to a relative change
+    of 1e-4 against FP64 populations converged to 1e-9 -- and the combined fast form: the
+    five models batched in one context (persistent launch), FP32 bulk, learned start,
+    against the plain FP64 ALIs run one model at a time."""
+    import numpy as np
+    import torch
+
+    from paper_1912_08445_amd import warmstart
+    from paper_1912_08445_amd.binding import Solver
+    from synth import configs
+    from synth.configs import Workload
+    from synth.models import concat_models
+    n = args.disc_points
+    t0 = time.perf_counter()
+    mean = std = None
+    rows = []
+    for k, sd in enumerate(range(100, 100 + args.train_models)):
+        st = Solver(0)
+        st.setup(configs.disc10(n_points=n, seed=sd), precision="fp32")
+        if mean is None:
+            mean, std = warmstart.feature_norm([st.features()])
+        X, T, rep = warmstart.converged_rows(st, mean, std, tol=1e-6, sample=args.train_sample)
+        rows.append((X, T))
+        st.close()
+        log(f"held-out block: training disc {k + 1}/{args.train_models} (seed {sd}): {rep['iterations']} iterations")
+    t_data = time.perf_counter() - t0
+    # the five held-out discs batched in one context (persistent launch, FP32 bulk), which
+    # also trains the network
+    ws = [configs.disc10(n_points=n, seed=sd) for sd in HELD_OUT_SEEDS]
+    offs, merged = concat_models([w.model for w in ws])
+    bw = Workload("held-out discs", merged, ws[0].species, ws[0].rays, ws[0].quad_x, ws[0].quad_w, offsets=offs)
+    b = Solver(0)
+    b.setup(bw, precision="fp32", persistent=1)
+    t0 = time.perf_counter()
+    curve = warmstart.train(b, rows, mean, std, warmstart.SCHEDULE, batch=4096, seed=1)
+    t_train = time.perf_counter() - t0
+    theta = b.mlp_get_weights()
+    n_lev = 10
+    log(f"held-out block: {sum(int(r[0].shape[0]) for r in rows)} rows, data {t_data:.1f} s, training "
+        f"{t_train:.1f} s, loss {curve[:5].mean():.3e} -> {curve[-50:].mean():.3e}")
+    res = {"disc_points": n, "rays": 192, "train_seeds": list(range(100, 100 + args.train_models)),
+           "rows": sum(int(r[0].shape[0]) for r in rows), "data_s": t_data, "train_s": t_train,
+           "loss_start": float(curve[:5].mean()), "loss_end": float(curve[-50:].mean()), "seeds": {}}
+
+    def best_of(fn):
+        best = None
+        for _ in range(max(1, args.ali_runs)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            if best is None or wall < best[0]:
+                best = (wall, r)
+        return best
+
+    refs = []
+    for sd, w in zip(HELD_OUT_SEEDS, ws):
+        s = Solver(0)
+        s.setup(w, precision="fp64")
+        s.mlp_set_weights(theta, n_lev)
+        s.mlp_set_norm(mean, std)
+        out = torch.empty((w.n_points, n_lev), dtype=torch.float64, device=dev)
+        s.set_params(tol=1e-9, max_iter=500)
+        s.run_ali_dev(None, out)
+        torch.cuda.synchronize()
+        ref = out.cpu().numpy()
+        refs.append(ref)
+        ntot = w.model.abundance * w.model.n_h2
+        s.set_params(tol=1e-4, max_iter=200)
+        e = {}
+        for key, fn in (("fp64_lte", lambda: s.run_ali_dev(None, out)), ("fp64_warm", lambda: s.run_ali_warm_dev(out))):
+            wall, r = best_of(fn)
+            e[key] = {"iterations": r["iterations"], "wall_s": wall,
+                      "max_rel_diff_vs_fp64_reference": _rel_err(out.cpu().numpy(), ref, ntot),
+                      "max_change": [float(c) for c in r["max_change"]]}
+        s.close()
+        res["seeds"][sd] = e
+        log(f"held-out seed {sd}: FP64 from LTE {e['fp64_lte']['iterations']} iterations "
+            f"{e['fp64_lte']['wall_s']:.3f} s; from the learned start {e['fp64_warm']['iterations']} iterations "
+            f"{e['fp64_warm']['wall_s']:.3f} s")
+    b.set_params(tol=1e-4, max_iter=200)
+    out = torch.empty((bw.n_points, n_lev), dtype=torch.float64, device=dev)
+    wall, r = best_of(lambda: b.run_ali_warm_dev(out))
+    pops = out.cpu().numpy()
+    its = b.model_status()[0]
+    ntot = merged.abundance * merged.n_h2
+    errs = [_rel_err(pops[offs[m]:offs[m + 1]], refs[m], ntot[offs[m]:offs[m + 1]]) for m in range(len(refs))]
+    plain = sum(res["seeds"][sd]["fp64_lte"]["wall_s"] for sd in HELD_OUT_SEEDS)
+    res["combined"] = {"form": "FP32 bulk, 5 models batched in one persistent launch per sweep, learned start",
+                       "iterations": r["iterations"], "model_iterations": [int(x) for x in its], "wall_s": wall,
+                       "used_network": r["used_network"], "max_rel_diff_vs_fp64_reference": max(errs),
+                       "plain_fp64_lte_wall_s": plain, "wall_ratio": wall / plain,
+                       "plain_fp64_lte_iterations": [res["seeds"][sd]["fp64_lte"]["iterations"] for sd in HELD_OUT_SEEDS]}
+    log(f"combined fast form on the 5 held-out discs: {r['iterations']} iterations (models {list(its)}), "
+        f"{wall:.3f} s against {plain:.3f} s of plain FP64 from LTE ({wall / plain:.2f}x), max rel diff "
+        f"{max(errs):.2e}")
+    b._bench_rows = rows
+    res["mlp"] = mlp_timing(b, bw, dev)
+    b.close()
+    return res
+
+
 def training_factory(args, make):
     """Single training models of the measured workload's family, by seed (None: no warm
     start for this workload)."""
     from synth import configs
     if args.workload == "discs":
         return (lambda sd: configs.disc_model(sd)), 100
-    if args.workload == "batch256":
-        return None, 0
+    if args.workload in ("batch256", "disc10"):
+        return None, 0   # (the disc family has its own held-out block)
     if args.points is None:
         return (lambda sd: make(seed=sd)), 101
     return (lambda sd: make(n_points=args.points, seed=sd)), 101
@@ -415,22 +538,27 @@ def mlp_timing(s, w, dev, steps=50):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="outflow5", choices=["outflow5", "sphere2", "disc10", "batch256", "discs"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="disc10", choices=["disc10", "outflow5", "sphere2", "batch256", "discs"])
     ap.add_argument("--autotune", default=None, metavar="CACHE",
                     help="pick the formal-solve launch variant by timing (cache file path)")
     ap.add_argument("--points", type=int, default=None, help="override the point count")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ali", action="store_true")
-    ap.add_argument("--ali-runs", type=int, default=3,
-                    help="runs per ALI form, the fastest reported (the first also captures the graphs)")
+    ap.add_argument("--ali-runs", type=int, default=None,
+                    help="runs per ALI form, the fastest reported (the first also captures the graphs); "
+                         "default 1 for disc10, else 3")
+    ap.add_argument("--fp32-steps", type=int, default=2, help="timed sweeps of the FP32-bulk form")
+    ap.add_argument("--no-held-out", action="store_true", help="skip the disc family's held-out warm-start block")
+    ap.add_argument("--disc-points", type=int, default=100000,
+                    help="points of each disc of the held-out warm-start block")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the Ng, band-ALO and scattering ALI forms and the image timing")
     ap.add_argument("--train-models", type=int, default=None,
-                    help="other seeds of the workload whose converged populations train the warm start "
-                         "(0: no warm start; default 48 for discs, else 8)")
+                    help="other seeds of the workload (of the disc family for disc10) whose converged "
+                         "populations train the warm start (0: no warm start; default 48 for discs, else 8)")
     ap.add_argument("--train-sample", type=int, default=20000,
                     help="rows taken from each training model")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -439,6 +567,10 @@ def main():
     args = ap.parse_args()
     if args.train_models is None:
         args.train_models = 48 if args.workload == "discs" else 8
+    if args.ali_runs is None:
+        args.ali_runs = 1 if args.workload == "disc10" else 3
+    if args.workload == "disc10":
+        args.no_variants = True
 
     if args.copy_probe_mib > 0:
         import torch
@@ -503,8 +635,11 @@ def main():
         s.stateq_dev(bufs[0], J, Je, L, bufs[1])
         bufs.reverse()
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        if P >= 200000:
+            torch.cuda.synchronize()
+            log(f"  warmup step {i + 1}/{args.warmup}")
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
@@ -519,6 +654,8 @@ def main():
     ev0.record(stream)
     for i in range(args.steps):
         step()
+        if (i + 1) % 5 == 0 and i + 1 < args.steps:
+            log(f"  timed step {i + 1}/{args.steps}")
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_total = ev0.elapsed_time(ev1)
@@ -534,6 +671,7 @@ def main():
 
     units = P * w.rays.shape[0] * nl * w.quad_x.shape[0]
     value = units / (ms_step * 1e-3)
+    launch = s.launch()
     node_freq = steps_per_freq * nl * w.quad_x.shape[0]
     # the kernel collapses far-wing segments (zero opacity throughout) into one step, so
     # the flops it performs are counted on the steps it executes, not the method's
@@ -547,9 +685,36 @@ def main():
             "executed_node_freq_per_launch": exec_per_launch,
             "flops_per_node_freq": FLOPS_PER_STEP}
 
+    # the FP32-bulk form's sweep on the same model
+    fp32_form = None
+    if args.precision == "fp64" and args.fp32_steps > 0:
+        s.set_params(precision="fp32")
+        s.lte_dev(pops)
+        s.formal_solve_dev(pops, J, Je, L)
+        torch.cuda.synchronize()
+        s.set_params(profile=1)
+        s.reset_kernel_stats()
+        for _ in range(args.fp32_steps):
+            s.formal_solve_dev(pops, J, Je, L)
+        torch.cuda.synchronize()
+        f_ms, f_n = s.kernel_stats("formal_solve")
+        f_exec = s.executed_steps() / max(f_n, 1)
+        s.set_params(profile=0, precision="fp64")
+        f_ms /= max(f_n, 1)
+        f_tf = f_exec * FLOPS_PER_STEP / (f_ms * 1e-3) / 1e12
+        fp32_form = {"kernel_ms": f_ms, "value": units / (f_ms * 1e-3), "unit": "point*ray*freq/s (kernel time)",
+                     "executed_node_freq_per_launch": f_exec, "achieved_tflops": f_tf,
+                     "frac_of_fp64_peak": f_tf / PEAK_FP64_TFLOPS, "launch": s.launch()}
+        log(f"FP32-bulk form: formal_solve kernel {f_ms:.3f} ms ({f_tf:.1f} TFLOP/s by the 17-flop count)")
+
     ali = None
     if not args.no_ali:
         ali = ali_forms(s, w, make, args, dev)
+
+    held = None
+    if args.workload == "disc10" and not args.no_held_out and args.train_models > 0:
+        s.close()   # one million-point model less in HBM while the block runs
+        held = held_out_discs(args, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -575,11 +740,14 @@ def main():
         "config": {"workload": desc, "points": P, "rays": int(w.rays.shape[0]), "lines": nl,
                    "frequencies": int(w.quad_x.shape[0]), "levels": nlev,
                    "precision": args.precision, "cells_cached": total_cells,
-                   "node_freq_per_sweep": node_freq, "models": w.n_models, "launch": tuned},
+                   "node_freq_per_sweep": node_freq, "models": w.n_models, "launch": launch,
+                   "autotuned": tuned},
         "node_freq_per_s": node_freq / (ms_step * 1e-3),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "fp32_form": fp32_form,
         "ali": ali,
+        "held_out_warm_start": held,
     }
     print(json.dumps(line), flush=True)
 

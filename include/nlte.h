@@ -221,6 +221,13 @@ nlte_status nlte_get_order(nlte_ctx *ctx, int64_t *perm);
 nlte_status nlte_trace_stats(nlte_ctx *ctx, int64_t *total_cells, int *max_len,
                              int64_t *total_steps);
 
+/* Work per origin point as the trace counts it (Sec. 3.2 walks with the velocity
+ * sub-steps of Sec. 3.2.1): for each point, the sum over its rays of the ray's elimination
+ * steps for one frequency of one line (one per cached cell, or that cell's number of
+ * sub-steps) plus one.  cost [P] (host).  The persistent formal solve hands out points in
+ * decreasing order of this cost. */
+nlte_status nlte_get_point_cost(nlte_ctx *ctx, int64_t *cost);
+
 /* Per-point line-width speed sqrt(2kT/m + v_turb^2) [cm/s] as the kernels use it. */
 nlte_status nlte_get_line_width_speed(nlte_ctx *ctx, double *vw);
 

@@ -30,7 +30,7 @@ PREC_FP32_BULK = 1
 EXPORTS = (
     "nlte_default_params", "nlte_create", "nlte_destroy", "nlte_last_error", "nlte_set_species",
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
-    "nlte_get_ray", "nlte_get_order", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
+    "nlte_get_ray", "nlte_get_order", "nlte_get_point_cost", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_formal_solve_noalloc_dev", "nlte_stateq", "nlte_stateq_dev",
     "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_rays_healpix", "nlte_get_rays", "nlte_set_scattering", "nlte_formal_solve_scat",
     "nlte_formal_solve_scat_dev", "nlte_scattering_field",
@@ -105,6 +105,7 @@ def load():
     L.nlte_trace.argtypes = [vp]
     L.nlte_get_ray.argtypes = [vp, i64, C.c_int, vp, C.c_int, C.POINTER(C.c_int)]
     L.nlte_get_order.argtypes = [vp, vp]
+    L.nlte_get_point_cost.argtypes = [vp, vp]
     L.nlte_trace_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int), C.POINTER(i64)]
     L.nlte_get_line_width_speed.argtypes = [vp, vp]
     L.nlte_lte.argtypes = [vp, vp]
@@ -293,6 +294,12 @@ class Solver:
         """Morton processing order of the points (global indices)."""
         out = np.zeros(self.P, dtype=np.int64)
         self._chk(self.L.nlte_get_order(self.h, _p(out)))
+        return out
+
+    def point_cost(self):
+        """Elimination steps per frequency from each origin point over all its rays."""
+        out = np.zeros(self.P, dtype=np.int64)
+        self._chk(self.L.nlte_get_point_cost(self.h, _p(out)))
         return out
 
     def trace_stats(self):

@@ -915,6 +915,7 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_active);
     dfree(c->d_work_counter);
     dfree(c->d_order);
+    dfree(c->d_cost);
     dfree(c->d_model_of);
     dfree(c->d_model_off);
     dfree(c->d_morton);
@@ -1398,19 +1399,15 @@ nlte_status nlte_trace(nlte_ctx *c)
     c->max_len = mx;
     // elimination steps per frequency (cells + velocity sub-steps), per-point cost and
     // the points in decreasing-cost order for the persistent formal solve
-    unsigned long long *cost = nullptr;
-    if ((st = dalloc(c, &cost, c->P))) return st;
-    if ((st = dalloc(c, &c->d_order, c->P))) {
-        dfree(cost);
-        return st;
-    }
+    if ((st = dalloc(c, &c->d_cost, c->P))) return st;
+    if ((st = dalloc(c, &c->d_order, c->P))) return st;
+    unsigned long long *cost = c->d_cost;
     hipError_t e2 = hipMemsetAsync(cost, 0, sizeof(unsigned long long) * c->P, s);
     if (e2 == hipSuccess) e2 = hipMemsetAsync(c->d_maser, 0, sizeof(int64_t), s);
     SolveArgs a = solve_args(c, nullptr, nullptr, nullptr);
     if (e2 == hipSuccess) e2 = launch_count_steps(a, c->d_maser, cost, s);
     if (e2 == hipSuccess) e2 = hipMemcpyAsync(&c->total_steps, c->d_maser, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e2 == hipSuccess) e2 = sort_by_cost(cost, c->d_order, c->P, s);
-    dfree(cost);
     if (e2 != hipSuccess) return fail(c, NLTE_E_HIP, std::string("step count: ") + hipGetErrorString(e2));
     drop_graphs(c);
     c->traced = true;
@@ -1447,6 +1444,16 @@ nlte_status nlte_get_order(nlte_ctx *c, int64_t *perm)
     std::vector<int32_t> o(c->P);
     HIPCHK(c, hipMemcpy(o.data(), c->d_morton, sizeof(int32_t) * c->P, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < c->P; ++i) perm[i] = o[i];
+    return NLTE_OK;
+}
+
+nlte_status nlte_get_point_cost(nlte_ctx *c, int64_t *cost)
+{
+    nlte_status st = need(c, true);
+    if (st) return st;
+    if (!cost) return fail(c, NLTE_E_INVALID_ARG, "null output");
+    static_assert(sizeof(unsigned long long) == sizeof(int64_t), "cost element size");
+    HIPCHK(c, hipMemcpy(cost, c->d_cost, sizeof(int64_t) * c->P, hipMemcpyDeviceToHost));
     return NLTE_OK;
 }
 

@@ -268,6 +268,7 @@ struct nlte_ctx {
 
     // ray cache, per-point costs and the decreasing-cost order
     int32_t *d_order = nullptr;                 // [P]
+    unsigned long long *d_cost = nullptr;       // [P] elimination steps per frequency
     unsigned long long *d_work_counter = nullptr;
     unsigned long long *d_exec = nullptr;   // executed formal-solve steps (profile mode)
     bool traced = false;

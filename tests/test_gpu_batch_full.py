@@ -1,7 +1,8 @@
 """The 256-model batch (about 1.26 M points, 48 rays, 4 lines x 31 frequencies) at full
 size in the launch configuration the benchmark's autotuner picks for it (persistent
-cost-ordered queue, two lines per lane): sampled origins of sampled models against the
-oracle in both precision forms, and the FP32 form against the FP64 one at every point."""
+cost-ordered queue, two lines per lane): 100 origins of 20 models (those holding the
+costliest points and random others; in each its costliest origins and random ones)
+against the oracle in both precision forms, and the FP32 form against the FP64 one at every point."""
 import numpy as np
 import pytest
 
@@ -33,15 +34,32 @@ def test_batch256_full_size_sampled():
     s.set_params(precision="fp32")
     J32, Je32, L32 = s.formal_solve(pops)
     print("fp32 sweep done", flush=True)
+    # 20 models: those holding the costliest points, then seeded random others; in each,
+    # its 2 costliest origins and 3 random ones (100 origins)
+    cost = s.point_cost()
+    model_of = np.searchsorted(w.offsets, np.arange(w.n_points), side="right") - 1
+    models = []
+    for p in np.argsort(-cost, kind="stable"):
+        if model_of[p] not in models:
+            models.append(int(model_of[p]))
+        if len(models) == 10:
+            break
     rng = np.random.default_rng(8)
-    for m in rng.choice(w.n_models, 3, replace=False):
-        wm, o0 = _model(w, int(m))
+    others = [m for m in rng.permutation(w.n_models) if m not in models]
+    models += [int(m) for m in others[:10]]
+    n_checked = 0
+    for m in models:
+        wm, o0 = _model(w, m)
         o = oracle_for(wm)
-        loc = rng.choice(wm.n_points, 2, replace=False)
+        c = cost[o0:o0 + wm.n_points]
+        top = np.argsort(-c, kind="stable")[:2]
+        loc = np.concatenate([top, rng.choice(np.setdiff1d(np.arange(wm.n_points), top), 3, replace=False)])
         rJ, rJe, rL = o.formal_solve(pops[o0:o0 + wm.n_points], sel=loc)
         g = o0 + loc
         assert rel(J[g], rJ).max() <= 1e-10 and rel(Je[g], rJe).max() <= 1e-10 and rel(L[g], rL).max() <= 1e-10
-        assert rel(J32[g], rJ).max() <= 1e-4
+        assert rel(J32[g], rJ).max() <= 1e-4 and rel(Je32[g], rJe).max() <= 1e-4 and rel(L32[g], rL).max() <= 1e-4
+        n_checked += len(loc)
+    assert n_checked == 100
     print("oracle done", flush=True)
     errs = {k: float(rel(a, b).max()) for k, a, b in (("J", J32, J), ("Jeff", Je32, Je), ("L*", L32, L))}
     print("FP32 vs FP64 over all points:", errs, flush=True)
