@@ -71,10 +71,12 @@ def lib():
         L.or_walk_all.restype = C.c_int64
         L.or_features.argtypes = [C.c_void_p, _dp]
         L.or_formal_solve_band.argtypes = [C.c_void_p, _dp, C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.or_solve_ray_gen.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int,
+        L.or_solve_ray_gen.argtypes = [C.c_int, _dp, _dp, C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_int,
                                        C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        L.or_formal_solve_scat.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int64, C.c_void_p, _dp, _dp, _dp, _dp]
+        L.or_solve_ray_gen.restype = C.c_int
+        L.or_formal_solve_scat.argtypes = [C.c_void_p, _dp, _dp, C.c_void_p, _dp, C.c_int64, C.c_void_p, _dp, _dp,
+                                           _dp, _dp]
         L.or_formal_solve_scat.restype = C.c_int
         L.or_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -111,13 +113,18 @@ def solve_ray(z, chi, S, I_lo, I_hi, o, tau_floor=1e-100, want_all=False):
     return u.value, lam.value, ue.value
 
 
-def solve_ray_gen(z, chi, Splus, sigma, I_lo, I_hi, o, own=0.0, tau_floor=1e-100):
-    """Generalised Feautrier solve (Eq. GFE with an isotropic scattering opacity) on
-    explicit nodes: returns (u_o, Lambda_oo, ueff_o, v_o)."""
+def solve_ray_gen(z, chi, Splus, sigma, I_lo, I_hi, o, own=0.0, tau_floor=1e-100, chim=None):
+    """Generalised Feautrier solve (both equations of Eq. GFE) on explicit nodes with total
+    opacity chi = chi + chi^+ and, optionally, the odd scattering opacity chim = chi^- along
+    +z: returns (u_o, Lambda_oo, ueff_o, v_o)."""
     z, chi, Splus, sigma = _f64(z), _f64(chi), _f64(Splus), _f64(sigma)
+    cm = None if chim is None else _f64(chim)
     u, lam, ue, v = C.c_double(), C.c_double(), C.c_double(), C.c_double()
-    lib().or_solve_ray_gen(z.shape[0], z, chi, Splus, sigma, I_lo, I_hi, int(o), tau_floor, own,
-                           C.byref(u), C.byref(lam), C.byref(ue), C.byref(v))
+    rc = lib().or_solve_ray_gen(z.shape[0], z, chi, None if cm is None else cm.ctypes.data, Splus, sigma,
+                                I_lo, I_hi, int(o), tau_floor, own, C.byref(u), C.byref(lam), C.byref(ue),
+                                C.byref(v))
+    if rc != 0:
+        raise ValueError("the integrating factor e^M leaves the FP64 range (|M| > 700)")
     return u.value, lam.value, ue.value, v.value
 
 
@@ -255,9 +262,11 @@ class Oracle:
         Ib = np.array([planck(nu, self.t_cmb) for nu in self.line_frequencies()])
         return np.broadcast_to(Ib[None, :, None], (self.P, self.n_lines, self.n_q)).copy()
 
-    def formal_solve_scat(self, pops, chi_sca, Jnu_in, sel=None):
-        """Formal solve with isotropic coherent scattering (chi_sca [P][n_lines], cm^-1)
-        driven by the previous J_nu: returns (J, Jeff, L, Jnu_out [n][n_lines][n_q])."""
+    def formal_solve_scat(self, pops, chi_sca, Jnu_in, sel=None, chi_dip=None):
+        """Formal solve with coherent scattering of opacity chi_sca + chi_dip . n
+        (chi_sca [P][n_lines], chi_dip [P][n_lines][3] or None; cm^-1) driven by the previous
+        weighted mean intensity Jw (J_nu for chi_dip = None): returns (J, Jeff, L,
+        Jw_out [n][n_lines][n_q])."""
         pops = _f64(pops)
         if sel is None:
             n, selp = self.P, None
@@ -266,12 +275,18 @@ class Oracle:
             n, selp = sel_arr.shape[0], sel_arr.ctypes.data
         J, Je, Ls = (np.zeros((n, self.n_lines)) for _ in range(3))
         Jnu = np.zeros((n, self.n_lines, self.n_q))
-        rc = self._L.or_formal_solve_scat(self.c, pops, _f64(chi_sca), _f64(Jnu_in), n, selp, J, Je, Ls, Jnu)
-        if rc != 0:
+        dip = None if chi_dip is None else _f64(chi_dip)
+        rc = self._L.or_formal_solve_scat(self.c, pops, _f64(chi_sca), None if dip is None else dip.ctypes.data,
+                                          _f64(Jnu_in), n, selp, J, Je, Ls, Jnu)
+        if rc == -1:
             raise ValueError("the scattering solve needs an ascending quadrature")
+        if rc == -3:
+            raise ValueError("|chi_dip| exceeds chi_sca: a negative scattering opacity")
+        if rc == -2:
+            raise ValueError("a ray's integrating factor e^M leaves the FP64 range (|M| > 700)")
         return J, Je, Ls, Jnu
 
-    def run_ali_scat(self, chi_sca, pops_init=None, max_iter=50, tol=1e-4):
+    def run_ali_scat(self, chi_sca, pops_init=None, max_iter=50, tol=1e-4, chi_dip=None):
         """ALI with scattering: each iteration one formal solve driven by the previous J_nu
         (starting from scattering_start()), then the statistical equilibrium.  Returns
         (populations, changes, last J_nu)."""
@@ -279,7 +294,7 @@ class Oracle:
         Jnu = self.scattering_start()
         ch = []
         for _ in range(max_iter):
-            J, Je, Ls, Jnu = self.formal_solve_scat(pops, chi_sca, Jnu)
+            J, Je, Ls, Jnu = self.formal_solve_scat(pops, chi_sca, Jnu, chi_dip=chi_dip)
             new, _ = self.stateq(pops, J, Je, Ls)
             ch.append(self.rel_change(pops, new)[0])
             pops = new

@@ -949,45 +949,84 @@ void or_formal_solve_band(const or_ctx *c, const double *pops, int64_t n_sel, co
 /* ------------------------------------------------------------------ scattering */
 
 /*
- * Generalised Feautrier equation on a ray pair (Sec. 3.3, Eq. GFE) with an isotropic
- * scattering opacity (chi^- = 0), so D = d/dtau with dtau = (chi + chi^+) dz, and known
- * (previous-iteration) right-hand sides: Splus = (eta + Psi^+)/(chi + chi^+) and
- * sigma = Psi^-/(chi + chi^+) per node:
- *     u - d^2u/dtau^2 = Splus - d sigma/dtau.
- * The first-order pair of Eq. RTE2 reads du/dtau = -v + sigma, dv/dtau = Splus - u; with
- * the half-node fluxes v_{i+1/2} = -(u_{i+1} - u_i)/dt_{i+1/2} + (sigma_i + sigma_{i+1})/2
- * the interior rows are those of or_solve_ray with
+ * Generalised Feautrier equations on a ray pair (Sec. 3.3, Eq. RTE2 and GFE) with known
+ * (previous-iteration) right-hand sides, per node: the total opacity chi = chi_line + chi^+,
+ * the odd part of the scattering opacity chim = chi^- along +z (NULL: zero), and
+ * Splus = (eta + Psi^+)/(chi + chi^+), sigma = Psi^-/(chi + chi^+).  With dtau = chi dz and
+ * mu = chi^-/chi, the operator of Eq. GFE is D = d/dtau + mu, and the first-order pair of
+ * Eq. RTE2 reads
+ *     D u = sigma - v,    D v = Splus - u.
+ * The integrating factor e^M, M(z) = int_{z_o}^{z} chi^- dz' (trapezoid over the nodes, so
+ * M_o = 0), makes D e^{-M} = e^{-M} d/dtau exactly: u~ = e^M u and v~ = e^M v obey the pair
+ * with mu = 0 and sources e^M Splus, e^M sigma, and the incoming intensities become
+ * e^{M_0} I_lo and e^{M_N-1} I_hi.  At the origin u~ = u and v~ = v.  (|M| <= the optical
+ * depth from o, since |chi^-| <= chi^+; beyond |M| = 700 the factors leave the FP64 range
+ * and the function returns -2.)
+ * The transformed pair is discretised with half-node values: from du/dtau = sigma - v,
+ * v_{i+1/2} = (sigma_i + sigma_{i+1})/2 - (u_{i+1} - u_i)/dt_{i+1/2}, and integrating
+ * dv/dtau = Splus - u over the nodes' cells gives the rows
+ *     -A_i u_{i-1} + (1 + A_i + C_i) u_i - C_i u_{i+1} = R_i,
  *     R_i = Splus_i - (sigma_{i+1} - sigma_{i-1})/(dt_- + dt_+),
- * and the boundary rows (incoming I_lo along +z at node 0, I_hi along -z at node N-1,
- * v_0 = I_lo - u_0, v_{N-1} = u_{N-1} - I_hi, half-cell integration of dv/dtau) take
+ * A_i = 2/(dt_-(dt_- + dt_+)), C_i = 2/(dt_+(dt_- + dt_+)); the boundary rows (incoming
+ * I_lo along +z at node 0, I_hi along -z at node N-1: v_0 = I_lo - u_0, v_{N-1} = u_{N-1} -
+ * I_hi, half-cell integration) have C_0 = A_{N-1} = 2/dt^2 and
  *     R_0 = Splus_0 + (2/dt)(I_lo - (sigma_0 + sigma_1)/2),
  *     R_{N-1} = Splus_{N-1} + (2/dt)(I_hi + (sigma_{N-2} + sigma_{N-1})/2).
- * With sigma = 0 this is exactly the system of or_solve_ray.
- * Solved by the Rybicki-Hummer elimination from both ends toward o (F, z from node 0, G, w
- * from node N-1) and the two-sided combine at o.  Outputs at node o: u_o, Lambda_oo
- * (diagonal of the inverse), ueff_o (the solution with `own` removed from R_o) and the
- * flux-like v_o = (I(+z) - I(-z))/2 at o: the half-node fluxes on both sides, whose
- * differences u_o - u_{o-+1} come from the elimination relations (well conditioned when
- * the optical depth steps are tiny), interpolated linearly in tau to the node
- * (v_o = (dt_+ v_{o-1/2} + dt_- v_{o+1/2})/(dt_- + dt_+)); at an end node the boundary
- * condition gives it, and a single node has v = (I_lo - I_hi)/2.
+ * The second equation of Eq. GFE, (1 - D^2) v = sigma - D Splus, is the same pair with the
+ * roles of Splus and sigma exchanged (half-node u from dv/dtau, cells integrating du/dtau,
+ * u_0 = I_lo - v_0, u_{N-1} = I_hi + v_{N-1}): the same matrix with
+ *     Rv_i = sigma_i - (Splus_{i+1} - Splus_{i-1})/(dt_- + dt_+),
+ *     Rv_0 = sigma_0 + (2/dt)(I_lo - (Splus_0 + Splus_1)/2),
+ *     Rv_{N-1} = sigma_{N-1} + (2/dt)((Splus_{N-2} + Splus_{N-1})/2 - I_hi).
+ * With chim = NULL and sigma = 0 the u rows are exactly those of or_solve_ray.
+ * Both right-hand sides go through one Rybicki-Hummer elimination from both ends toward o
+ * (F, z from node 0, G, w from node N-1) and the two-sided combine at o.  Outputs at node
+ * o: u_o, Lambda_oo (diagonal of the inverse), ueff_o (u with `own` removed from R_o) and
+ * v_o = (I(+z) - I(-z))/2; a single node has u = (I_lo + I_hi)/2, v = (I_lo - I_hi)/2.
  */
-void or_solve_ray_gen(int N, const double *z, const double *chi, const double *Splus,
-                      const double *sigma, double I_lo, double I_hi, int o, double tau_floor,
-                      double own, double *u_o, double *lam_o, double *ueff_o, double *v_o)
+int or_solve_ray_gen(int N, const double *z, const double *chi, const double *chim, const double *Splus,
+                     const double *sigma, double I_lo, double I_hi, int o, double tau_floor, double own,
+                     double *u_o, double *lam_o, double *ueff_o, double *v_o)
 {
     if (N == 1) {
         *u_o = 0.5 * (I_lo + I_hi);
         *lam_o = 0.0;
         *ueff_o = *u_o;
         *v_o = 0.5 * (I_lo - I_hi);
-        return;
+        return 0;
     }
+    double *E = malloc(sizeof(double) * N), *Sp = malloc(sizeof(double) * N), *sg = malloc(sizeof(double) * N);
+    /* integrating factor e^M, M_o = 0 */
+    double M = 0.0;
+    int bad = 0;
+    E[o] = 1.0;
+    for (int i = o + 1; i < N; ++i) {
+        if (chim) M += 0.5 * (chim[i - 1] + chim[i]) * (z[i] - z[i - 1]);
+        if (fabs(M) > 700.0) bad = 1;
+        E[i] = exp(M);
+    }
+    M = 0.0;
+    for (int i = o - 1; i >= 0; --i) {
+        if (chim) M -= 0.5 * (chim[i] + chim[i + 1]) * (z[i + 1] - z[i]);
+        if (fabs(M) > 700.0) bad = 1;
+        E[i] = exp(M);
+    }
+    if (bad) {
+        free(E); free(Sp); free(sg);
+        return -2;
+    }
+    for (int i = 0; i < N; ++i) {
+        Sp[i] = E[i] * Splus[i];
+        sg[i] = E[i] * sigma[i];
+    }
+    I_lo *= E[0];
+    I_hi *= E[N - 1];
+
     double *dt = malloc(sizeof(double) * N);
     double *Ac = calloc(N, sizeof(double)), *Cc = calloc(N, sizeof(double));
-    double *Hc = malloc(sizeof(double) * N), *R = malloc(sizeof(double) * N);
-    double *F = malloc(sizeof(double) * N), *zz = malloc(sizeof(double) * N);
-    double *G = malloc(sizeof(double) * N), *ww = malloc(sizeof(double) * N);
+    double *Hc = malloc(sizeof(double) * N), *R = malloc(sizeof(double) * N), *Rv = malloc(sizeof(double) * N);
+    double *F = malloc(sizeof(double) * N), *zz = malloc(sizeof(double) * N), *zv = malloc(sizeof(double) * N);
+    double *G = malloc(sizeof(double) * N), *ww = malloc(sizeof(double) * N), *wv = malloc(sizeof(double) * N);
     for (int i = 0; i + 1 < N; ++i) {
         double d = 0.5 * (chi[i] + chi[i + 1]) * (z[i + 1] - z[i]);
         dt[i] = d > tau_floor ? d : tau_floor;
@@ -995,55 +1034,52 @@ void or_solve_ray_gen(int N, const double *z, const double *chi, const double *S
     for (int i = 0; i < N; ++i) Hc[i] = 1.0;
     Cc[0] = 2.0 / (dt[0] * dt[0]);
     Hc[0] = 1.0 + 2.0 / dt[0];
-    R[0] = Splus[0] + 2.0 / dt[0] * (I_lo - 0.5 * (sigma[0] + sigma[1]));
+    R[0] = Sp[0] + 2.0 / dt[0] * (I_lo - 0.5 * (sg[0] + sg[1]));
+    Rv[0] = sg[0] + 2.0 / dt[0] * (I_lo - 0.5 * (Sp[0] + Sp[1]));
     for (int i = 1; i < N - 1; ++i) {
         Ac[i] = 2.0 / (dt[i - 1] * (dt[i - 1] + dt[i]));
         Cc[i] = 2.0 / (dt[i] * (dt[i - 1] + dt[i]));
-        R[i] = Splus[i] - (sigma[i + 1] - sigma[i - 1]) / (dt[i - 1] + dt[i]);
+        R[i] = Sp[i] - (sg[i + 1] - sg[i - 1]) / (dt[i - 1] + dt[i]);
+        Rv[i] = sg[i] - (Sp[i + 1] - Sp[i - 1]) / (dt[i - 1] + dt[i]);
     }
     Ac[N - 1] = 2.0 / (dt[N - 2] * dt[N - 2]);
     Hc[N - 1] = 1.0 + 2.0 / dt[N - 2];
-    R[N - 1] = Splus[N - 1] + 2.0 / dt[N - 2] * (I_hi + 0.5 * (sigma[N - 2] + sigma[N - 1]));
+    R[N - 1] = Sp[N - 1] + 2.0 / dt[N - 2] * (I_hi + 0.5 * (sg[N - 2] + sg[N - 1]));
+    Rv[N - 1] = sg[N - 1] + 2.0 / dt[N - 2] * (0.5 * (Sp[N - 2] + Sp[N - 1]) - I_hi);
 
-    /* Rybicki-Hummer elimination from both ends toward o: u_{i-1} = zz_{i-1} + u_i/(1 + F_{i-1})
-     * below o and u_{i+1} = ww_{i+1} + u_i/(1 + G_{i+1}) above it */
+    /* Rybicki-Hummer elimination from both ends toward o: x_{i-1} = zz_{i-1} + x_i/(1 + F_{i-1})
+     * below o and x_{i+1} = ww_{i+1} + x_i/(1 + G_{i+1}) above it (zz, ww for u; zv, wv for v) */
     for (int i = 0; i < o; ++i) {
         double q = i > 0 ? Ac[i] * F[i - 1] / (1.0 + F[i - 1]) : 0.0;
         F[i] = (Hc[i] + q) / Cc[i];
         zz[i] = (R[i] + (i > 0 ? Ac[i] * zz[i - 1] : 0.0)) / (Cc[i] * (1.0 + F[i]));
+        zv[i] = (Rv[i] + (i > 0 ? Ac[i] * zv[i - 1] : 0.0)) / (Cc[i] * (1.0 + F[i]));
     }
     for (int i = N - 1; i > o; --i) {
         double q = i < N - 1 ? Cc[i] * G[i + 1] / (1.0 + G[i + 1]) : 0.0;
         G[i] = (Hc[i] + q) / Ac[i];
         ww[i] = (R[i] + (i < N - 1 ? Cc[i] * ww[i + 1] : 0.0)) / (Ac[i] * (1.0 + G[i]));
+        wv[i] = (Rv[i] + (i < N - 1 ? Cc[i] * wv[i + 1] : 0.0)) / (Ac[i] * (1.0 + G[i]));
     }
-    double den = Hc[o], num = R[o];
+    double den = Hc[o], num = R[o], numv = Rv[o];
     if (o > 0) {
         den += Ac[o] * F[o - 1] / (1.0 + F[o - 1]);
         num += Ac[o] * zz[o - 1];
+        numv += Ac[o] * zv[o - 1];
     }
     if (o < N - 1) {
         den += Cc[o] * G[o + 1] / (1.0 + G[o + 1]);
         num += Cc[o] * ww[o + 1];
+        numv += Cc[o] * wv[o + 1];
     }
-    double u = num / den;
-    *u_o = u;
+    *u_o = num / den;
     *lam_o = 1.0 / den;
     *ueff_o = (num - own) / den;
-    if (o == 0) {
-        *v_o = I_lo - u;
-    } else if (o == N - 1) {
-        *v_o = u - I_hi;
-    } else {
-        double dm = dt[o - 1], dp = dt[o];
-        /* (u_o - u_{o-1})/dt_- and (u_o - u_{o+1})/dt_+ from the elimination relations */
-        double pb = (u * F[o - 1] / (1.0 + F[o - 1]) - zz[o - 1]) / dm;
-        double pf = (u * G[o + 1] / (1.0 + G[o + 1]) - ww[o + 1]) / dp;
-        double vm = -pb + 0.5 * (sigma[o - 1] + sigma[o]);
-        double vp = pf + 0.5 * (sigma[o] + sigma[o + 1]);
-        *v_o = (dp * vm + dm * vp) / (dm + dp);
-    }
-    free(dt); free(Ac); free(Cc); free(Hc); free(R); free(F); free(zz); free(G); free(ww);
+    *v_o = numv / den;
+    free(E); free(Sp); free(sg);
+    free(dt); free(Ac); free(Cc); free(Hc); free(R); free(Rv); free(F); free(zz); free(zv);
+    free(G); free(ww); free(wv);
+    return 0;
 }
 
 /* J_nu of point q, line l at offset x (in q's line widths, q's frame): linear in x
@@ -1061,35 +1097,51 @@ static double jnu_at(const or_ctx *c, const double *Jnu, int64_t q, int l, doubl
 }
 
 /*
- * Formal solve with scattering (Sec. 2.1 Eq. RTE, 3.3, 3.4).  The scattering opacity
- * chi_sca [P][n_lines] (cm^-1) is isotropic and grey over each line's frequencies, and
- * scatters coherently and isotropically in the comoving frame of each point, so a photon
- * at offset y (widths, the scatterer's frame) is re-emitted with chi_sca J_nu(y), J_nu the
- * scatterer's mean intensity there, taken from the previous iteration (Jnu_in
- * [P][n_lines][n_q], at the quadrature offsets, interpolated by jnu_at).  The pair at
- * lane offset x joins I(n, x) and I(-n, -x); at a node whose offset is y = a x - b the two
- * directions see chi_sca J(y) and chi_sca J(-y), so
- *     Psi^+ = chi_sca (J(y) + J(-y))/2,   Psi^- = chi_sca (J(y) - J(-y))/2,
- * and with chi_tot = chi_line + chi_sca:  Splus = (chi_line S + Psi^+)/chi_tot,
+ * Formal solve with scattering (Sec. 2.1 Eq. RTE, 3.3, 3.4).  The scattering opacity of
+ * direction n is chi_sca + chi_dip . n (cm^-1; chi_sca [P][n_lines], chi_dip
+ * [P][n_lines][3] or NULL for zero, |chi_dip| <= chi_sca so that it is nowhere negative),
+ * grey over each line's frequencies, so chi^+ = chi_sca and chi^- = chi_dip . n.  The
+ * scattering is coherent in the comoving frame of the scatterer, with the redistribution
+ * Phi(n, n') = chi_s(n) chi_s(n') / (4 pi chi_sca) (chi_s(n) the opacity of direction n):
+ * the radiation removed from every direction is re-emitted in all (energy is conserved,
+ * int Phi dOmega = chi_s(n')), and I = B solves every direction in thermal equilibrium
+ * (int Phi dOmega' = chi_s(n)).  At offset y (widths, the scatterer's frame) the
+ * emissivity into n is then chi_s(n) Jw(y), Jw = (1/4pi) int w(n') I(n', y) dOmega' with
+ * w(n) = chi_s(n)/chi_sca = 1 + (chi_dip . n)/chi_sca (w = 1 where chi_sca = 0; Jw is the
+ * mean intensity J_nu when chi_dip = 0).  Jw comes from the previous iteration (Jnu_in
+ * [P][n_lines][n_q], at the quadrature offsets, interpolated by jnu_at).  The pair at lane
+ * offset x joins I(n, x) and I(-n, -x); at a node whose offset is y = a x - b, with
+ * chi^- = chi_dip . n there, the two directions receive (chi_sca + chi^-) Jw(y) and
+ * (chi_sca - chi^-) Jw(-y), and Psi^+-, the half sum and half difference of these, give
+ * with chi_tot = chi_line + chi_sca:  Splus = (chi_line S + Psi^+)/chi_tot,
  * sigma = Psi^-/chi_tot (both 0 where chi_tot = 0).  Velocity sub-steps interpolate
- * chi_sca and the J_nu of the segment's end cells linearly in t, at the sub-step's own
- * offset.  Per selected point and line:
+ * chi_sca, chi_dip . n and the Jw of the segment's end cells linearly in t, at the
+ * sub-step's own offset.  Per selected point and line:
  *   J     (2/N_rays) sum_pairs sum_n w_n u_o,
  *   L     (2/N_rays) sum sum w_n Lambda_oo chi_line,o/chi_tot,o     (Eq. ALO),
  *   Jeff  (2/N_rays) sum sum w_n (u_o - Lambda_oo (chi_line,o/chi_tot,o) S_o),
  *         with the share chi_line,o/chi_tot,o taken as 1 where chi_tot,o = 0,
- *   Jnu_out[n] = (1/N_rays) sum over pairs of I(n, x_n) + I(-n, x_n), with
- *         I(n, x) = u(x) + v(x) and I(-n, x) = u(-x) - v(-x) (the mirrored offset).
- * The quadrature must be ascending (and, as always, symmetric); returns -1 otherwise.
+ *   Jnu_out[n] = (1/N_rays) sum over pairs of w_o(n) I(n, x_n) + w_o(-n) I(-n, x_n), with
+ *         I(n, x) = u(x) + v(x) and I(-n, x) = u(-x) - v(-x) (the mirrored offset), u and v
+ *         from the two equations of Eq. GFE (or_solve_ray_gen).
+ * Returns -1 unless the quadrature is ascending (and, as always, symmetric), -3 if some
+ * |chi_dip| exceeds chi_sca (by more than 1e-12 relative), -2 if a ray leaves the range
+ * of or_solve_ray_gen's integrating factor.
  */
-int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_sca,
+int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_sca, const double *chi_dip,
                          const double *Jnu_in, int64_t n_sel, const int64_t *sel, double *J,
                          double *Jeff, double *L, double *Jnu_out)
 {
     int nl = c->n_lines, nq = c->nq;
     for (int n = 0; n + 1 < nq; ++n)
         if (!(c->qx[n] < c->qx[n + 1])) return -1;
+    if (chi_dip)
+        for (int64_t i = 0; i < c->P * nl; ++i) {
+            const double *d = chi_dip + 3 * i;
+            if (!(sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= chi_sca[i] * (1.0 + 1e-12))) return -3;
+        }
     double norm = 2.0 / (double)c->n_rays;
+    int status = 0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < n_sel; ++s) {
         int64_t O = sel ? sel[s] : s;
@@ -1105,9 +1157,25 @@ int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_
             double *kap = malloc(sizeof(double) * N * nl), *S = malloc(sizeof(double) * N * nl);
             pair_nodes_src(c, pops, O, p, N, z, a, b, kap, S, clo, chh, th, &io);
             double *ct = malloc(sizeof(double) * N), *Sp = malloc(sizeof(double) * N);
-            double *sg = malloc(sizeof(double) * N);
+            double *sg = malloc(sizeof(double) * N), *cm = malloc(sizeof(double) * N);
+            const double *nr = c->dir + 3 * c->pair_r[p];   /* +z of the pair's nodes */
             for (int l = 0; l < nl; ++l) {
                 double Ib = or_planck(c->nu[l], c->t_cmb);
+                /* chi^- along +z at every node, and the weights of the two directions at O */
+                double wp = 1.0, wm = 1.0;
+                for (int i = 0; i < N; ++i) {
+                    double t = th[i], mlo = 0.0, mhi = 0.0;
+                    if (chi_dip) {
+                        const double *dl = chi_dip + 3 * (clo[i] * nl + l), *dh = chi_dip + 3 * (chh[i] * nl + l);
+                        mlo = dl[0] * nr[0] + dl[1] * nr[1] + dl[2] * nr[2];
+                        mhi = dh[0] * nr[0] + dh[1] * nr[1] + dh[2] * nr[2];
+                    }
+                    cm[i] = (1.0 - t) * mlo + t * mhi;
+                }
+                if (chi_sca[O * nl + l] > 0.0) {
+                    wp = 1.0 + cm[io] / chi_sca[O * nl + l];
+                    wm = 1.0 - cm[io] / chi_sca[O * nl + l];
+                }
                 for (int n = 0; n < nq; ++n) {
                     double clO = 0.0, ctO = 0.0;
                     for (int i = 0; i < N; ++i) {
@@ -1117,10 +1185,12 @@ int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_
                         double cs = (1.0 - t) * chi_sca[clo[i] * nl + l] + t * chi_sca[chh[i] * nl + l];
                         double jp = (1.0 - t) * jnu_at(c, Jnu_in, clo[i], l, y) + t * jnu_at(c, Jnu_in, chh[i], l, y);
                         double jm = (1.0 - t) * jnu_at(c, Jnu_in, clo[i], l, -y) + t * jnu_at(c, Jnu_in, chh[i], l, -y);
+                        /* emissivities into +z (offset y) and -z (offset -y) */
+                        double psi_p = (cs + cm[i]) * jp, psi_m = (cs - cm[i]) * jm;
                         double tot = cl + cs;
                         ct[i] = tot;
-                        Sp[i] = tot > 0.0 ? (cl * S[i * nl + l] + cs * 0.5 * (jp + jm)) / tot : 0.0;
-                        sg[i] = tot > 0.0 ? cs * 0.5 * (jp - jm) / tot : 0.0;
+                        Sp[i] = tot > 0.0 ? (cl * S[i * nl + l] + 0.5 * (psi_p + psi_m)) / tot : 0.0;
+                        sg[i] = tot > 0.0 ? 0.5 * (psi_p - psi_m) / tot : 0.0;
                         if (i == io) {
                             clO = cl;
                             ctO = tot;
@@ -1131,17 +1201,21 @@ int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_
                     double share = ctO > 0.0 ? clO / ctO : 1.0;
                     double own = share * S[io * nl + l];
                     double u, lam, ue, v;
-                    or_solve_ray_gen(N, z, ct, Sp, sg, Ib, Ib, io, c->tau_floor, own, &u, &lam, &ue, &v);
+                    if (or_solve_ray_gen(N, z, ct, chi_dip ? cm : NULL, Sp, sg, Ib, Ib, io, c->tau_floor, own, &u,
+                                         &lam, &ue, &v) != 0) {
+#pragma omp atomic write
+                        status = -2;
+                    }
                     double w = c->qw[n];
                     Js[l] += w * u;
                     Ls[l] += w * lam * share;
                     Es[l] += w * ue;
-                    Jp[(size_t)l * nq + n] += u + v;
-                    Jm[(size_t)l * nq + n] += u - v;
+                    Jp[(size_t)l * nq + n] += wp * (u + v);
+                    Jm[(size_t)l * nq + n] += wm * (u - v);
                 }
             }
             free(z); free(a); free(b); free(th); free(clo); free(chh); free(kap); free(S);
-            free(ct); free(Sp); free(sg);
+            free(ct); free(Sp); free(sg); free(cm);
         }
         for (int l = 0; l < nl; ++l) {
             J[s * nl + l] = norm * Js[l];
@@ -1153,7 +1227,7 @@ int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_
         }
         free(Js); free(Ls); free(Es); free(Jp); free(Jm);
     }
-    return 0;
+    return status;
 }
 
 /* Threads of the OpenMP loops over origin points (timing runs). */

@@ -40,10 +40,10 @@ int64_t or_walk_all(const or_ctx *c, int64_t *off, int32_t *cells);
 void or_features(const or_ctx *c, double *F);
 void or_formal_solve_band(const or_ctx *c, const double *pops, int64_t n_sel, const int64_t *sel,
                           double *J, double *Jeff, double *L, double *Jb, double *Ld, double *Ln);
-void or_solve_ray_gen(int N, const double *z, const double *chi, const double *Splus,
-                      const double *sigma, double I_lo, double I_hi, int o, double tau_floor,
-                      double own, double *u_o, double *lam_o, double *ueff_o, double *v_o);
-int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_sca,
+int or_solve_ray_gen(int N, const double *z, const double *chi, const double *chim, const double *Splus,
+                     const double *sigma, double I_lo, double I_hi, int o, double tau_floor,
+                     double own, double *u_o, double *lam_o, double *ueff_o, double *v_o);
+int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_sca, const double *chi_dip,
                          const double *Jnu_in, int64_t n_sel, const int64_t *sel, double *J,
                          double *Jeff, double *L, double *Jnu_out);
 void or_set_threads(int n);

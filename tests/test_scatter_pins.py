@@ -125,11 +125,14 @@ def test_generalised_solve_brute_force(oracle_lib, seed):
     assert errs[-1] < 1e-4
 
 
-def _moving_chain_exact(o, mdl, pops, chi_sca, Jnu, O, xq, steps=60):
+def _moving_chain_exact(o, mdl, pops, chi_sca, Jnu, O, xq, steps=60, chim_x=None):
     """J_nu(x) at chain point O by integrating dI/ds = chi_tot (S_dir - I) along +x and
     along -x, with every profile-free quantity linear between the chain nodes (what the
     velocity sub-steps discretise): Doppler coefficients a, b, line kappa and S, chi_sca,
-    and the nodes' J_nu evaluated at the local offset."""
+    and the nodes' J_nu evaluated at the local offset.  With chim_x (the odd scattering
+    opacity along +x per point) each direction s = +-1 has scattering opacity
+    chi_sca + s chim_x and emissivity (chi_sca + s chim_x) Jw, and the result is O's
+    weighted field ((1 + e) I(+x) + (1 - e) I(-x))/2, e = chim_x/chi_sca at O."""
     sp = o.species
     nu = o.line_frequencies()[0]
     Bul = sp.line_A[0] * CL ** 2 / (2 * H * nu ** 3)
@@ -154,6 +157,8 @@ def _moving_chain_exact(o, mdl, pops, chi_sca, Jnu, O, xq, steps=60):
         y = aa * qx - sign * bb
         cl = (kap[k] + t * (kap[k + 1] - kap[k])) * np.exp(-y * y)
         cs = chi_sca[k, 0] + t * (chi_sca[k + 1, 0] - chi_sca[k, 0])
+        if chim_x is not None:
+            cs = cs + sign * (chim_x[k] + t * (chim_x[k + 1] - chim_x[k]))
         jj = (1 - t) * jnode(k, y) + t * jnode(k + 1, y)
         Sl = S[k] + t * (S[k + 1] - S[k])
         tot = cl + cs
@@ -177,7 +182,8 @@ def _moving_chain_exact(o, mdl, pops, chi_sca, Jnu, O, xq, steps=60):
 
     Ip = integrate(x[0], x[O], +1.0)
     Im = integrate(x[-1], x[O], -1.0)
-    return 0.5 * (Ip + Im)
+    e = 0.0 if chim_x is None else chim_x[O] / chi_sca[O, 0]
+    return 0.5 * ((1 + e) * Ip + (1 - e) * Im)
 
 
 def test_scattering_in_a_moving_medium_brute_force(oracle_lib):
