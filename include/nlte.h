@@ -321,20 +321,38 @@ nlte_status nlte_stateq_band(nlte_ctx *ctx, const double *pops_old, const double
 
 /*
  * Scattering (Sec. 2.1 Eq. RTE; Sec. 3.3 Eq. RTE2, GFE).  chi_sca [P][n_lines] (cm^-1, >= 0,
- * host, copied) is an isotropic scattering opacity, grey over each line's frequencies,
- * that scatters coherently and isotropically in the comoving frame of each point.  The
- * formal solve then solves the u-equation of the generalised Feautrier form with
- * chi^+ = chi_sca, chi^- = 0 and the Psi^+- terms of the mean intensity J_nu of the
- * previous iteration (the paper's iterative treatment of the coupling), and returns the
- * new J_nu [P][n_lines][n_q] (at the quadrature offsets, in each point's frame and line
- * widths) from u and the flux-like v at the origin.  L* and Jeff take the line's share
- * chi_line/(chi_line + chi_sca) of the origin's source (Eq. ALO).  With scattering set,
- * nlte_run_ali uses this solve (FP64 whatever the precision setting, not graph-captured),
- * starting from J_nu = the boundary intensity of each line.  Needs an ascending
- * quadrature (E_INVALID_ARG otherwise); does not combine with alo_band.  NULL clears it;
- * nlte_set_species and nlte_set_models clear it too.
+ * host, copied) is the scattering opacity, grey over each line's frequencies, isotropic
+ * unless nlte_set_scattering_dipole adds an odd part.  Scattering is coherent in the
+ * comoving frame of each point.  The formal solve then solves both equations of the
+ * generalised Feautrier form (u and the flux-like v) with chi^+ = chi_sca and the Psi^+-
+ * terms of the previous iteration's field (the paper's iterative treatment of the
+ * coupling), and returns the new field [P][n_lines][n_q] (at the quadrature offsets, in
+ * each point's frame and line widths) from u and v at the origin: the mean intensity
+ * J_nu, or with a dipole the weighted mean Jw described there.  L* and Jeff take the
+ * line's share chi_line/(chi_line + chi_sca) of the origin's source (Eq. ALO).  With
+ * scattering set, nlte_run_ali uses this solve (FP64 whatever the precision setting, not
+ * graph-captured), starting from the boundary intensity of each line.  Needs an ascending
+ * quadrature (E_INVALID_ARG otherwise); does not combine with alo_band.  NULL clears it
+ * (and the dipole); nlte_set_species and nlte_set_models clear both, and every call clears
+ * the dipole.
  */
 nlte_status nlte_set_scattering(nlte_ctx *ctx, const double *chi_sca);
+
+/*
+ * Direction-dependent scattering opacity (Sec. 2.1, 3.3: chi^- != 0): chi_dip
+ * [P][n_lines][3] (cm^-1, host, copied) makes the opacity of direction n
+ * chi_sca + chi_dip . n, so chi^+ = chi_sca and chi^- = chi_dip . n along each ray pair.
+ * |chi_dip| <= chi_sca (1 + 1e-12) at every point and line (E_INVALID_ARG otherwise: a
+ * negative opacity).  The scattered radiation is redistributed reciprocally,
+ * Phi(n, n') = chi_s(n) chi_s(n') / (4 pi chi_sca): energy is conserved and I = B solves
+ * every direction in thermal equilibrium.  The emissivity into n is then chi_s(n) Jw, with
+ * Jw = (1/4pi) int (chi_s(n')/chi_sca) I(n') dOmega' the weighted mean intensity that the
+ * scattering field holds (J_nu without a dipole).  chi^- enters the ray-pair solve through
+ * the integrating factor e^{int chi^- ds}; an odd part that changes a ray's e-folding by
+ * more than 700 within one sub-step is clamped there.  NULL removes the odd part.
+ * E_STATE unless nlte_set_scattering set opacities.
+ */
+nlte_status nlte_set_scattering_dipole(nlte_ctx *ctx, const double *chi_dip);
 
 /* One formal solve with scattering driven by jnu_in (host arrays, [P][n_lines][n_q]):
  * J, Jeff, Lstar [P][n_lines] and jnu_out. */
@@ -345,7 +363,8 @@ nlte_status nlte_formal_solve_scat(nlte_ctx *ctx, const double *pops, const doub
 nlte_status nlte_formal_solve_scat_dev(nlte_ctx *ctx, const double *d_pops, const double *d_jnu_in,
                                        double *d_J, double *d_Jeff, double *d_Lstar,
                                        double *d_jnu_out, void *stream);
-/* J_nu [P][n_lines][n_q] after the last formal solve of the last nlte_run_ali with
+/* The scattering field (J_nu, or Jw with a dipole) [P][n_lines][n_q] after the last
+ * formal solve of the last nlte_run_ali with
  * scattering (host copy); E_STATE if there is none.  nlte_formal_solve_scat (host) works
  * in the same buffers: read the field before calling it. */
 nlte_status nlte_scattering_field(nlte_ctx *ctx, double *jnu);

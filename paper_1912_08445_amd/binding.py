@@ -32,7 +32,7 @@ EXPORTS = (
     "nlte_set_models", "nlte_set_rays", "nlte_set_quadrature", "nlte_set_params", "nlte_trace",
     "nlte_get_ray", "nlte_get_order", "nlte_get_point_cost", "nlte_trace_stats", "nlte_get_line_width_speed", "nlte_lte", "nlte_lte_dev",
     "nlte_formal_solve", "nlte_formal_solve_dev", "nlte_formal_solve_noalloc_dev", "nlte_stateq", "nlte_stateq_dev",
-    "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_rays_healpix", "nlte_get_rays", "nlte_set_scattering", "nlte_formal_solve_scat",
+    "nlte_formal_solve_band", "nlte_stateq_band", "nlte_set_rays_healpix", "nlte_get_rays", "nlte_set_scattering", "nlte_set_scattering_dipole", "nlte_formal_solve_scat",
     "nlte_formal_solve_scat_dev", "nlte_scattering_field",
     "nlte_run_ali", "nlte_run_ali_dev", "nlte_get_model_status", "nlte_autotune", "nlte_get_launch",
     "nlte_kernel_stats", "nlte_reset_kernel_stats", "nlte_executed_steps",
@@ -118,6 +118,7 @@ def load():
     L.nlte_formal_solve_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.nlte_stateq_band.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.nlte_set_scattering.argtypes = [vp, vp]
+    L.nlte_set_scattering_dipole.argtypes = [vp, vp]
     L.nlte_set_rays_healpix.argtypes = [vp, C.c_int]
     L.nlte_get_rays.argtypes = [vp, C.POINTER(C.c_int), vp]
     L.nlte_formal_solve_scat.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -369,6 +370,15 @@ class Solver:
             return
         self._scat = _c(chi_sca, np.float64)
         self._chk(self.L.nlte_set_scattering(self.h, _p(self._scat)))
+
+    def set_scattering_dipole(self, chi_dip=None):
+        """Odd part of the scattering opacity [P][n_lines][3] (cm^-1): the opacity of
+        direction n is chi_sca + chi_dip . n; None removes it."""
+        if chi_dip is None:
+            self._chk(self.L.nlte_set_scattering_dipole(self.h, None))
+            return
+        d = _c(chi_dip, np.float64)
+        self._chk(self.L.nlte_set_scattering_dipole(self.h, _p(d)))
 
     def formal_solve_scat(self, pops, jnu_in):
         """(J, Jeff, L*, J_nu out) of one formal solve with scattering."""

@@ -765,6 +765,7 @@ nlte_status formal_solve_scat_impl(nlte_ctx *c, const double *d_pops, const doub
     a.qw = c->d_qw;
     a.ibdy = c->d_ibdy;
     a.chi_sca = c->d_chi_sca;
+    a.chi_dip = c->dip_on ? c->d_chi_dip : nullptr;
     a.Jin = d_jin;
     a.Jout = d_jout;
     a.J = d_J;
@@ -921,6 +922,7 @@ void nlte_destroy(nlte_ctx *c)
     dfree(c->d_morton);
     dfree(c->d_vch);
     dfree(c->d_chi_sca);
+    dfree(c->d_chi_dip);
     dfree(c->d_jnu[0]);
     dfree(c->d_jnu[1]);
     dfree(c->d_first);
@@ -1070,6 +1072,7 @@ nlte_status nlte_set_species(nlte_ctx *c, int n_lev, const double *E, const doub
     drop_graphs(c);
     c->have_species = true;
     c->scat_on = false;     // scattering opacities are per line
+    c->dip_on = false;
     c->jnu_last = -1;
     // line widths and work buffers depend on the species: the model must be set again
     c->have_model = false;
@@ -1160,6 +1163,7 @@ nlte_status nlte_set_models(nlte_ctx *c, int n_models, const int64_t *offsets, c
     c->have_model = true;
     c->traced = false;
     c->scat_on = false;     // scattering opacities belong to the previous points
+    c->dip_on = false;
     c->jnu_last = -1;
     drop_graphs(c);
     // point -> model map and per-model convergence state
@@ -2222,6 +2226,7 @@ nlte_status nlte_set_scattering(nlte_ctx *c, const double *chi_sca)
     if (!c->have_model) return fail(c, NLTE_E_STATE, "nlte_set_models has not been called");
     (void)hipSetDevice(c->device);
     c->jnu_last = -1;
+    c->dip_on = false;   // the odd part is bounded by the opacities it was set with
     if (!chi_sca) {
         c->scat_on = false;
         return NLTE_OK;
@@ -2234,6 +2239,34 @@ nlte_status nlte_set_scattering(nlte_ctx *c, const double *chi_sca)
     if ((st = dalloc(c, &c->d_chi_sca, (size_t)n))) return st;
     HIPCHK(c, hipMemcpy(c->d_chi_sca, chi_sca, sizeof(double) * n, hipMemcpyHostToDevice));
     c->scat_on = true;
+    return NLTE_OK;
+}
+
+nlte_status nlte_set_scattering_dipole(nlte_ctx *c, const double *chi_dip)
+{
+    if (!c) return NLTE_E_INVALID_ARG;
+    if (!c->scat_on) return fail(c, NLTE_E_STATE, "nlte_set_scattering has not been called");
+    (void)hipSetDevice(c->device);
+    c->jnu_last = -1;
+    if (!chi_dip) {
+        c->dip_on = false;
+        return NLTE_OK;
+    }
+    const int64_t n = c->P * c->n_lines;
+    std::vector<double> cs(n);
+    HIPCHK(c, hipMemcpy(cs.data(), c->d_chi_sca, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) {
+        const double *d = chi_dip + 3 * i;
+        if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
+            return fail(c, NLTE_E_INVALID_ARG, "dipole scattering opacities must be finite");
+        if (!(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) <= cs[i] * (1.0 + 1e-12)))
+            return fail(c, NLTE_E_INVALID_ARG,
+                        "|chi_dip| exceeds chi_sca: the scattering opacity would be negative in some direction");
+    }
+    nlte_status st;
+    if ((st = dalloc(c, &c->d_chi_dip, (size_t)(3 * n)))) return st;
+    HIPCHK(c, hipMemcpy(c->d_chi_dip, chi_dip, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    c->dip_on = true;
     return NLTE_OK;
 }
 

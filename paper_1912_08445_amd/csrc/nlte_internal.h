@@ -128,8 +128,9 @@ struct ScatArgs {
     const int32_t *pair_r, *anti;
     const double *qx, *qw;   // [n_q], ascending and symmetric
     const double *ibdy;      // [n_lines]
-    const double *chi_sca;   // [P][n_lines] scattering opacity [cm^-1]
-    const double *Jin;       // [P][n_lines][n_q] previous J_nu
+    const double *chi_sca;   // [P][n_lines] scattering opacity chi^+ [cm^-1]
+    const double *chi_dip;   // [P][n_lines][3] its odd part (chi^- = chi_dip . n), or null
+    const double *Jin;       // [P][n_lines][n_q] previous weighted mean intensity Jw
     double *Jout;            // [P][n_lines][n_q]
     double *J, *Jeff, *L;    // [P][n_lines]
     double f_sub, norm, inv_rays;
@@ -308,7 +309,9 @@ struct nlte_ctx {
 
     // scattering: opacity and the ALI's J_nu in two buffers (last one written: jnu_last)
     double *d_chi_sca = nullptr;         // [P][n_lines]
+    double *d_chi_dip = nullptr;         // [P][n_lines][3]
     bool scat_on = false;
+    bool dip_on = false;
     double *d_jnu[2] = {nullptr, nullptr};  // [P][n_lines][n_q] each
     int64_t jnu_elems = 0;
     int jnu_last = -1;

@@ -1,16 +1,25 @@
-// Formal solve with scattering: the u-equation of the generalised Feautrier form
-// (Sec. 3.3, Eq. GFE) for an isotropic scattering opacity chi_s (chi^- = 0), grey over a
-// line's frequencies, scattering coherently and isotropically in each point's comoving
-// frame, with the right-hand sides from the previous iteration's mean intensity J_nu
-// (Sec. 3.3: the Psi terms are evaluated with the previous solution).
+// Formal solve with scattering: both equations of the generalised Feautrier form
+// (Sec. 3.3, Eq. GFE) for a scattering opacity chi_s(n) = chi_s + chi_dip . n, grey over
+// a line's frequencies (chi^+ = chi_s, chi^- = chi_dip . n), scattering coherently in
+// each point's comoving frame with the reciprocal redistribution
+// chi_s(n) chi_s(n')/(4 pi chi_s), so that the emissivity into n is chi_s(n) Jw with Jw
+// the mean intensity weighted by w(n') = chi_s(n')/chi_s, and with the right-hand sides
+// from the previous iteration's Jw (Sec. 3.3: the Psi terms are evaluated with the
+// previous solution).  Jw is J_nu when chi_dip = 0.
 //
-// At a node whose comoving offset is y (line widths of that node) the photon of the
-// sweep's own direction sees chi_s J(y) and the one of the opposite direction chi_s J(-y),
-// so with chi_t = chi_line + chi_s
-//   S+ = (chi_line S + chi_s (J(y) + J(-y))/2) / chi_t,
-//   sigma~ = chi_s (J(-y) - J(y))/2 / chi_t   (Psi^-/chi_t along the sweep direction),
-// and the interior rows of the second-order system gain -d sigma/dtau as the central
-// difference over the two neighbours; the boundary rows gain the half-node value of sigma.
+// At a node the photon of the sweep's own direction has comoving offset -y (y = a x - b
+// for the lane's x), the opposite one +y; with chi^- along the sweep direction cm,
+// chi_t = chi_line + chi_s, r = chi_s/chi_t and rm = cm/chi_t:
+//   S+ = S + r (Jbar - S) + rm dJ,   sigma~ = r dJ + rm Jbar   (Psi^-/chi_t, sweep direction),
+// Jbar = (Jw(-y) + Jw(y))/2, dJ = (Jw(-y) - Jw(y))/2.  The interior rows of the u-equation
+// gain -d sigma/dtau as the central difference over the two neighbours, those of the
+// v-equation -d S+/dtau; the boundary rows the half-node values.  Both equations share the
+// matrix, so one elimination carries two particular solutions (y for u, yv for v).
+// chi^- enters through the integrating factor e^M, M = int chi^- ds along the sweep: the
+// transformed pair has chi^- = 0 and sources e^M S+, e^M sigma; the elimination keeps its
+// particular solutions and held sources in the frame of the current node (M = 0 there), so
+// each step multiplies them by e^{-dM} of its sub-interval (trapezoid of chi^-), and at the
+// origin the frames of both halves coincide.
 // J(y) is linear in y between the quadrature offsets (constant beyond them; the offset is
 // located once for both end cells of a sub-step segment, by its arithmetic position on an
 // evenly spaced quadrature, where -y mirrors +y, and by bisection otherwise); velocity
@@ -20,16 +29,16 @@
 // One workgroup per point and line (two lines, in lanes 0-31 and 32-63, when n_q <= 32),
 // one lane per frequency (n_q <= 256 lanes).  Each lane
 // eliminates both halves of every ray pair from the far ends toward the origin in the
-// division-free scaled state of the line formal solve (n, d, y~ with node coefficients
+// division-free scaled state of the line formal solve (n, d, y~, yv~ with node coefficients
 // chi dz/(2 sqrt 2)) in FP64, and combines them at the origin.  The block stages up to 24
 // nodes of a half ray at a time in LDS (cell records, the lines' coefficients, their J_nu
 // rows, and the sub-step segments between them).  Inside a sub-step segment the line
 // profile follows the multiplicative recurrence of the line formal solve (exact restarts
 // after at most 16 widths of travel) and, on an evenly spaced quadrature, the position
 // of +-y advances by a constant; the state is renormalised at every cell node and every
-// fourth sub-step.  Besides J, L* (times chi_line/chi_t) and Jeff it returns J_nu at the
-// quadrature offsets from u and the flux-like v at the origin: I(n, x) = u(x) + v(x) and
-// I(-n, x) = u(-x) - v(-x) for the pair representative n.
+// fourth sub-step.  Besides J, L* (times chi_line/chi_t) and Jeff it returns Jw at the
+// quadrature offsets from u and v at the origin: I(n, x) = u(x) + v(x) and
+// I(-n, x) = u(-x) - v(-x) for the pair representative n, weighted by w(+-n) of the origin.
 #include "nlte_internal.h"
 #include "device_math.h"
 
@@ -172,7 +181,7 @@ __device__ __forceinline__ void j_sub(const QGeo &g, const double *rp, const dou
 // line slot the line-centre opacity, source function, scattering opacity and J_nu row.
 struct SNode {
     double Z, s, vw, a, b;
-    double kap[2], S[2], cs[2];
+    double kap[2], S[2], cs[2], cm[2];   // cm: chi^- along the sweep direction
     const double *jrow[2];
 };
 
@@ -180,9 +189,12 @@ struct SNode {
 // hz = (Z - Z_next)/(2 sqrt 2 m), per sub-interval increments of the Doppler coefficients
 // and of kappa, S and chi_s; maxdx bounds |dy| over the quadrature, K is the restart
 // interval of the profile recurrence (0: direct evaluation).
+// With an odd opacity: per sub-interval the increment dcm of cm, the path length ds, and
+// the frame factor e^{-dM} of the first sub-interval (f0) and its ratio between successive
+// ones (rho), dM = ds (cm_j + cm_{j+1})/2 being linear in the sub-interval index.
 struct SSeg {
-    double hz, da, db, im, maxdx;
-    double dk[2], dS[2], dcs[2];
+    double hz, da, db, im, maxdx, ds;
+    double dk[2], dS[2], dcs[2], dcm[2], f0[2], rho[2];
     int m, K;
 };
 
@@ -191,15 +203,23 @@ struct NodeVal {
     double chit, Sp, sq;
 };
 
-// S+ = S + r (Jbar - S) and sigma~ = r (J(-y) - J(y))/2 with r = chi_s/chi_t, the
-// scattering share (safe for denormal far-wing opacities).
-__device__ __forceinline__ NodeVal node_val(double cl, double cs, double S, double jp, double jm)
+// S+ = S + r (Jbar - S) + rm dJ and sigma~ = r dJ + rm Jbar with r = chi_s/chi_t, the
+// scattering share, and rm = cm/chi_t (safe for denormal far-wing opacities; cm = 0
+// wherever chi_s = 0).
+template <bool ANISO>
+__device__ __forceinline__ NodeVal node_val(double cl, double cs, double cm, double S, double jp, double jm)
 {
     NodeVal v;
     v.chit = cl + cs;
-    const double r = cs > 0.0 ? cs * rcp_refined(v.chit) : 0.0;   // chit >= cs > 0
+    const double ic = cs > 0.0 ? rcp_refined(v.chit) : 0.0;   // chit >= cs > 0
+    const double r = cs * ic;
     v.Sp = v.chit > 0.0 ? fma(0.5 * r, jp + jm, fma(-r, S, S)) : 0.0;
     v.sq = (0.5 * kISq2 * r) * (jm - jp);
+    if (ANISO) {
+        const double rm = cm * ic;
+        v.Sp = fma(0.5 * rm, jm - jp, v.Sp);
+        v.sq = fma(0.5 * kISq2 * rm, jp + jm, v.sq);
+    }
     return v;
 }
 
@@ -207,10 +227,11 @@ __device__ __forceinline__ NodeVal node_val(double cl, double cs, double S, doub
 __device__ __forceinline__ double profile(double y) { return exp_le700(fmax(-(y * y), -800.0)); }
 
 // Elimination state of a half sweep and the last node reached (chit, Sp, sq), with sq_pp
-// the sq of the node before it (a virtual -sq at the far end).
+// and Sp_pp the sq and Sp of the node before it (virtual -sq, -Sp at the far end); y is
+// the particular solution of the u-equation, yv that of the v-equation.
 struct HalfState {
-    double n, d, y, Pm;
-    double chit, Sp, sq, sq_pp;
+    double n, d, y, yv, Pm;
+    double chit, Sp, sq, sq_pp, Sp_pp;
 };
 
 __device__ __forceinline__ void start(HalfState &h, const NodeVal &first, double I_in)
@@ -218,11 +239,28 @@ __device__ __forceinline__ void start(HalfState &h, const NodeVal &first, double
     h.n = kSq2;
     h.d = 1.0;
     h.y = kSq2 * I_in;
+    h.yv = kSq2 * I_in;
     h.Pm = 0.0;
     h.chit = first.chit;
     h.Sp = first.Sp;
     h.sq = first.sq;
     h.sq_pp = -first.sq;
+    h.Sp_pp = -first.Sp;
+}
+
+// Move the state into the frame of the next node: the particular solutions and the held
+// sources times e^{-dM} of the sub-interval.
+template <bool ANISO>
+__device__ __forceinline__ void reframe(HalfState &h, double f)
+{
+    if (ANISO) {
+        h.y *= f;
+        h.yv *= f;
+        h.Sp *= f;
+        h.sq *= f;
+        h.sq_pp *= f;
+        h.Sp_pp *= f;
+    }
 }
 
 // Eliminate the last node, stepping to node v over a sub-interval of weight hz.
@@ -233,9 +271,12 @@ __device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
     const double hd = (h.Pm + P) * h.d;
     h.n += hd;
     h.y = fma(h.sq_pp - v.sq, h.d, fma(h.Sp, hd, h.y));   // y + S+ h d - (sigma~ - sigma~_pp) d / sqrt 2
+    // yv + sigma~ h d - (S+ - S+_pp) d / sqrt 2
+    h.yv = fma((h.Sp_pp - v.Sp) * kISq2, h.d, fma(kSq2 * h.sq, hd, h.yv));
     h.d = fma(P, h.n, h.d);
     h.Pm = P;
     h.sq_pp = h.sq;
+    h.Sp_pp = h.Sp;
     h.chit = v.chit;
     h.Sp = v.Sp;
     h.sq = v.sq;
@@ -244,18 +285,20 @@ __device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
         h.n = ldexp(h.n, -ex);
         h.d = ldexp(h.d, -ex);
         h.y = ldexp(h.y, -ex);
+        h.yv = ldexp(h.yv, -ex);
     }
 }
 
-// Running values of a lane inside a recurrence segment (pos: the lookup position).
+// Running values of a lane inside a recurrence segment (pos: the lookup position; f: the
+// frame factor of the next sub-interval).
 struct SubRun {
-    double g, r, kq, cs, S, pos, tt;
+    double g, r, kq, cs, cm, S, pos, tt, f;
 };
 
-template <bool UNI, bool RENORM>
-__device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, double dk, double dcs, double dS,
-                                         double dpos, double im, const QGeo &qg, const double *rp, const double *rq,
-                                         double hz)
+template <bool UNI, bool ANISO, bool RENORM>
+__device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, double dk, double dcs, double dcm,
+                                         double dS, double dpos, double im, double rho, const QGeo &qg,
+                                         const double *rp, const double *rq, double hz)
 {
     w.g *= w.r;
     w.r *= c;
@@ -264,15 +307,22 @@ __device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, doub
     w.S += dS;
     w.pos += dpos;
     w.tt += im;
+    if (ANISO) w.cm += dcm;
     double jp, jm;
     j_sub<UNI>(qg, rp, rq, w.pos, w.tt, jp, jm);
-    step<RENORM>(h, node_val(w.kq * w.g, w.cs, w.S, jp, jm), hz);
+    const NodeVal v = node_val<ANISO>(w.kq * w.g, w.cs, w.cm, w.S, jp, jm);
+    reframe<ANISO>(h, w.f);
+    if (ANISO) w.f *= rho;
+    step<RENORM>(h, v, hz);
 }
 
+// e^{-x} for the frame factors, with x kept where the factor and its inverse are finite.
+__device__ __forceinline__ double frame_exp(double x) { return exp_le700(fmin(fmax(-x, -700.0), 700.0)); }
+
 // Half sweep along `ray` (lane offset x in that ray's frame, line slot gs of the `per`
-// staged lines line0 ..) from the far end of its walk to O; on return h holds O's node.
-// jr receives the staged nodes' J_nu rows, [node][slot][n_q].
-template <bool UNI>
+// staged lines line0 ..) from the far end of its walk to O; on return h holds O's node,
+// in O's frame.  jr receives the staged nodes' J_nu rows, [node][slot][n_q].
+template <bool UNI, bool ANISO>
 __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, double *jr, int per, int64_t O,
                      const CellRec &cO, int ray, double x, int line0, int gs, double I_in, double xq_max,
                      HalfState &h)
@@ -282,7 +332,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
     const int64_t beg = a.roff[O * a.n_rays + ray];
     const int L = (int)(a.roff[O * a.n_rays + ray + 1] - beg);   // cells; nodes 0 .. L (O)
     const double2 *lc = reinterpret_cast<const double2 *>(a.lc);
-    double y_cur = 0.0, g_cur = 0.0, kap_cur = 0.0, cs_cur = 0.0, S_cur = 0.0, travel = 0.0;
+    double y_cur = 0.0, g_cur = 0.0, kap_cur = 0.0, cs_cur = 0.0, cm_cur = 0.0, S_cur = 0.0, travel = 0.0;
     const double *row_cur = nullptr;
     for (int b0 = 0;; b0 += kChunk - 1) {
         __syncthreads();
@@ -306,6 +356,12 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                 v.kap[l] = k.x;
                 v.S[l] = k.y;
                 v.cs[l] = a.chi_sca[c * a.n_lines + ln];
+                v.cm[l] = 0.0;
+                if (ANISO) {
+                    // the sweep runs toward O, against the ray's direction
+                    const double *dp = a.chi_dip + 3 * (c * a.n_lines + ln);
+                    v.cm[l] = -((dp[0] * nx + dp[1] * ny) + dp[2] * nz);
+                }
                 v.jrow[l] = a.Jin + (c * a.n_lines + ln) * a.n_q;
             }
             nd[t] = v;
@@ -326,6 +382,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
             e.m = m;
             e.im = 1.0 / (double)m;
             e.hz = 0.5 * kISq2 * (p.Z - q.Z) * e.im;
+            e.ds = (p.Z - q.Z) * e.im;
             e.da = (q.a - p.a) * e.im;
             e.db = (q.b - p.b) * e.im;
 #pragma unroll
@@ -333,6 +390,13 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                 e.dk[l] = (q.kap[l] - p.kap[l]) * e.im;
                 e.dS[l] = (q.S[l] - p.S[l]) * e.im;
                 e.dcs[l] = (q.cs[l] - p.cs[l]) * e.im;
+                e.dcm[l] = 0.0;
+                e.f0[l] = e.rho[l] = 1.0;
+                if (ANISO) {
+                    e.dcm[l] = (q.cm[l] - p.cm[l]) * e.im;
+                    e.f0[l] = frame_exp(e.ds * fma(0.5, e.dcm[l], p.cm[l]));
+                    e.rho[l] = frame_exp(e.ds * e.dcm[l]);
+                }
             }
             e.maxdx = (fabs(q.a - p.a) * xq_max + fabs(q.b - p.b)) * e.im;
             e.K = e.maxdx > 4.0 ? 0 : (e.maxdx > 0.25 ? (int)(16.0 / e.maxdx) : 64);
@@ -357,25 +421,29 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
             g_cur = profile(y_cur);
             kap_cur = nd[0].kap[gs];
             cs_cur = nd[0].cs[gs];
+            cm_cur = nd[0].cm[gs];
             S_cur = nd[0].S[gs];
             double jp, jm;
             j_node<UNI>(qg, row_cur, qpos<UNI>(qg, y_cur), jp, jm);
-            start(h, node_val(kap_cur * g_cur, cs_cur, S_cur, jp, jm), I_in);
+            start(h, node_val<ANISO>(kap_cur * g_cur, cs_cur, cm_cur, S_cur, jp, jm), I_in);
         }
         const int nseg = min(kChunk - 1, L - b0);
         for (int i = 0; i < nseg; ++i) {
             const int m = sgm[i].m;
             const double hz = sgm[i].hz;
             const double kap_n = nd[i + 1].kap[gs], cs_n = nd[i + 1].cs[gs], S_n = nd[i + 1].S[gs];
+            const double cm_n = nd[i + 1].cm[gs];
             const double *row_n = jr + ((i + 1) * per + gs) * a.n_q;
             const double y_n = nd[i + 1].a * x - nd[i + 1].b;
             double g_n;
+            double f = ANISO ? sgm[i].f0[gs] : 1.0;   // frame factor of the next sub-interval
             if (m == 1) {
                 g_n = profile(y_n);
                 travel = 0.0;
             } else {
                 const double dy = sgm[i].da * x - sgm[i].db;
                 const double dk = sgm[i].dk[gs], dS = sgm[i].dS[gs], dcs = sgm[i].dcs[gs], im = sgm[i].im;
+                const double dcm = ANISO ? sgm[i].dcm[gs] : 0.0, rho = ANISO ? sgm[i].rho[gs] : 1.0;
                 const double mdx = sgm[i].maxdx;
                 const int K = sgm[i].K;
                 if (K == 0 || m == 2) {
@@ -384,8 +452,11 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                         const double yj = fma(fj, dy, y_cur);
                         double jp, jm;
                         j_sub<UNI>(qg, row_cur, row_n, qpos<UNI>(qg, yj), fj * im, jp, jm);
-                        step<true>(h, node_val(fma(fj, dk, kap_cur) * profile(yj), fma(fj, dcs, cs_cur),
-                                               fma(fj, dS, S_cur), jp, jm), hz);
+                        const NodeVal v = node_val<ANISO>(fma(fj, dk, kap_cur) * profile(yj), fma(fj, dcs, cs_cur),
+                                                          fma(fj, dcm, cm_cur), fma(fj, dS, S_cur), jp, jm);
+                        reframe<ANISO>(h, f);
+                        if (ANISO) f *= rho;
+                        step<true>(h, v, hz);
                     }
                     g_n = profile(y_n);
                     travel = 0.0;
@@ -401,9 +472,11 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                     w.r = exp_le700(fmax(fmin(-(2.0 * y_cur + dy) * dy, 700.0), -800.0));
                     w.kq = kap_cur;
                     w.cs = cs_cur;
+                    w.cm = cm_cur;
                     w.S = S_cur;
                     w.pos = qpos<UNI>(qg, y_cur);
                     w.tt = 0.0;
+                    w.f = f;
                     const double dpos = UNI ? dy * qg.inv_h : dy;
                     int budget = K;
                     if (mdx > 0.0) budget = (int)fmin((16.0 - travel) / mdx, (double)K);
@@ -418,19 +491,20 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                         const int jint = min(jend, m - 1);
                         int jj = j;
                         for (; jj + 3 < jint; jj += 4) {
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, true>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, true>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
                         }
                         // the last 0-3 steps; the cell node's step that follows renormalises,
                         // so at most seven steps pass between renormalisations
                         const int rem = jint - jj;
                         if (rem >= 2) {
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
-                            sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
                         }
-                        if (rem & 1) sub_step<UNI, false>(h, w, c, dk, dcs, dS, dpos, im, qg, row_cur, row_n, hz);
+                        if (rem & 1)
+                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
                         travel += mdx * (double)(jint - j);
                         j = jint;
                         if (jend == m) {
@@ -447,19 +521,27 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                         w.cs = fma(fj, dcs, cs_cur);
                         w.S = fma(fj, dS, S_cur);
                         w.tt = fj * im;
+                        if (ANISO) {
+                            w.cm = fma(fj, dcm, cm_cur);
+                            w.f = frame_exp(sgm[i].ds * fma(fj + 0.5, dcm, cm_cur));
+                        }
                         travel = 0.0;
                         budget = K;
                     }
                     g_n = w.g;
+                    f = w.f;
                 }
             }
             double jp, jm;
             j_node<UNI>(qg, row_n, qpos<UNI>(qg, y_n), jp, jm);
-            step<true>(h, node_val(kap_n * g_n, cs_n, S_n, jp, jm), hz);
+            const NodeVal vn = node_val<ANISO>(kap_n * g_n, cs_n, cm_n, S_n, jp, jm);
+            reframe<ANISO>(h, f);
+            step<true>(h, vn, hz);
             y_cur = y_n;
             g_cur = g_n;
             kap_cur = kap_n;
             cs_cur = cs_n;
+            cm_cur = cm_n;
             S_cur = S_n;
             row_cur = row_n;
         }
@@ -469,7 +551,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
 
 }  // namespace
 
-template <bool UNI>
+template <bool UNI, bool ANISO>
 __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
 {
     extern __shared__ double smem[];
@@ -510,12 +592,23 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
     const CellRec cO = a.cell[O];
     const double I_in = a.ibdy[lc_line];
     const double2 lcO = reinterpret_cast<const double2 *>(a.lc)[row];
+    // direction weights of the re-emitted field at O: w(+-n) = 1 +- e . n, e = chi_dip/chi_s
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    if (ANISO) {
+        const double cs = a.chi_sca[row];
+        if (cs > 0.0) {
+            const double *dp = a.chi_dip + 3 * row;
+            ex = dp[0] / cs;
+            ey = dp[1] / cs;
+            ez = dp[2] / cs;
+        }
+    }
     double accJ = 0.0, accL = 0.0, accE = 0.0, jp = 0.0, jm = 0.0;
     for (int p = 0; p < a.n_pairs; ++p) {
         const int r = a.pair_r[p], rb = a.anti[r];
         HalfState f, b;
-        half<UNI>(a, qg, nd, sgm, jr, per, O, cO, r, x, line0, g, I_in, xq_max, f);
-        half<UNI>(a, qg, nd, sgm, jr, per, O, cO, rb, -x, line0, g, I_in, xq_max, b);
+        half<UNI, ANISO>(a, qg, nd, sgm, jr, per, O, cO, r, x, line0, g, I_in, xq_max, f);
+        half<UNI, ANISO>(a, qg, nd, sgm, jr, per, O, cO, rb, -x, line0, g, I_in, xq_max, b);
         // combine at O: h u + (Q_f u - y_f) + (Q_b u - y_b) = h R_O (scaled rows)
         const double idf = 1.0 / f.d, idb = 1.0 / b.d;
         const double h = f.Pm + b.Pm;
@@ -529,13 +622,18 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
         accJ += w * u;
         accL += w * (h * inv) * ratio;
         accE += w * ((h * (f.Sp - ratio * lcO.y) + yy + sgO) * inv);
-        // v along n = ray r: the half-node fluxes (u_O - u_nb)/dtau on each side from the
-        // elimination state, with sigma at the half nodes, interpolated in tau to O
-        const double fl_f = ((f.n * u - f.y) * idf - (f.sq_pp + f.sq)) * kISq2;
-        const double fl_b = ((b.n * u - b.y) * idb - (b.sq_pp + b.sq)) * kISq2;
-        const double v = h > 0.0 ? (b.Pm * fl_f - f.Pm * fl_b) / h : 0.5 * (fl_f - fl_b);
-        jp += u + v;
-        jm += u - v;
+        // v along n = ray r, the sweep direction of half b, from the v-equation: the same
+        // combine with b's particular solution and f's with the sign of the other
+        // orientation, sigma~_O (b's) in place of S+_O and the S+ difference across O
+        const double v = (h * kSq2 * b.sq + (b.yv * idb - f.yv * idf) + (b.Sp_pp - f.Sp_pp) * kISq2) * inv;
+        double wp = 1.0, wm = 1.0;
+        if (ANISO) {
+            const double en = (ex * a.dir[3 * r] + ey * a.dir[3 * r + 1]) + ez * a.dir[3 * r + 2];
+            wp += en;
+            wm -= en;
+        }
+        jp += wp * (u + v);
+        jm += wm * (u - v);
     }
     __syncthreads();   // the staging area becomes the reduction area
     s_red[t] = act ? accJ : 0.0;
@@ -586,10 +684,18 @@ hipError_t launch_formal_solve_scat(const ScatArgs &a, hipStream_t s)
     const size_t stage = kChunk * (sizeof(SNode) + sizeof(SSeg) + sizeof(double) * (size_t)per * a.n_q);
     const size_t red = 5 * sizeof(double) * (size_t)threads;
     const size_t shmem = sizeof(double) * (size_t)a.n_q + (stage > red ? stage : red);
-    if (a.q_uniform)
-        hipLaunchKernelGGL(k_formal_solve_scat<true>, dim3((unsigned)(a.P * groups)), dim3(threads), shmem, s, a);
-    else
-        hipLaunchKernelGGL(k_formal_solve_scat<false>, dim3((unsigned)(a.P * groups)), dim3(threads), shmem, s, a);
+    const dim3 grid((unsigned)(a.P * groups));
+    if (a.chi_dip != nullptr) {
+        if (a.q_uniform)
+            hipLaunchKernelGGL((k_formal_solve_scat<true, true>), grid, dim3(threads), shmem, s, a);
+        else
+            hipLaunchKernelGGL((k_formal_solve_scat<false, true>), grid, dim3(threads), shmem, s, a);
+    } else {
+        if (a.q_uniform)
+            hipLaunchKernelGGL((k_formal_solve_scat<true, false>), grid, dim3(threads), shmem, s, a);
+        else
+            hipLaunchKernelGGL((k_formal_solve_scat<false, false>), grid, dim3(threads), shmem, s, a);
+    }
     return hipGetLastError();
 }
 

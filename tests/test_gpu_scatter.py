@@ -152,3 +152,100 @@ def test_scattering_argument_checks():
     s.set_scattering(None)
     with pytest.raises(NlteError):
         s.formal_solve_scat(s.lte(), np.zeros((w.n_points, 1, w.quad_x.shape[0])))
+
+
+# ---------------------------------------------------------------- odd scattering opacity
+
+
+def _dipole(w, chi_sca, seed, frac=(0.0, 1.0)):
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(w.n_points, w.species.n_lines, 3))
+    d /= np.linalg.norm(d, axis=2, keepdims=True)
+    return d * (chi_sca * rng.uniform(*frac, chi_sca.shape))[:, :, None]
+
+
+@pytest.mark.parametrize("nq", [31, "gh24"])
+def test_dipole_formal_solve_matches_oracle(nq):
+    """chi_s(n) = chi_sca + chi_dip . n with dipoles up to the full opacity: J, L*, Jeff and
+    the weighted field Jw against the oracle's global integrating factor (the kernel
+    re-frames its elimination at every sub-step)."""
+    w = configs.outflow5(n_points=300, seed=2, nside=1)
+    if nq == "gh24":
+        w.quad_x, w.quad_w = directions.gauss_hermite(24)
+    o = oracle_for(w)
+    pops, chi_sca, Jnu = _fields(o, w, 15)
+    dip = _dipole(w, chi_sca, 16)
+    ref = o.formal_solve_scat(pops, chi_sca, Jnu, chi_dip=dip)
+    s = solver_for(w)
+    s.set_scattering(chi_sca)
+    s.set_scattering_dipole(dip)
+    _check(s.formal_solve_scat(pops, Jnu), ref, tol=1e-9)
+    # the odd part matters at this size
+    iso = o.formal_solve_scat(pops, chi_sca, Jnu)
+    assert rel(ref[3], iso[3]).max() > 1e-3
+
+
+def test_dipole_formal_solve_static_sphere_matches_oracle():
+    w = configs.sphere2(n_points=400, seed=7)
+    o = oracle_for(w)
+    pops, chi_sca, Jnu = _fields(o, w, 17)
+    dip = _dipole(w, chi_sca, 18)
+    s = solver_for(w)
+    s.set_scattering(chi_sca)
+    s.set_scattering_dipole(dip)
+    _check(s.formal_solve_scat(pops, Jnu), o.formal_solve_scat(pops, chi_sca, Jnu, chi_dip=dip), tol=1e-9)
+
+
+def test_zero_dipole_is_the_isotropic_solve():
+    w = configs.outflow5(n_points=200, seed=5, nside=1)
+    o = oracle_for(w)
+    pops, chi_sca, Jnu = _fields(o, w, 19)
+    s = solver_for(w)
+    s.set_scattering(chi_sca)
+    a = s.formal_solve_scat(pops, Jnu)
+    s.set_scattering_dipole(np.zeros((w.n_points, w.species.n_lines, 3)))
+    b = s.formal_solve_scat(pops, Jnu)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    # a new scattering opacity drops the dipole
+    s.set_scattering_dipole(_dipole(w, chi_sca, 20))
+    assert not np.array_equal(s.formal_solve_scat(pops, Jnu)[3], a[3])
+    s.set_scattering(chi_sca)
+    assert np.array_equal(s.formal_solve_scat(pops, Jnu)[3], a[3])
+
+
+@pytest.mark.parametrize("iters", [1, 3])
+def test_dipole_ali_matches_oracle(iters):
+    w = configs.outflow5(n_points=100, seed=3, nside=1)
+    o = oracle_for(w)
+    _, chi_sca, _ = _fields(o, w, 21)
+    dip = _dipole(w, chi_sca, 22)
+    ref, ch, Jref = o.run_ali_scat(chi_sca, max_iter=iters, tol=0.0, chi_dip=dip)
+    s = solver_for(w, max_iter=iters, tol=0.0)
+    s.set_scattering(chi_sca)
+    s.set_scattering_dipole(dip)
+    pops, rep = s.run_ali()
+    assert rep["iterations"] == iters
+    assert rel(pops, ref).max() <= 1e-9
+    assert rel(s.scattering_field(), Jref).max() <= 1e-9
+    assert np.allclose(rep["max_change"], ch, rtol=1e-6, atol=1e-14)
+
+
+def test_dipole_argument_checks():
+    from paper_1912_08445_amd.binding import NlteError
+    w = configs.sphere2(n_points=100)
+    s = solver_for(w)
+    d = np.zeros((w.n_points, 1, 3))
+    with pytest.raises(NlteError):
+        s.set_scattering_dipole(d)          # no scattering opacity yet
+    chi = np.ones((w.n_points, 1)) * 1e-18
+    s.set_scattering(chi)
+    d[5, 0] = [1e-18, 1e-18, 0.0]           # |d| = 1.41 chi_sca
+    with pytest.raises(NlteError):
+        s.set_scattering_dipole(d)
+    d[5, 0] = [np.nan, 0.0, 0.0]
+    with pytest.raises(NlteError):
+        s.set_scattering_dipole(d)
+    d[5, 0] = [0.0, 0.0, 1e-18]             # exactly the full opacity along z
+    s.set_scattering_dipole(d)
+    s.set_scattering_dipole(None)
