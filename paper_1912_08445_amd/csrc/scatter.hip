@@ -39,6 +39,8 @@
 // fourth sub-step.  Besides J, L* (times chi_line/chi_t) and Jeff it returns Jw at the
 // quadrature offsets from u and v at the origin: I(n, x) = u(x) + v(x) and
 // I(-n, x) = u(-x) - v(-x) for the pair representative n, weighted by w(+-n) of the origin.
+#include <type_traits>
+
 #include "nlte_internal.h"
 #include "device_math.h"
 
@@ -223,8 +225,8 @@ __device__ __forceinline__ NodeVal node_val(double cl, double cs, double cm, dou
     return v;
 }
 
-// e^{-y^2}, clamped where the result is 0 in FP64 anyway.
-__device__ __forceinline__ double profile(double y) { return exp_le700(fmax(-(y * y), -800.0)); }
+// e^{-y^2} by the table-driven exponential (tab: 2^{j/16} in LDS).
+__device__ __forceinline__ double profile(double y, const double *tab) { return exp_tab16(-(y * y), tab); }
 
 // Elimination state of a half sweep and the last node reached (chit, Sp, sq), with sq_pp
 // and Sp_pp the sq and Sp of the node before it (virtual -sq, -Sp at the far end); y is
@@ -295,21 +297,31 @@ struct SubRun {
     double g, r, kq, cs, cm, S, pos, tt, f;
 };
 
-template <bool UNI, bool ANISO, bool RENORM>
+// Jw end values of a segment whose lookups clamp: +y lookups a + t da, -y lookups a_m + t da_m.
+struct JEnds {
+    double ap, dap, am, dam;
+};
+
+template <bool UNI, bool ANISO, bool CLAMP, bool RENORM>
 __device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, double dk, double dcs, double dcm,
                                          double dS, double dpos, double im, double rho, const QGeo &qg,
-                                         const double *rp, const double *rq, double hz)
+                                         const double *rp, const double *rq, const JEnds &je, double hz)
 {
     w.g *= w.r;
     w.r *= c;
     w.kq += dk;
     w.cs += dcs;
     w.S += dS;
-    w.pos += dpos;
     w.tt += im;
     if (ANISO) w.cm += dcm;
     double jp, jm;
-    j_sub<UNI>(qg, rp, rq, w.pos, w.tt, jp, jm);
+    if constexpr (CLAMP) {
+        jp = fma(w.tt, je.dap, je.ap);
+        jm = fma(w.tt, je.dam, je.am);
+    } else {
+        w.pos += dpos;
+        j_sub<UNI>(qg, rp, rq, w.pos, w.tt, jp, jm);
+    }
     const NodeVal v = node_val<ANISO>(w.kq * w.g, w.cs, w.cm, w.S, jp, jm);
     reframe<ANISO>(h, w.f);
     if (ANISO) w.f *= rho;
@@ -323,15 +335,16 @@ __device__ __forceinline__ double frame_exp(double x) { return exp_le700(fmin(fm
 // staged lines line0 ..) from the far end of its walk to O; on return h holds O's node,
 // in O's frame.  jr receives the staged nodes' J_nu rows, [node][slot][n_q].
 template <bool UNI, bool ANISO>
-__device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, double *jr, int per, int64_t O,
-                     const CellRec &cO, int ray, double x, int line0, int gs, double I_in, double xq_max,
-                     HalfState &h)
+__device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode *nd, SSeg *sgm, double *jr, int per, int64_t O,
+                     const CellRec &cO, int ray, double x, bool live, int line0, int gs, double I_in,
+                     double xq_max, HalfState &h)
 {
     const int t = threadIdx.x;
     const double nx = a.dir[3 * ray], ny = a.dir[3 * ray + 1], nz = a.dir[3 * ray + 2];
     const int64_t beg = a.roff[O * a.n_rays + ray];
     const int L = (int)(a.roff[O * a.n_rays + ray + 1] - beg);   // cells; nodes 0 .. L (O)
     const double2 *lc = reinterpret_cast<const double2 *>(a.lc);
+    const int rl = per * a.n_q, cslot = t / a.n_q, cq = t - cslot * a.n_q;
     double y_cur = 0.0, g_cur = 0.0, kap_cur = 0.0, cs_cur = 0.0, cm_cur = 0.0, S_cur = 0.0, travel = 0.0;
     const double *row_cur = nullptr;
     for (int b0 = 0;; b0 += kChunk - 1) {
@@ -402,23 +415,18 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
             e.K = e.maxdx > 4.0 ? 0 : (e.maxdx > 0.25 ? (int)(16.0 / e.maxdx) : 64);
             sgm[t] = e;
         }
-        {
-            // the staged nodes' J_nu rows, read row by row
+        if (t < rl) {
+            // the staged nodes' J_nu rows: lane t copies entry cq of slot cslot of every node
+            // (a row set per * n_q never exceeds the block)
             const int nst = min(kChunk, L - b0 + 1);
-            const int rl = per * a.n_q;
-            for (int idx = t; idx < nst * rl; idx += (int)blockDim.x) {
-                const int node = idx / rl;
-                const int rest = idx - node * rl;
-                const int slot = rest / a.n_q;
-                jr[idx] = nd[node].jrow[slot][rest - slot * a.n_q];
-            }
+            for (int node = 0; node < nst; ++node) jr[node * rl + t] = nd[node].jrow[cslot][cq];
         }
         __syncthreads();
         // ---- sweep the staged segments
         row_cur = jr + gs * a.n_q;   // node 0 of the chunk
         if (b0 == 0) {
             y_cur = nd[0].a * x - nd[0].b;
-            g_cur = profile(y_cur);
+            g_cur = profile(y_cur, tab);
             kap_cur = nd[0].kap[gs];
             cs_cur = nd[0].cs[gs];
             cm_cur = nd[0].cm[gs];
@@ -438,7 +446,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
             double g_n;
             double f = ANISO ? sgm[i].f0[gs] : 1.0;   // frame factor of the next sub-interval
             if (m == 1) {
-                g_n = profile(y_n);
+                g_n = profile(y_n, tab);
                 travel = 0.0;
             } else {
                 const double dy = sgm[i].da * x - sgm[i].db;
@@ -446,30 +454,58 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                 const double dcm = ANISO ? sgm[i].dcm[gs] : 0.0, rho = ANISO ? sgm[i].rho[gs] : 1.0;
                 const double mdx = sgm[i].maxdx;
                 const int K = sgm[i].K;
-                if (K == 0 || m == 2) {
-                    for (int j = 1; j < m; ++j) {
-                        const double fj = (double)j;
-                        const double yj = fma(fj, dy, y_cur);
-                        double jp, jm;
-                        j_sub<UNI>(qg, row_cur, row_n, qpos<UNI>(qg, yj), fj * im, jp, jm);
-                        const NodeVal v = node_val<ANISO>(fma(fj, dk, kap_cur) * profile(yj), fma(fj, dcs, cs_cur),
-                                                          fma(fj, dcm, cm_cur), fma(fj, dS, S_cur), jp, jm);
-                        reframe<ANISO>(h, f);
-                        if (ANISO) f *= rho;
-                        step<true>(h, v, hz);
-                    }
-                    g_n = profile(y_n);
-                    travel = 0.0;
+                // Every lane's offsets beyond the quadrature on one side over the whole
+                // segment (x is linear in the sub-step index): both lookups clamp to the end
+                // values of the rows, so Jw of a sub-node is linear in its fraction t
+                bool clampJ;
+                if constexpr (UNI) {
+                    const double pc = qpos<UNI>(qg, y_cur), pn = qpos<UNI>(qg, y_n);
+                    clampJ = (pc >= qg.top && pn >= qg.top) || (pc <= 0.0 && pn <= 0.0);
                 } else {
+                    const double lo = qg.qx[0], hi = qg.qx[qg.nq - 1];
+                    clampJ = (y_cur >= hi && y_n >= hi) || (y_cur <= lo && y_n <= lo);
+                }
+                clampJ = __all(clampJ || !live);   // (lanes without a frequency do not vote)
+                // (lookup of +y at ep, of -y at em; the rows' end values and their changes over t)
+                const int ep = y_cur > 0.0 ? qg.nq - 1 : 0, em = qg.nq - 1 - ep;
+                const double ap = row_cur[ep], am = row_cur[em];
+                const double dap = row_n[ep] - ap, dam = row_n[em] - am;
+                // far wing besides: e^{-y^2} is 0 in FP64 at every sub-node (no line opacity)
+                const bool far = clampJ && __all(!live || (((y_cur > 0.0) == (y_n > 0.0)) && y_cur * y_cur > 750.0 &&
+                                                           y_n * y_n > 750.0));
+                auto sweep = [&](auto clamp_tag) {
+                    constexpr bool CLAMP = decltype(clamp_tag)::value;
+                    if (K == 0 || m == 2) {
+                        for (int j = 1; j < m; ++j) {
+                            const double fj = (double)j;
+                            const double yj = fma(fj, dy, y_cur);
+                            double jp, jm;
+                            if constexpr (CLAMP) {
+                                jp = fma(fj * im, dap, ap);
+                                jm = fma(fj * im, dam, am);
+                            } else {
+                                j_sub<UNI>(qg, row_cur, row_n, qpos<UNI>(qg, yj), fj * im, jp, jm);
+                            }
+                            const NodeVal v = node_val<ANISO>(fma(fj, dk, kap_cur) * profile(yj, tab), fma(fj, dcs, cs_cur),
+                                                              fma(fj, dcm, cm_cur), fma(fj, dS, S_cur), jp, jm);
+                            reframe<ANISO>(h, f);
+                            if (ANISO) f *= rho;
+                            step<true>(h, v, hz);
+                        }
+                        g_n = profile(y_n, tab);
+                        travel = 0.0;
+                        return;
+                    }
                     // g_{j+1} = g_j r_j, r_{j+1} = r_j c with r_j = e^{-2 y_j dy - dy^2} and
                     // c = e^{-2 dy^2}; exact values again whenever y may have moved by more
                     // than 16 widths since the last exact one, so that an underflowed value
                     // (|y| > 27) cannot hide a profile above e^{-121}
                     const double u2 = 2.0 * dy * dy;
                     const double c = mdx <= 0.5 ? exp_neg_small(u2) : exp_le700(-u2);
+                    const JEnds je{ap, dap, am, dam};
                     SubRun w;
                     w.g = g_cur;
-                    w.r = exp_le700(fmax(fmin(-(2.0 * y_cur + dy) * dy, 700.0), -800.0));
+                    w.r = exp_tab16(fmin(-(2.0 * y_cur + dy) * dy, 700.0), tab);
                     w.kq = kap_cur;
                     w.cs = cs_cur;
                     w.cm = cm_cur;
@@ -481,7 +517,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                     int budget = K;
                     if (mdx > 0.0) budget = (int)fmin((16.0 - travel) / mdx, (double)K);
                     if (budget < 1) {
-                        w.g = profile(y_cur);
+                        w.g = profile(y_cur, tab);
                         travel = 0.0;
                         budget = K;
                     }
@@ -491,20 +527,20 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                         const int jint = min(jend, m - 1);
                         int jj = j;
                         for (; jj + 3 < jint; jj += 4) {
-                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
-                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
-                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
-                            sub_step<UNI, ANISO, true>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, CLAMP, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, je, hz);
+                            sub_step<UNI, ANISO, CLAMP, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, je, hz);
+                            sub_step<UNI, ANISO, CLAMP, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, je, hz);
+                            sub_step<UNI, ANISO, CLAMP, true>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, je, hz);
                         }
                         // the last 0-3 steps; the cell node's step that follows renormalises,
                         // so at most seven steps pass between renormalisations
                         const int rem = jint - jj;
                         if (rem >= 2) {
-                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
-                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, CLAMP, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, je, hz);
+                            sub_step<UNI, ANISO, CLAMP, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, je, hz);
                         }
                         if (rem & 1)
-                            sub_step<UNI, ANISO, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, hz);
+                            sub_step<UNI, ANISO, CLAMP, false>(h, w, c, dk, dcs, dcm, dS, dpos, im, rho, qg, row_cur, row_n, je, hz);
                         travel += mdx * (double)(jint - j);
                         j = jint;
                         if (jend == m) {
@@ -515,8 +551,8 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                         const double fj = (double)j;
                         const double yj = fma(fj, dy, y_cur);
                         w.pos = qpos<UNI>(qg, yj);
-                        w.g = profile(yj);
-                        w.r = exp_le700(fmax(fmin(-(2.0 * yj + dy) * dy, 700.0), -800.0));
+                        w.g = profile(yj, tab);
+                        w.r = exp_tab16(fmin(-(2.0 * yj + dy) * dy, 700.0), tab);
                         w.kq = fma(fj, dk, kap_cur);
                         w.cs = fma(fj, dcs, cs_cur);
                         w.S = fma(fj, dS, S_cur);
@@ -530,6 +566,46 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, SNode *nd, SSeg *sgm, do
                     }
                     g_n = w.g;
                     f = w.f;
+                };
+                if (far) {
+                    // no line opacity anywhere in the segment: each sub-node is the scattering
+                    // term alone, S+ = Jbar and sigma~ = dJ (sqrt 2 sq), linear in the sub-node
+                    // index like Jw and chi_s (r = 1 wherever chi_s > 0: at every sub-node when
+                    // either end has scattering, linear interpolation keeping it positive)
+                    const double on = (cs_cur > 0.0 || nd[i + 1].cs[gs] > 0.0) ? 1.0 : 0.0;
+                    const double Sp0 = (0.5 * on) * (ap + am), dSp = (0.5 * on * im) * (dap + dam);
+                    const double sq0 = (0.5 * kISq2 * on) * (am - ap), dsq = (0.5 * kISq2 * on * im) * (dam - dap);
+                    auto far_step = [&](int j, auto renorm_tag) {
+                        const double fj = (double)j;
+                        NodeVal v;
+                        v.chit = fma(fj, dcs, cs_cur);
+                        v.Sp = fma(fj, dSp, Sp0);
+                        v.sq = fma(fj, dsq, sq0);
+                        if (ANISO) {
+                            const double cm = fma(fj, dcm, cm_cur);
+                            const double jb = fma(fj * im, dap + dam, ap + am), dj = fma(fj * im, dam - dap, am - ap);
+                            const double rm = v.chit > 0.0 ? cm * rcp_refined(v.chit) : 0.0;
+                            v.Sp = fma(0.5 * rm, dj, v.Sp);
+                            v.sq = fma(0.5 * kISq2 * rm, jb, v.sq);
+                        }
+                        reframe<ANISO>(h, f);
+                        if (ANISO) f *= rho;
+                        step<decltype(renorm_tag)::value>(h, v, hz);
+                    };
+                    int j = 1;
+                    for (; j + 3 < m; j += 4) {
+                        far_step(j, std::false_type{});
+                        far_step(j + 1, std::false_type{});
+                        far_step(j + 2, std::false_type{});
+                        far_step(j + 3, std::true_type{});
+                    }
+                    for (; j < m; ++j) far_step(j, std::false_type{});
+                    g_n = 0.0;   // e^{-y_n^2} underflows too
+                    travel = 0.0;
+                } else if (clampJ) {
+                    sweep(std::true_type{});
+                } else {
+                    sweep(std::false_type{});
                 }
             }
             double jp, jm;
@@ -557,11 +633,12 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
     extern __shared__ double smem[];
     // lanes: with n_q <= 32 two lines per wave (lanes 32 g + frequency), else one line
     const int nq = a.n_q, t = threadIdx.x, nt = blockDim.x;
-    double *s_qx = smem;
-    SNode *nd = reinterpret_cast<SNode *>(smem + nq);
+    double *s_tab = smem;        // [16] 2^{j/16} for the exponential
+    double *s_qx = smem + 16;
+    SNode *nd = reinterpret_cast<SNode *>(smem + 16 + nq);
     SSeg *sgm = reinterpret_cast<SSeg *>(nd + kChunk);
     double *jr = reinterpret_cast<double *>(sgm + kChunk);   // [kChunk][per][n_q]
-    double *s_red = smem + nq;   // after the sweeps: [5][nt] over the staging area
+    double *s_red = smem + 16 + nq;   // after the sweeps: [5][nt] over the staging area
     const int per = nq <= 32 ? 2 : 1;
     const int groups = (a.n_lines + per - 1) / per;
     const int64_t O = blockIdx.x / groups;
@@ -578,6 +655,7 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
         return;
     }
     if (t < nq) s_qx[t] = a.qx[t];
+    if (t < 16) s_tab[t] = kExp2Sixteenths[t];
     __syncthreads();
     QGeo qg;
     qg.qx = s_qx;
@@ -607,8 +685,8 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
     for (int p = 0; p < a.n_pairs; ++p) {
         const int r = a.pair_r[p], rb = a.anti[r];
         HalfState f, b;
-        half<UNI, ANISO>(a, qg, nd, sgm, jr, per, O, cO, r, x, line0, g, I_in, xq_max, f);
-        half<UNI, ANISO>(a, qg, nd, sgm, jr, per, O, cO, rb, -x, line0, g, I_in, xq_max, b);
+        half<UNI, ANISO>(a, qg, s_tab, nd, sgm, jr, per, O, cO, r, x, act, line0, g, I_in, xq_max, f);
+        half<UNI, ANISO>(a, qg, s_tab, nd, sgm, jr, per, O, cO, rb, -x, act, line0, g, I_in, xq_max, b);
         // combine at O: h u + (Q_f u - y_f) + (Q_b u - y_b) = h R_O (scaled rows)
         const double idf = 1.0 / f.d, idb = 1.0 / b.d;
         const double h = f.Pm + b.Pm;
@@ -617,7 +695,7 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
         const double inv = 1.0 / (h + f.n * idf + b.n * idb);
         const double u = (h * f.Sp + yy + sgO) * inv;
         // line part of O's own source, for L* and Jeff (Eq. ALO)
-        const double clO = lcO.x * exp_le700(-(x * x));
+        const double clO = lcO.x * profile(x, s_tab);
         const double ratio = f.chit > 0.0 ? clO / f.chit : 1.0;   // all of it without opacity
         accJ += w * u;
         accL += w * (h * inv) * ratio;
@@ -683,7 +761,7 @@ hipError_t launch_formal_solve_scat(const ScatArgs &a, hipStream_t s)
     const int64_t groups = (a.n_lines + per - 1) / per;
     const size_t stage = kChunk * (sizeof(SNode) + sizeof(SSeg) + sizeof(double) * (size_t)per * a.n_q);
     const size_t red = 5 * sizeof(double) * (size_t)threads;
-    const size_t shmem = sizeof(double) * (size_t)a.n_q + (stage > red ? stage : red);
+    const size_t shmem = sizeof(double) * (16 + (size_t)a.n_q) + (stage > red ? stage : red);
     const dim3 grid((unsigned)(a.P * groups));
     if (a.chi_dip != nullptr) {
         if (a.q_uniform)
