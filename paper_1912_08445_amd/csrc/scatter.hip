@@ -213,7 +213,10 @@ __device__ __forceinline__ NodeVal node_val(double cl, double cs, double cm, dou
 {
     NodeVal v;
     v.chit = cl + cs;
-    const double ic = cs > 0.0 ? rcp_refined(v.chit) : 0.0;   // chit >= cs > 0
+    // 1/chit: the hardware estimate and one Newton step
+    double ic = __builtin_amdgcn_rcp(v.chit);
+    ic = fma(ic, fma(-v.chit, ic, 1.0), ic);
+    ic = cs > 0.0 ? ic : 0.0;   // chit >= cs > 0
     const double r = cs * ic;
     v.Sp = v.chit > 0.0 ? fma(0.5 * r, jp + jm, fma(-r, S, S)) : 0.0;
     v.sq = (0.5 * kISq2 * r) * (jm - jp);
