@@ -94,10 +94,14 @@ typedef struct {
                          to rounding.  -1 */
     int stage_nodes;  /* ray nodes a formal-solve wave stages in LDS at a time, 2..64 (0 = by
                          rule: the most that keep the register budget's occupancy).  0 */
+    int tile_points;  /* formal-solve work items (point, line block) a workgroup takes at a time,
+                         1..16 (0 = 1): the grid launch gives each workgroup that many
+                         consecutive items, the persistent launch takes that many from the
+                         queue per atomic.  Results do not depend on it.  0 */
 } nlte_params;
 
 /* Defaults listed above; max_iter 50, tol 1e-4, use_alo 1, precision FP64, profile 0, ng_every 0,
- * alo_band 0, long_segments -1, stage_nodes 0. */
+ * alo_band 0, long_segments -1, stage_nodes 0, tile_points 0. */
 void nlte_default_params(nlte_params *p);
 
 typedef struct {
@@ -393,10 +397,10 @@ nlte_status nlte_get_model_status(nlte_ctx *ctx, int32_t *iterations, uint8_t *c
 
 /* The formal-solve launch the current parameters resolve to (after the rules for the
  * choices left at 0 or -1): lines per lane, waves per SIMD of the register budget, long
- * segments (0/1), ray nodes staged per round, persistent (0/1); any pointer may be NULL.
- * Needs nlte_trace (the collapse rule reads the trace). */
+ * segments (0/1), ray nodes staged per round, persistent (0/1), work items per workgroup
+ * grab; any pointer may be NULL.  Needs nlte_trace (the collapse rule reads the trace). */
 nlte_status nlte_get_launch(nlte_ctx *ctx, int *lines_per_lane, int *waves_per_simd, int *long_segments,
-                            int *stage_nodes, int *persistent);
+                            int *stage_nodes, int *persistent, int *tile_points);
 
 /*
  * Time formal-solve launch choices on the current model with LTE populations and keep the

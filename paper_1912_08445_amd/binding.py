@@ -51,7 +51,8 @@ class Params(C.Structure):
                 ("max_iter", C.c_int), ("use_alo", C.c_int), ("precision", C.c_int),
                 ("profile", C.c_int), ("use_graph", C.c_int), ("lines_per_lane", C.c_int),
                 ("waves_per_simd", C.c_int), ("persistent", C.c_int), ("ng_every", C.c_int),
-                ("alo_band", C.c_int), ("long_segments", C.c_int), ("stage_nodes", C.c_int)]
+                ("alo_band", C.c_int), ("long_segments", C.c_int), ("stage_nodes", C.c_int),
+                ("tile_points", C.c_int)]
 
 
 class AliReport(C.Structure):
@@ -128,7 +129,7 @@ def load():
     L.nlte_run_ali_dev.argtypes = [vp, vp, vp, C.POINTER(AliReport), vp]
     L.nlte_get_model_status.argtypes = [vp, vp, vp, vp]
     L.nlte_autotune.argtypes = [vp, C.c_char_p, C.c_int, C.c_char_p, C.c_int]
-    L.nlte_get_launch.argtypes = [vp] + [C.POINTER(C.c_int)] * 5
+    L.nlte_get_launch.argtypes = [vp] + [C.POINTER(C.c_int)] * 6
     L.nlte_kernel_stats.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.nlte_reset_kernel_stats.argtypes = [vp]
     L.nlte_executed_steps.argtypes = [vp, C.POINTER(i64)]
@@ -438,10 +439,11 @@ class Solver:
 
     def launch(self):
         """The formal-solve launch the parameters resolve to: dict of lines_per_lane,
-        waves_per_simd, long_segments, stage_nodes, persistent."""
-        v = [C.c_int() for _ in range(5)]
+        waves_per_simd, long_segments, stage_nodes, persistent, tile_points."""
+        v = [C.c_int() for _ in range(6)]
         self._chk(self.L.nlte_get_launch(self.h, *[C.byref(x) for x in v]))
-        return dict(zip(("lines_per_lane", "waves_per_simd", "long_segments", "stage_nodes", "persistent"),
+        return dict(zip(("lines_per_lane", "waves_per_simd", "long_segments", "stage_nodes", "persistent",
+                         "tile_points"),
                         (x.value for x in v)))
 
     def autotune(self, cache_path=None, trials=3):
@@ -456,6 +458,7 @@ class Solver:
         self.params.long_segments = int(fields["long"])
         self.params.stage_nodes = int(fields["ns"])
         self.params.persistent = int(fields["persistent"])
+        self.params.tile_points = int(fields["tile"])
         return choice
 
     # ---------------------------------------------------------------- imaging

@@ -178,6 +178,7 @@ void set_launch_shape(nlte_ctx *c, SolveArgs &a, bool fp32)
     if (c->cfg.ns >= 2 && c->cfg.ns <= kWave) ns = c->cfg.ns;
     a.ns = ns;
     a.persistent = c->cfg.persistent;
+    a.tile = (c->cfg.tile >= 1 && c->cfg.tile <= 16) ? c->cfg.tile : 1;
 }
 
 SolveArgs solve_args(nlte_ctx *c, double *J, double *Jeff, double *L)
@@ -578,6 +579,7 @@ nlte_status formal_solve_band_impl(nlte_ctx *c, const double *d_pops, double *d_
         set_launch_shape(c, a, false);
         c->cfg = keep;
         a.persistent = 0;
+        a.tile = 1;
     }
     if (ali) a.model_done = c->d_model_done;
     a.Jb = c->d_Jb;
@@ -839,6 +841,7 @@ void nlte_default_params(nlte_params *p)
     p->waves_per_simd = 0;
     p->long_segments = -1;
     p->stage_nodes = 0;
+    p->tile_points = 0;
     p->persistent = 0;
     p->ng_every = 0;
     p->alo_band = 0;
@@ -1340,18 +1343,20 @@ nlte_status nlte_set_params(nlte_ctx *c, const nlte_params *p)
         p->max_iter > 100000 || (p->precision != NLTE_PREC_FP64 && p->precision != NLTE_PREC_FP32_BULK) ||
         p->lines_per_lane < 0 || p->lines_per_lane > kMaxLpl || p->waves_per_simd < 0 ||
         p->waves_per_simd > 3 || p->long_segments < -1 || p->long_segments > 1 ||
-        !(p->stage_nodes == 0 || (p->stage_nodes >= 2 && p->stage_nodes <= kWave)) ||
+        !(p->stage_nodes == 0 || (p->stage_nodes >= 2 && p->stage_nodes <= kWave)) || p->tile_points < 0 ||
+        p->tile_points > 16 ||
         !(p->ng_every == 0 || (p->ng_every >= 3 && p->ng_every <= kNgMaxM)) ||
         !(p->alo_band == 0 || (p->alo_band == 1 && p->use_alo)))
         return fail(c, NLTE_E_INVALID_ARG,
                     "parameter out of range (lines_per_lane: 0..5; waves_per_simd: 0..3; long_segments: -1..1; "
-                    "stage_nodes: 0 or 2..64; ng_every: 0 or 3..8; "
+                    "stage_nodes: 0 or 2..64; tile_points: 0..16; ng_every: 0 or 3..8; "
                     "alo_band: 0, or 1 with use_alo)");
     c->params = *p;
     c->cfg.lpl = p->lines_per_lane;
     c->cfg.waves = p->waves_per_simd;
     c->cfg.long_seg = p->long_segments;
     c->cfg.ns = p->stage_nodes;
+    c->cfg.tile = p->tile_points;
     c->cfg.persistent = p->persistent ? 1 : 0;
     drop_graphs(c);
     return upload_ibdy(c);
@@ -1787,16 +1792,17 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
             char line[1024];
             while (fgets(line, sizeof line, f)) {
                 char k2[512];
-                int lpl, wv, far, ns, pe;
+                int lpl, wv, far, ns, pe, tl;
                 double ms;
-                if (sscanf(line, "%511s lpl=%d waves=%d long=%d ns=%d persistent=%d ms=%lf", k2, &lpl, &wv, &far, &ns,
-                           &pe, &ms) == 7 &&
+                if (sscanf(line, "%511s lpl=%d waves=%d long=%d ns=%d persistent=%d tile=%d ms=%lf", k2, &lpl, &wv,
+                           &far, &ns, &pe, &tl, &ms) == 8 &&
                     strcmp(k2, key) == 0) {
                     best.lpl = lpl;
                     best.waves = wv;
                     best.long_seg = far;
                     best.ns = ns;
                     best.persistent = pe;
+                    best.tile = tl;
                     best_ms = ms;
                     cached = true;
                 }
@@ -1816,6 +1822,7 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
         cur.waves = a0.waves;
         cur.long_seg = a0.collapse;
         cur.ns = a0.ns;
+        cur.tile = a0.tile;
         auto restore = [&](nlte_status code) {
             c->cfg = saved;
             c->params.profile = saved_profile;
@@ -1824,7 +1831,7 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
         if ((st = time_choice(c, cur, trials, &best_ms))) return restore(st);
         best = cur;
         const int lpl_cap = std::min(kMaxLpl, (c->n_lines + a0.ngrp - 1) / a0.ngrp);
-        for (int dim = 0; dim < 5; ++dim) {
+        for (int dim = 0; dim < 6; ++dim) {
             std::vector<int> cand;
             if (dim == 0)
                 for (int v = 1; v <= lpl_cap; ++v) cand.push_back(v);
@@ -1834,12 +1841,18 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
                 cand = {0, 1};
             else if (dim == 3)
                 cand = {16, 32, 48, 64};
-            else
+            else if (dim == 4)
                 cand = {0, 1};
+            else
+                cand = {1, 2, 4, 8};
             for (int v : cand) {
                 SolveConfig k = best;
-                int *field = dim == 0 ? &k.lpl : dim == 1 ? &k.waves : dim == 2 ? &k.long_seg : dim == 3 ? &k.ns
-                                                                                                     : &k.persistent;
+                int *field = dim == 0   ? &k.lpl
+                             : dim == 1 ? &k.waves
+                             : dim == 2 ? &k.long_seg
+                             : dim == 3 ? &k.ns
+                             : dim == 4 ? &k.persistent
+                                        : &k.tile;
                 if (*field == v) continue;
                 *field = v;
                 if (dim == 0) k.ns = 0;   // a new line count takes the rule's staging depth
@@ -1860,8 +1873,8 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
         if (cache_path) {
             FILE *f = fopen(cache_path, "a");
             if (f) {
-                fprintf(f, "%s lpl=%d waves=%d long=%d ns=%d persistent=%d ms=%.4f\n", key, best.lpl, best.waves,
-                        best.long_seg, best.ns, best.persistent, best_ms);
+                fprintf(f, "%s lpl=%d waves=%d long=%d ns=%d persistent=%d tile=%d ms=%.4f\n", key, best.lpl,
+                        best.waves, best.long_seg, best.ns, best.persistent, best.tile, best_ms);
                 fclose(f);
             }
         }
@@ -1871,20 +1884,22 @@ nlte_status nlte_autotune(nlte_ctx *c, const char *cache_path, int trials, char 
     c->cfg.long_seg = best.long_seg;
     c->cfg.ns = best.ns;
     c->cfg.persistent = best.persistent;
+    c->cfg.tile = best.tile;
     c->params.lines_per_lane = best.lpl;
     c->params.waves_per_simd = best.waves;
     c->params.long_segments = best.long_seg;
     c->params.stage_nodes = best.ns;
     c->params.persistent = best.persistent;
+    c->params.tile_points = best.tile;
     drop_graphs(c);
     if (choice && cap > 0)
-        snprintf(choice, cap, "lpl=%d waves=%d long=%d ns=%d persistent=%d ms=%.4f%s", best.lpl, best.waves,
-                 best.long_seg, best.ns, best.persistent, best_ms, cached ? " (cached)" : "");
+        snprintf(choice, cap, "lpl=%d waves=%d long=%d ns=%d persistent=%d tile=%d ms=%.4f%s", best.lpl, best.waves,
+                 best.long_seg, best.ns, best.persistent, best.tile, best_ms, cached ? " (cached)" : "");
     return NLTE_OK;
 }
 
 nlte_status nlte_get_launch(nlte_ctx *c, int *lines_per_lane, int *waves_per_simd, int *long_segments, int *stage_nodes,
-                            int *persistent)
+                            int *persistent, int *tile_points)
 {
     nlte_status st = need(c, true);
     if (st) return st;
@@ -1894,6 +1909,7 @@ nlte_status nlte_get_launch(nlte_ctx *c, int *lines_per_lane, int *waves_per_sim
     if (long_segments) *long_segments = a.collapse;
     if (stage_nodes) *stage_nodes = a.ns;
     if (persistent) *persistent = a.persistent;
+    if (tile_points) *tile_points = a.tile;
     return NLTE_OK;
 }
 

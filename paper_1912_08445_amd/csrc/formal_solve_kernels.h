@@ -638,13 +638,14 @@ constexpr size_t fs_lds_bytes(int ns)
     return fs_rows_bytes<F32, LPL>() + (size_t)ns * sizeof(NodeRec<typename Bulk<F32>::T, 2 * LPL>);
 }
 
-// One workgroup per (point, line block), or (a.persistent) a fixed grid of workgroups that
-// take items from an atomic counter in the order a.order gives (points by decreasing
-// cached step count, so the longest items start first and the tail is short); every
-// workgroup leaves the loop once the counter has passed the last item.  In the grid form
-// consecutive hardware workgroups go round-robin to the 8 XCDs and each XCD gets a
-// contiguous range of origin points, so that the cells their rays share stay in that
-// XCD's L2.  W: waves per SIMD the register budget is built for.
+// Work items are (point, line block); a workgroup takes a.tile consecutive items at a time.
+// Grid form: one workgroup per tile of items; consecutive hardware workgroups go
+// round-robin to the 8 XCDs and each XCD gets a contiguous range of origin points, so
+// that the cells their rays share stay in that XCD's L2.  Persistent form (a.persistent):
+// a fixed grid of workgroups takes tiles from an atomic counter in the order a.order gives
+// (points by decreasing cached step count, so the longest items start first and the tail
+// is short); every workgroup leaves the loop once the counter has passed the last item.
+// W: waves per SIMD the register budget is built for.
 template <bool F32, int LPL, int W, bool COLLAPSE>
 __global__ __launch_bounds__(64, W) void k_formal_solve(SolveArgs a)
 {
@@ -658,25 +659,31 @@ __global__ __launch_bounds__(64, W) void k_formal_solve(SolveArgs a)
     }
     // one call site for both forms (the sweep is compiled once): a grid workgroup takes
     // its own item and stops
+    // a workgroup takes a.tile consecutive items at a time
     __shared__ unsigned long long item_s;
-    int64_t item;
+    const int64_t tile = a.tile;
+    int64_t first;
     if (a.persistent) {
-        if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1ull);
+        if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, (unsigned long long)tile);
         __syncthreads();
-        item = (int64_t)item_s;
+        first = (int64_t)item_s;
     } else {
-        const int64_t nb8 = (a.n_blocks + 7) / 8;
-        item = (int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
+        const int64_t n_tiles = (a.n_blocks + tile - 1) / tile;
+        const int64_t nb8 = (n_tiles + 7) / 8;
+        first = ((int64_t)(blockIdx.x & 7) * nb8 + (blockIdx.x >> 3)) * tile;
     }
-    while (item < a.n_blocks) {
-        const int64_t rank = item / a.groups;
-        const int64_t O = a.persistent ? (int64_t)a.order[rank] : rank;
-        solve_item<F32, LPL, COLLAPSE>(a, O, (int)(item - rank * a.groups), rec, red, tab);
+    while (first < a.n_blocks) {
+        const int64_t last = first + tile < a.n_blocks ? first + tile : a.n_blocks;
+        for (int64_t item = first; item < last; ++item) {
+            const int64_t rank = item / a.groups;
+            const int64_t O = a.persistent ? (int64_t)a.order[rank] : rank;
+            solve_item<F32, LPL, COLLAPSE>(a, O, (int)(item - rank * a.groups), rec, red, tab);
+        }
         if (!a.persistent) break;
         __syncthreads();
-        if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, 1ull);
+        if (threadIdx.x == 0) item_s = atomicAdd(a.work_counter, (unsigned long long)tile);
         __syncthreads();
-        item = (int64_t)item_s;
+        first = (int64_t)item_s;
     }
 }
 
@@ -684,7 +691,8 @@ template <bool F32, int LPL, int W, bool COLLAPSE>
 hipError_t launch_fs_variant(const SolveArgs &a, int n_wg, hipStream_t s)
 {
     const size_t lds = fs_lds_bytes<F32, LPL>(a.ns);
-    const unsigned grid = a.persistent ? (unsigned)n_wg : (unsigned)(((a.n_blocks + 7) / 8) * 8);
+    const int64_t n_tiles = (a.n_blocks + a.tile - 1) / a.tile;
+    const unsigned grid = a.persistent ? (unsigned)n_wg : (unsigned)(((n_tiles + 7) / 8) * 8);
     hipLaunchKernelGGL((k_formal_solve<F32, LPL, W, COLLAPSE>), dim3(grid), dim3(kWave), lds, s, a);
     return hipGetLastError();
 }

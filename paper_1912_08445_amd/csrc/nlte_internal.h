@@ -82,6 +82,7 @@ struct SolveArgs {
     int waves;               // register budget of the launch: 2 or 3 waves per SIMD
     int collapse;            // 1: long-segment mode (profile recurrence, far-wing collapse)
     int persistent;          // 1: items from the work counter in decreasing-cost order
+    int tile;                // work items a workgroup takes at a time (1..16)
     int64_t n_blocks;        // work items (P * groups)
     double *J, *Jeff, *L;    // [P][n_lines]
     double *Jb, *Ld;         // band operator: J without the band's share, its diagonal [P][n_lines]
@@ -174,6 +175,7 @@ struct SolveConfig {
     int long_seg = -1;        // long-segment mode: 1 on, 0 off, -1 by the trace's steps per cell
     int ns = 0;               // ray nodes staged per round (2..64; 0 = by rule)
     int persistent = 0;       // 1: work-queue kernel in decreasing-cost order
+    int tile = 0;             // work items per workgroup grab (1..16; 0 = 1)
     int n_wg = 0;             // workgroups of the persistent kernel
 };
 

@@ -33,7 +33,7 @@ def _config(seed):
     w.f_sub = float(rng.choice([0.1, 0.25, 0.5]))
     launch = dict(lines_per_lane=int(rng.choice([0, 1, 2, 3, 4, 5])), waves_per_simd=int(rng.integers(0, 4)),
                   persistent=int(rng.integers(0, 2)), long_segments=int(rng.integers(-1, 2)),
-                  stage_nodes=int(rng.choice([0, 2, 9, 24, 64])))
+                  stage_nodes=int(rng.choice([0, 2, 9, 24, 64])), tile_points=int(rng.choice([0, 1, 2, 5, 16])))
     desc = f"seed {seed}: {w.name} n={n} lev={nlev} q={q} rays={w.rays.shape[0]} f_sub={w.f_sub} {launch}"
     return w, launch, desc, rng
 
