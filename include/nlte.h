@@ -206,7 +206,10 @@ nlte_status nlte_set_params(nlte_ctx *ctx, const nlte_params *p);
 nlte_status nlte_trace(nlte_ctx *ctx);
 
 /* Cells met by ray `ray` from global point `point`, nearest first.  Copies up to cap
- * indices (model-local, like nbr) into cells; *len receives the full length. */
+ * indices (model-local, like nbr) into cells; *len receives the full length.  The velocity
+ * sub-step counts of the segments between them (Sec. 3.2) are not part of the cache: every
+ * sweep recomputes them from the cell records (the same FP64 decision as the walk's), so
+ * there is no per-segment count to return; nlte_get_point_cost gives their sum per point. */
 nlte_status nlte_get_ray(nlte_ctx *ctx, int64_t point, int ray, int32_t *cells, int cap,
                          int *len);
 
