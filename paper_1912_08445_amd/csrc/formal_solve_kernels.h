@@ -315,13 +315,16 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                 Sn[l] = rec[i + 1].S[grp * LPL + l];
                 a_prev[l] = (ls.k_cur[l] * g_cur) * dzq;
             }
-            if (COLLAPSE && !TRACK && m > 1) {
+            if (COLLAPSE && m > 1) {
                 // Far wing: every lane beyond the range of its profile (exactly 0 past
                 // x^2 = 750 in FP64, 105 in FP32) at both ends of the segment, on one side
                 // of the line centre, and zero opacity at its first node.  Then every node of
                 // the segment has zero opacity, the elimination steps after the first change
                 // nothing, and one step with zero opacity and the end node's source leaves
-                // the same state.  (A segment without sub-steps is one step anyway.)
+                // the same state.  (A segment without sub-steps is one step anyway.)  The
+                // band operator's record of the last step: its weight is 0 (zero optical
+                // depth on both sides of the last sub-step node), so that node's source does
+                // not enter the neighbour entry.
                 const T far2 = F32 ? (T)105 : (T)750;
                 bool far = ((x_cur > (T)0) == (xn > (T)0)) && x_cur * x_cur > far2 && xn * xn > far2;
 #pragma unroll
@@ -331,7 +334,12 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                     for (int l = 0; l < LPL; ++l) {
                         elim_step<F32, false, TRACK>((T)0, Sn[l], a_prev[l], ls.S_e[l], ls.st[l]);
                         ls.k_cur[l] = kn[l];
+                        if (TRACK) {
+                            ls.st[l].hd = 0.0;
+                            ls.st[l].Sl = 0.0;
+                        }
                     }
+                    if (TRACK) ls.m_last = m;
                     rescale_if_big<LPL, TRACK>(ls);
                     x_cur = xn;
                     g_cur = (T)0;

@@ -22,8 +22,8 @@ size_t formal_solve_lds_f64(int lpl, int ns)
 
 // Band-operator variant of the grid kernel: also the entries of the inverse system matrix
 // between O and its neighbour nodes (Jb, Ld, Ln of SolveArgs).  LONG: the long-segment
-// profile recurrence (far-wing segments are never collapsed here: the band operator reads
-// the last step of each half sweep).
+// mode, profile recurrence and far-wing collapse (a collapsed last segment records a last
+// step of weight 0, as its zero-opacity sub-steps would).
 template <int LPL, bool LONG>
 __global__ __launch_bounds__(64, 2) void k_formal_solve_band(SolveArgs a)
 {
