@@ -234,7 +234,8 @@ __device__ __forceinline__ double profile(double y, const double *tab) { return 
 
 // Elimination state of a half sweep and the last node reached (chit, Sp, sq), with sq_pp
 // and Sp_pp the sq and Sp of the node before it (virtual -sq, -Sp at the far end); y is
-// the particular solution of the u-equation, yv that of the v-equation.
+// the particular solution of the u-equation, yv that of the v-equation divided by sqrt 2
+// (which leaves a factor 1/2 as its only constant).
 struct HalfState {
     double n, d, y, yv, Pm;
     double chit, Sp, sq, sq_pp, Sp_pp;
@@ -245,7 +246,7 @@ __device__ __forceinline__ void start(HalfState &h, const NodeVal &first, double
     h.n = kSq2;
     h.d = 1.0;
     h.y = kSq2 * I_in;
-    h.yv = kSq2 * I_in;
+    h.yv = I_in;
     h.Pm = 0.0;
     h.chit = first.chit;
     h.Sp = first.Sp;
@@ -269,16 +270,16 @@ __device__ __forceinline__ void reframe(HalfState &h, double f)
     }
 }
 
-// Eliminate the last node, stepping to node v over a sub-interval of weight hz.
+// Eliminate the last node, stepping to node v over a sub-interval with optical-depth
+// weight P (the trapezoid chi dz / sqrt 2).
 template <bool RENORM>
-__device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
+__device__ __forceinline__ void step_p(HalfState &h, const NodeVal &v, double P)
 {
-    const double P = (h.chit + v.chit) * hz;
     const double hd = (h.Pm + P) * h.d;
     h.n += hd;
     h.y = fma(h.sq_pp - v.sq, h.d, fma(h.Sp, hd, h.y));   // y + S+ h d - (sigma~ - sigma~_pp) d / sqrt 2
-    // yv + sigma~ h d - (S+ - S+_pp) d / sqrt 2
-    h.yv = fma((h.Sp_pp - v.Sp) * kISq2, h.d, fma(kSq2 * h.sq, hd, h.yv));
+    // (yv + sigma~ h d - (S+ - S+_pp) d / sqrt 2) / sqrt 2
+    h.yv = fma((h.Sp_pp - v.Sp) * 0.5, h.d, fma(h.sq, hd, h.yv));
     h.d = fma(P, h.n, h.d);
     h.Pm = P;
     h.sq_pp = h.sq;
@@ -293,6 +294,13 @@ __device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
         h.y = ldexp(h.y, -ex);
         h.yv = ldexp(h.yv, -ex);
     }
+}
+
+// The same over a sub-interval of weight hz per unit of the two nodes' total opacities.
+template <bool RENORM>
+__device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
+{
+    step_p<RENORM>(h, v, (h.chit + v.chit) * hz);
 }
 
 // Running values of a lane inside a recurrence segment (pos: the lookup position; f: the
@@ -449,6 +457,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
             const double y_n = nd[i + 1].a * x - nd[i + 1].b;
             double g_n;
             double f = ANISO ? sgm[i].f0[gs] : 1.0;   // frame factor of the next sub-interval
+            int end_lookup = -1;   // >= 0: the end node's lookups clamp (+y at this row index)
             if (m == 1) {
                 g_n = profile(y_n, tab);
                 travel = 0.0;
@@ -470,6 +479,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                     clampJ = (y_cur >= hi && y_n >= hi) || (y_cur <= lo && y_n <= lo);
                 }
                 clampJ = __all(clampJ || !live);   // (lanes without a frequency do not vote)
+                if (clampJ) end_lookup = y_cur > 0.0 ? qg.nq - 1 : 0;
                 // (lookup of +y at ep, of -y at em; the rows' end values and their changes over t)
                 const int ep = y_cur > 0.0 ? qg.nq - 1 : 0, em = qg.nq - 1 - ep;
                 const double ap = row_cur[ep], am = row_cur[em];
@@ -579,6 +589,8 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                     const double on = (cs_cur > 0.0 || nd[i + 1].cs[gs] > 0.0) ? 1.0 : 0.0;
                     const double Sp0 = (0.5 * on) * (ap + am), dSp = (0.5 * on * im) * (dap + dam);
                     const double sq0 = (0.5 * kISq2 * on) * (am - ap), dsq = (0.5 * kISq2 * on * im) * (dam - dap);
+                    // the sub-interval ending at sub-node j has P = (chi_{j-1} + chi_j) hz, linear in j
+                    const double dP = 2.0 * dcs * hz, P0 = (2.0 * cs_cur - dcs) * hz;
                     auto far_step = [&](int j, auto renorm_tag) {
                         const double fj = (double)j;
                         NodeVal v;
@@ -594,7 +606,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                         }
                         reframe<ANISO>(h, f);
                         if (ANISO) f *= rho;
-                        step<decltype(renorm_tag)::value>(h, v, hz);
+                        step_p<decltype(renorm_tag)::value>(h, v, fma(fj, dP, P0));
                     };
                     int j = 1;
                     for (; j + 3 < m; j += 4) {
@@ -613,7 +625,12 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                 }
             }
             double jp, jm;
-            j_node<UNI>(qg, row_n, qpos<UNI>(qg, y_n), jp, jm);
+            if (end_lookup >= 0) {
+                jp = row_n[end_lookup];
+                jm = row_n[qg.nq - 1 - end_lookup];
+            } else {
+                j_node<UNI>(qg, row_n, qpos<UNI>(qg, y_n), jp, jm);
+            }
             const NodeVal vn = node_val<ANISO>(kap_n * g_n, cs_n, cm_n, S_n, jp, jm);
             reframe<ANISO>(h, f);
             step<true>(h, vn, hz);
@@ -707,7 +724,7 @@ __global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
         // v along n = ray r, the sweep direction of half b, from the v-equation: the same
         // combine with b's particular solution and f's with the sign of the other
         // orientation, sigma~_O (b's) in place of S+_O and the S+ difference across O
-        const double v = (h * kSq2 * b.sq + (b.yv * idb - f.yv * idf) + (b.Sp_pp - f.Sp_pp) * kISq2) * inv;
+        const double v = kSq2 * ((h * b.sq + (b.yv * idb - f.yv * idf) + (b.Sp_pp - f.Sp_pp) * 0.5) * inv);
         double wp = 1.0, wm = 1.0;
         if (ANISO) {
             const double en = (ex * a.dir[3 * r] + ey * a.dir[3 * r + 1]) + ez * a.dir[3 * r + 2];
