@@ -61,3 +61,28 @@ def test_scattering_full_size_sampled(outflow):
     assert np.all(np.isfinite(Jn))
     assert rel((Jn * np.asarray(w.quad_w)[None, None, :]).sum(axis=2), J).max() <= 1e-12
     s.set_scattering(None)
+
+
+def test_scattering_dipole_full_size_sampled(outflow):
+    """The full outflow with a scattering opacity that differs by direction (dipoles up to
+    the whole opacity): sampled origins against the oracle, every point finite."""
+    w, s, o = outflow
+    pops = s.lte()
+    nd = o.pair_nodes(pops, 0, 0)
+    rng = np.random.default_rng(16)
+    chi = np.median(nd["kappa"], axis=0)[None, :] * rng.uniform(0.2, 2.0, (w.n_points, w.species.n_lines))
+    d = rng.normal(size=(w.n_points, w.species.n_lines, 3))
+    d *= (chi * rng.uniform(0.0, 1.0, chi.shape) / np.linalg.norm(d, axis=2))[:, :, None]
+    Jnu = o.scattering_start() * rng.uniform(0.5, 2.0, (w.n_points, w.species.n_lines, 1))
+    s.set_scattering(chi)
+    s.set_scattering_dipole(d)
+    J, Je, L, Jn = s.formal_solve_scat(pops, Jnu)
+    print("scattering sweep done", flush=True)
+    sel = np.random.default_rng(17).choice(w.n_points, 3, replace=False)
+    rJ, rJe, rL, rJn = o.formal_solve_scat(pops, chi, Jnu, sel=sel, chi_dip=d)
+    print("oracle done", flush=True)
+    assert rel(J[sel], rJ).max() <= 1e-9 and rel(L[sel], rL).max() <= 1e-9
+    assert (np.abs(Je[sel] - rJe) / rJ).max() <= 1e-9
+    assert rel(Jn[sel], rJn).max() <= 1e-9
+    assert np.all(np.isfinite(Jn)) and np.all(np.isfinite(J))
+    s.set_scattering(None)

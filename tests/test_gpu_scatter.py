@@ -249,3 +249,26 @@ def test_dipole_argument_checks():
     d[5, 0] = [0.0, 0.0, 1e-18]             # exactly the full opacity along z
     s.set_scattering_dipole(d)
     s.set_scattering_dipole(None)
+
+
+def test_dipole_ali_is_per_model_in_a_batch():
+    ws = [configs.outflow5(n_points=n, seed=sd, nside=1) for n, sd in ((150, 31), (220, 32))]
+    offs, merged = concat_models([w.model for w in ws])
+    wb = configs.outflow5(n_points=10, nside=1)
+    wb.model, wb.offsets = merged, offs
+    chis = [_fields(oracle_for(w), w, 33 + m)[1] for m, w in enumerate(ws)]
+    dips = [_dipole(w, c, 35 + m) for m, (w, c) in enumerate(zip(ws, chis))]
+    sb = solver_for(wb, max_iter=40, tol=1e-6)
+    sb.set_scattering(np.concatenate(chis))
+    sb.set_scattering_dipole(np.concatenate(dips))
+    pb, _ = sb.run_ali()
+    its, conv, _ = sb.model_status()
+    jb = sb.scattering_field()
+    for m, w in enumerate(ws):
+        s = solver_for(w, max_iter=40, tol=1e-6)
+        s.set_scattering(chis[m])
+        s.set_scattering_dipole(dips[m])
+        ps, rs = s.run_ali()
+        assert its[m] == rs["iterations"]
+        assert rel(pb[offs[m]:offs[m + 1]], ps).max() <= 1e-13
+        assert rel(jb[offs[m]:offs[m + 1]], s.scattering_field()).max() <= 1e-13
