@@ -170,7 +170,7 @@ __device__ __forceinline__ void recur_step(double &g, double &r, double c, doubl
 // COLLAPSE: eliminate far-wing sub-step segments in one step (see below).
 template <bool F32, int LPL, bool COLLAPSE, bool TRACK = false>
 __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename Bulk<F32>::T, 2 * LPL> *rec,
-                                          const double *tab, int64_t O, const CellRec &cO, int ray,
+                                          const double *tab, int64_t O, int ray,
                                           typename Bulk<F32>::T xq, int grp, int line0, int nlw,
                                           LineState<typename Bulk<F32>::T, LPL> &ls, int64_t &nexec)
 {
@@ -198,7 +198,6 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
     const int64_t beg = a.roff[base];
     const int L = (int)(a.roff[base + 1] - beg);
     if (L == 0) return;
-    const double nx = a.dir[3 * ray], ny = a.dir[3 * ray + 1], nz = a.dir[3 * ray + 2];
     // x_cur, g_cur: Doppler offset and profile at the current node; travel bounds how far
     // x moved (any lane) since g was last evaluated exactly
     T x_cur = 0, g_cur = 0;
@@ -213,6 +212,11 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
         if (load) {
             cidx = (s < L) ? (int64_t)a.rcells[beg + (L - 1 - s)] : O;
             const CellRec c = a.cell[cidx];
+            // O's record and the ray's direction are read again for each staging round (from
+            // the caches) rather than held in registers through the sweep
+            reload_fence();
+            const CellRec cO = a.cell[O];
+            const double nx = a.dir[3 * ray], ny = a.dir[3 * ray + 1], nz = a.dir[3 * ray + 2];
             double dx = c.px - cO.px, dy = c.py - cO.py, dz = c.pz - cO.pz;
             Zs = (dx * nx + dy * ny) + dz * nz;
             double dvx = c.vx - cO.vx, dvy = c.vy - cO.vy, dvz = c.vz - cO.vz;
@@ -493,7 +497,6 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
     const int grp = ngrp == 2 ? lane >> 5 : 0;
     const int sub = lane & (width - 1);           // lane within its group
     const T2 *lc = reinterpret_cast<const T2 *>(a.lc);
-    const CellRec cO = a.cell[O];
     bool lact[LPL];
 #pragma unroll
     for (int l = 0; l < LPL; ++l) lact[l] = grp * LPL + l < nlw;
@@ -519,7 +522,7 @@ __device__ __forceinline__ void solve_item(const SolveArgs &a, int64_t O, int w,
             // the two halves (unrolled: measured faster than one compiled sweep in a loop)
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
-                half_sweep<F32, LPL, COLLAPSE, BAND>(a, rec, tab, O, cO, half ? rb : r, (T)(half ? -xq : xq), grp,
+                half_sweep<F32, LPL, COLLAPSE, BAND>(a, rec, tab, O, half ? rb : r, (T)(half ? -xq : xq), grp,
                                                      line0, nlw, ls, nex);
                 if (half) break;
                 if (BAND) mf = ls.m_last;
