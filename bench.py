@@ -559,15 +559,19 @@ def main():
                     help="skip the Ng, band-ALO and scattering ALI forms and the image timing")
     ap.add_argument("--train-models", type=int, default=None,
                     help="other seeds of the workload (of the disc family for disc10) whose converged "
-                         "populations train the warm start (0: no warm start; default 48 for discs, else 8)")
-    ap.add_argument("--train-sample", type=int, default=20000,
-                    help="rows taken from each training model")
+                         "populations train the warm start (0: no warm start; default 20 for disc10, "
+                         "48 for discs, else 8)")
+    ap.add_argument("--train-sample", type=int, default=None,
+                    help="rows taken from each training model (default: every point of the disc family's "
+                         "training discs for disc10, else 20000)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (4 launches), "
                          "the calibration kernel for HBM byte counters")
     args = ap.parse_args()
     if args.train_models is None:
-        args.train_models = 48 if args.workload == "discs" else 8
+        args.train_models = {"discs": 48, "disc10": 20}.get(args.workload, 8)
+    if args.train_sample is None:
+        args.train_sample = args.disc_points if args.workload == "disc10" else 20000
     if args.ali_runs is None:
         args.ali_runs = 1 if args.workload == "disc10" else 3
     if args.workload == "disc10":
