@@ -164,6 +164,59 @@ __device__ __forceinline__ void recur_step(double &g, double &r, double c, doubl
     }
 }
 
+// The elimination step of elim_step with the segment's P = D_+ / sqrt 2 given and the
+// source S_row of the row being eliminated; nothing is carried to the next step but the
+// state (the lean form of the sweeps without the band operator's record).
+__device__ __forceinline__ void elim_p(double Pp, double S_row, HalfState &st)
+{
+    const double hd = (st.Hm + Pp) * st.D;
+    st.N = st.N + hd;
+    st.Y = fma(S_row, hd, st.Y);
+    st.D = fma(Pp, st.N, st.D);
+    st.Hm = Pp;
+}
+
+// One segment without sub-steps, to staged node r1 (the segment's dzq given): the
+// profile g1 of this lane at r1, r1's kappa and S of the lane's lines (k1, S1), and every
+// line's step with P = (kappa_0 g0 + kappa_1 g1) dzq and the row source S0 (in FP32 formed
+// as the general path forms it, so that both segment modes give the same bits).  A loop over
+// segments that calls this twice per iteration with the (g, k, S) sets swapped copies no
+// registers between segments.
+template <bool F32, int LPL>
+__device__ __forceinline__ void short_node(const NodeRec<typename Bulk<F32>::T, 2 * LPL> &r1,
+                                           typename Bulk<F32>::T dzq, typename Bulk<F32>::T xq,
+                                           const double *tab, int grp, typename Bulk<F32>::T g0,
+                                           typename Bulk<F32>::T &g1, const typename Bulk<F32>::T (&k0)[LPL],
+                                           typename Bulk<F32>::T (&k1)[LPL], const typename Bulk<F32>::T (&S0)[LPL],
+                                           typename Bulk<F32>::T (&S1)[LPL], LineState<typename Bulk<F32>::T, LPL> &ls)
+{
+    using T = typename Bulk<F32>::T;
+    const T xn = r1.a * xq - r1.b;
+    g1 = profile_far(xn, tab);
+#pragma unroll
+    for (int l = 0; l < LPL; ++l) {
+        const int c = grp * LPL + l;
+        k1[l] = r1.kap[c];
+        S1[l] = r1.S[c];
+        T Pp;
+        if constexpr (F32)
+            Pp = (k0[l] * g0) * dzq + (k1[l] * g1) * dzq;   // as the general path forms it, bit for bit
+        else
+            Pp = fma(k0[l], g0, k1[l] * g1) * dzq;
+        elim_p((double)Pp, (double)S0[l], ls.st[l]);
+    }
+    rescale_if_big<LPL, false>(ls);
+}
+
+// Runs of segments without sub-steps take the loop of short_node (not in the long-segment
+// mode, whose far-wing collapse measured faster without it).
+template <bool F32, bool COLLAPSE>
+constexpr bool SHORT_LOOP = !COLLAPSE;
+// Sub-step segments: the form of the loop that alternates two sets of optical depths
+// (LEAN) or the one that carries a_prev and S_e through elim_step.
+template <bool F32, bool COLLAPSE>
+constexpr bool LEAN_SUBSTEPS = true;
+
 // Half-sweep along ray `ray` from its far end to O for Doppler offset xq of this lane.
 // The result is left in ls.st (one HalfState per line of the lane).  nexec counts the
 // elimination steps the wave executes (a collapsed far-wing segment counts as one).
@@ -279,7 +332,46 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
             }
         }
         for (int i = 0; i < nseg; ++i) {
-            if (!F32 && !COLLAPSE && rec[i].m == 1) {
+            if (!TRACK && SHORT_LOOP<F32, COLLAPSE> && rec[i].m == 1) {
+                // a run of segments without sub-steps (most of a disc's rays): one profile
+                // evaluation per node and one step per line (short_node), two segments per
+                // iteration so that the node values alternate between the A and B sets
+                T gA = g_cur, gB = 0;
+                T kA[LPL], kB[LPL], SA[LPL], SB[LPL];
+#pragma unroll
+                for (int l = 0; l < LPL; ++l) {
+                    kA[l] = ls.k_cur[l];
+                    SA[l] = ls.S_e[l];
+                }
+                for (;;) {
+                    short_node<F32, LPL>(rec[i + 1], rec[i].dzq, xq, tab, grp, gA, gB, kA, kB, SA, SB, ls);
+                    ++nexec;
+                    ++i;
+                    if (i >= nseg || rec[i].m != 1) {
+                        gA = gB;
+#pragma unroll
+                        for (int l = 0; l < LPL; ++l) {
+                            kA[l] = kB[l];
+                            SA[l] = SB[l];
+                        }
+                        break;
+                    }
+                    short_node<F32, LPL>(rec[i + 1], rec[i].dzq, xq, tab, grp, gB, gA, kB, kA, SB, SA, ls);
+                    ++nexec;
+                    ++i;
+                    if (i >= nseg || rec[i].m != 1) break;
+                }
+                g_cur = gA;
+                x_cur = rec[i].a * xq - rec[i].b;   // the same bits as the last xn
+#pragma unroll
+                for (int l = 0; l < LPL; ++l) {
+                    ls.k_cur[l] = kA[l];
+                    ls.S_e[l] = SA[l];
+                }
+                travel = 0.0;
+                if (i >= nseg) break;
+            }
+            if (TRACK && !F32 && !COLLAPSE && rec[i].m == 1) {
                 // a run of segments without sub-steps (most of a disc's rays): one step per
                 // node with the profile evaluated there, in a loop of its own (FP64 short-
                 // segment mode; the FP32 form, whose exponential is one instruction, and the
@@ -360,7 +452,51 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                 const int K = rec[i].K;
                 // direct evaluation where the recurrence would not pay for its two
                 // exponentials (no or one sub-step node) or cannot be used (K == 0)
-                if (F32 || !COLLAPSE || K == 0 || m <= 2) {
+                if (!TRACK && LEAN_SUBSTEPS<F32, COLLAPSE> && (F32 || !COLLAPSE || K == 0 || m <= 2)) {
+                    // sub-node j: x = x_cur + j dx, kappa and S linear in j; two sub-nodes per
+                    // iteration, the step's P formed from the optical depths a at both ends
+                    // (alternating between a_prev and aB) and the row's S recomputed from j, so
+                    // that nothing else is carried from one sub-step to the next
+                    T S0[LPL], dk[LPL], dS[LPL], aB[LPL];
+#pragma unroll
+                    for (int l = 0; l < LPL; ++l) {
+                        S0[l] = ls.S_e[l];
+                        dk[l] = (kn[l] - ls.k_cur[l]) * im;
+                        dS[l] = (Sn[l] - S0[l]) * im;
+                    }
+                    int j = 1;
+                    for (; j + 1 < m; j += 2) {
+                        const T t1 = (T)j, t2 = (T)(j + 1);
+                        const T g1 = profile_far(fma(t1, dx, x_cur), tab) * dzq;
+#pragma unroll
+                        for (int l = 0; l < LPL; ++l) {
+                            aB[l] = fma(t1, dk[l], ls.k_cur[l]) * g1;
+                            elim_p((double)(a_prev[l] + aB[l]), (double)fma(t1 - (T)1, dS[l], S0[l]), ls.st[l]);
+                        }
+                        const T g2 = profile_far(fma(t2, dx, x_cur), tab) * dzq;
+#pragma unroll
+                        for (int l = 0; l < LPL; ++l) {
+                            a_prev[l] = fma(t2, dk[l], ls.k_cur[l]) * g2;
+                            elim_p((double)(aB[l] + a_prev[l]), (double)fma(t1, dS[l], S0[l]), ls.st[l]);
+                        }
+                        if (((j + 1) & 3) == 0) rescale_if_big<LPL, false>(ls);   // (the end node checks too)
+                    }
+                    if (j < m) {
+                        const T t1 = (T)j;
+                        const T g1 = profile_far(fma(t1, dx, x_cur), tab) * dzq;
+#pragma unroll
+                        for (int l = 0; l < LPL; ++l) {
+                            aB[l] = fma(t1, dk[l], ls.k_cur[l]) * g1;
+                            elim_p((double)(a_prev[l] + aB[l]), (double)fma(t1 - (T)1, dS[l], S0[l]), ls.st[l]);
+                            a_prev[l] = aB[l];
+                        }
+                    }
+                    // the source of the last sub-node, whose row the end node's step eliminates
+#pragma unroll
+                    for (int l = 0; l < LPL; ++l) ls.S_e[l] = fma((T)(m - 1), dS[l], S0[l]);
+                    gn = profile_far(xn, tab);
+                    travel = 0.0;
+                } else if ((TRACK || !LEAN_SUBSTEPS<F32, COLLAPSE>) && (F32 || !COLLAPSE || K == 0 || m <= 2)) {
                     T S0[LPL], dk[LPL], dS[LPL];
 #pragma unroll
                     for (int l = 0; l < LPL; ++l) {
