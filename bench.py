@@ -525,14 +525,19 @@ def mlp_timing(s, w, dev, steps=50):
     u_ms, _ = s.kernel_stats("mlp_update")
     fwd_ms, tr_ms, up_ms = f_ms / f_n, t_ms / t_n, u_ms / t_n
     fwd_tf = fwd_f * w.n_points / (fwd_ms * 1e-3) / 1e12
+    # "train": the forward/backward and weight-gradient kernels of one step; "step": with
+    # the update kernel (chunk sums, Adam, operand packing) as well
     tr_tf = train_f * 4096 / (tr_ms * 1e-3) / 1e12
+    st_tf = train_f * 4096 / ((tr_ms + up_ms) * 1e-3) / 1e12
     r = {"rows_forward": w.n_points, "forward_ms": fwd_ms, "features_ms": ft_ms / f_n,
          "forward_tflops": fwd_tf, "forward_mfma_frac": fwd_tf / PEAK_BF16_MFMA_TFLOPS,
          "train_batch": 4096, "train_kernel_ms": tr_ms, "update_ms": up_ms,
          "train_tflops": tr_tf, "train_mfma_frac": tr_tf / PEAK_BF16_MFMA_TFLOPS,
+         "train_step_ms": tr_ms + up_ms, "train_step_mfma_frac": st_tf / PEAK_BF16_MFMA_TFLOPS,
          "flops_per_row": {"forward": fwd_f, "train": train_f}, "peak_tflops": PEAK_BF16_MFMA_TFLOPS}
     log(f"mlp: forward {fwd_ms:.3f} ms for {w.n_points} rows ({fwd_tf:.1f} TFLOP/s), features "
-        f"{ft_ms / f_n:.3f} ms; train step {tr_ms:.3f} + {up_ms:.3f} ms ({tr_tf:.1f} TFLOP/s)")
+        f"{ft_ms / f_n:.3f} ms; train step {tr_ms:.3f} + {up_ms:.3f} ms ({tr_tf:.1f} TFLOP/s, "
+        f"{st_tf:.1f} with the update)")
     return r
 
 

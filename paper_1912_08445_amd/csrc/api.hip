@@ -327,8 +327,8 @@ nlte_status ensure_graph(nlte_ctx *c, int slot, const double *cur, double *nxt)
 
 // ------------------------------------------------------------------ warm start helpers
 
-// Largest batch of one gradient evaluation: its workgroup partials take
-// ceil(rows / 64) * n_params FP32 values (145 MB at the limit).
+// Largest batch of one gradient evaluation: its layer inputs and output gradients take
+// 2400 bytes per row (157 MB at the limit).
 constexpr int kMlpMaxRows = 1 << 16;
 
 MlpDims mlp_dims(int n_out)
@@ -372,9 +372,11 @@ nlte_status mlp_alloc(nlte_ctx *c, int n_out)
     if (!m.d_bad && (st = dalloc(c, &m.d_bad, 1))) return st;
     HIPCHK(c, hipMemset(m.d_m, 0, sizeof(float) * np));
     HIPCHK(c, hipMemset(m.d_v, 0, sizeof(float) * np));
-    m.wg_cap = 0;
+    m.batch_cap = 0;
     dfree(m.d_gpart);
     dfree(m.d_lpart);
+    dfree(m.d_ht);
+    dfree(m.d_dzt);
     m.rows_cap = 0;
     dfree(m.d_x);
     dfree(m.d_y);
@@ -392,14 +394,17 @@ nlte_status mlp_upload(nlte_ctx *c, const std::vector<float> &theta)
     return NLTE_OK;
 }
 
-nlte_status mlp_ensure_wg(nlte_ctx *c, int64_t n_wg)
+// Training buffers for batches of up to `batch` rows.
+nlte_status mlp_ensure_batch(nlte_ctx *c, int batch)
 {
     MlpState &m = c->mlp;
-    if (n_wg <= m.wg_cap) return NLTE_OK;
+    if (batch <= m.batch_cap) return NLTE_OK;
     nlte_status st;
-    if ((st = dalloc(c, &m.d_gpart, (size_t)n_wg * m.dims.n_params))) return st;
-    if ((st = dalloc(c, &m.d_lpart, (size_t)n_wg))) return st;
-    m.wg_cap = n_wg;
+    if ((st = dalloc(c, &m.d_gpart, (size_t)mlp_train_chunks(batch) * m.dims.n_params))) return st;
+    if ((st = dalloc(c, &m.d_lpart, (size_t)mlp_train_ld(batch) / 16))) return st;
+    if ((st = dalloc(c, &m.d_ht, mlp_train_ht_count(batch)))) return st;
+    if ((st = dalloc(c, &m.d_dzt, mlp_train_dzt_count(batch)))) return st;
+    m.batch_cap = batch;
     return NLTE_OK;
 }
 
@@ -458,25 +463,22 @@ nlte_status train_impl(nlte_ctx *c, const float *d_X, const float *d_T, int64_t 
                        float *d_loss, hipStream_t s)
 {
     MlpState &m = c->mlp;
-    const int n_wg = mlp_train_blocks(tp->batch);
     nlte_status st;
-    if ((st = mlp_ensure_wg(c, n_wg))) return st;
+    if ((st = mlp_ensure_batch(c, tp->batch))) return st;
     const float inv_count = (float)(1.0 / ((double)tp->batch * m.dims.out[3]));
     for (int64_t i = 0; i < tp->steps; ++i) {
         const int64_t t = ++m.step;
         const int64_t start = (int64_t)(((__int128)(t - 1) * tp->batch) % n);
         HIPCHK(c, timed(c, c->st_mlp_train, s, [&] {
-            return launch_mlp_train(m.d_frags, m.d_theta, m.dims, d_X, d_T, n, start, tp->batch, m.d_gpart,
-                                    m.d_lpart, s);
+            return launch_mlp_train(m.d_frags, m.d_theta, m.dims, d_X, d_T, n, start, tp->batch, m.d_ht,
+                                    m.d_dzt, m.d_gpart, m.d_lpart, s);
         }));
         const float c1 = (float)(1.0 / (1.0 - pow(tp->beta1, (double)t)));
         const float c2 = (float)(1.0 / (1.0 - pow(tp->beta2, (double)t)));
         HIPCHK(c, timed(c, c->st_mlp_update, s, [&] {
-            hipError_t e = launch_mlp_reduce_adam(m.d_theta, m.d_m, m.d_v, m.d_gpart, n_wg, m.dims.n_params, 1,
-                                                  (float)tp->lr, (float)tp->beta1, (float)tp->beta2,
-                                                  (float)tp->eps, c1, c2, m.d_lpart, inv_count,
-                                                  d_loss ? d_loss + i : nullptr, nullptr, s);
-            return e == hipSuccess ? launch_mlp_pack(m.d_theta, m.dims, m.d_frags, s) : e;
+            return launch_mlp_update(m.d_theta, m.d_m, m.d_v, m.d_frags, m.dims, m.d_gpart, tp->batch, 1,
+                                     (float)tp->lr, (float)tp->beta1, (float)tp->beta2, (float)tp->eps, c1, c2,
+                                     m.d_lpart, inv_count, d_loss ? d_loss + i : nullptr, nullptr, s);
         }));
     }
     return NLTE_OK;
@@ -960,6 +962,8 @@ void nlte_destroy(nlte_ctx *c)
         dfree(m.d_frags);
         dfree(m.d_gpart);
         dfree(m.d_lpart);
+        dfree(m.d_ht);
+        dfree(m.d_dzt);
         dfree(m.d_loss);
         dfree(m.d_grad);
         dfree(m.d_x);
@@ -2089,18 +2093,18 @@ nlte_status nlte_mlp_loss_grad(nlte_ctx *c, const float *X, const float *T, int6
     HIPCHK(c, hipSetDevice(c->device));
     MlpState &m = c->mlp;
     const int no = m.dims.out[3];
-    const int n_wg = mlp_train_blocks((int)n);
     if ((st = mlp_ensure_rows(c, n))) return st;
-    if ((st = mlp_ensure_wg(c, n_wg))) return st;
+    if ((st = mlp_ensure_batch(c, (int)n))) return st;
     if (!m.d_loss && (st = dalloc(c, &m.d_loss, 1))) return st;
     if (m.loss_cap < 1) m.loss_cap = 1;
     HIPCHK(c, hipMemcpyAsync(m.d_x, X, sizeof(float) * n * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(m.d_y, T, sizeof(float) * n * no, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_mlp_train(m.d_frags, m.d_theta, m.dims, m.d_x, m.d_y, n, 0, (int)n, m.d_gpart, m.d_lpart,
+    HIPCHK(c, launch_mlp_train(m.d_frags, m.d_theta, m.dims, m.d_x, m.d_y, n, 0, (int)n, m.d_ht, m.d_dzt,
+                               m.d_gpart, m.d_lpart,
                                c->stream));
-    HIPCHK(c, launch_mlp_reduce_adam(m.d_theta, m.d_m, m.d_v, m.d_gpart, n_wg, m.dims.n_params, 0, 0.f, 0.f, 0.f,
-                                     0.f, 1.f, 1.f, m.d_lpart, (float)(1.0 / ((double)n * no)), m.d_loss, m.d_grad,
-                                     c->stream));
+    HIPCHK(c, launch_mlp_update(m.d_theta, m.d_m, m.d_v, m.d_frags, m.dims, m.d_gpart, (int)n, 0, 0.f, 0.f, 0.f,
+                                0.f, 1.f, 1.f, m.d_lpart, (float)(1.0 / ((double)n * no)), m.d_loss, m.d_grad,
+                                c->stream));
     float lval = 0.f;
     if (grad)
         HIPCHK(c, hipMemcpyAsync(grad, m.d_grad, sizeof(float) * m.dims.n_params, hipMemcpyDeviceToHost, c->stream));

@@ -206,9 +206,11 @@ struct MlpState {
     int64_t step = 0;                 // Adam steps since init / set_weights
     float *d_theta = nullptr, *d_m = nullptr, *d_v = nullptr;  // [n_params]
     void *d_frags = nullptr;          // bfloat16 A operands packed from d_theta
-    float *d_gpart = nullptr;         // [wg_cap][n_params]
-    float *d_lpart = nullptr;         // [wg_cap]
-    int64_t wg_cap = 0;
+    float *d_gpart = nullptr;         // [chunks][n_params] weight-gradient partials
+    float *d_lpart = nullptr;         // [ld / 16] loss partials
+    unsigned short *d_ht = nullptr;   // layer inputs of a batch (bfloat16, feature-major)
+    float *d_dzt = nullptr;           // layer output gradients of a batch (feature-major)
+    int64_t batch_cap = 0;            // largest batch the training buffers hold
     float *d_loss = nullptr;          // [loss_cap]
     int64_t loss_cap = 0;
     float *d_grad = nullptr;          // [n_params]
@@ -447,16 +449,21 @@ hipError_t launch_features(const CellRec *cell, const double *nh2, const double 
                            int k, const int64_t *roff, const int32_t *rcells, const double *dir, int R,
                            int64_t P, double *F, hipStream_t s);
 int mlp_frag_count();
-int mlp_train_blocks(int batch);
+// training buffers of a batch: rows padded to 32 (ld), row chunks of the weight
+// gradients, element counts of the layer inputs Ht (bfloat16) and output gradients DZt (FP32)
+int mlp_train_ld(int batch);
+int mlp_train_chunks(int batch);
+size_t mlp_train_ht_count(int batch);
+size_t mlp_train_dzt_count(int batch);
 hipError_t launch_mlp_pack(const float *theta, const MlpDims &d, void *frags, hipStream_t s);
 hipError_t launch_mlp_forward(const void *frags, const float *theta, const MlpDims &d, const float *X,
                               int64_t n, float *Y, hipStream_t s);
 hipError_t launch_mlp_train(const void *frags, const float *theta, const MlpDims &d, const float *X, const float *T,
-                            int64_t n, int64_t start, int batch, float *gpart, float *lpart, hipStream_t s);
-hipError_t launch_mlp_reduce_adam(float *theta, float *m, float *v, const float *gpart, int n_wg, int64_t np,
-                                  int update, float lr, float b1, float b2, float eps, float c1, float c2,
-                                  const float *lpart, float inv_count, float *loss, float *grad_out,
-                                  hipStream_t s);
+                            int64_t n, int64_t start, int batch, unsigned short *Ht, float *DZt, float *gpart,
+                            float *lpart, hipStream_t s);
+hipError_t launch_mlp_update(float *theta, float *m, float *v, void *frags, const MlpDims &d, const float *gpart,
+                             int batch, int update, float lr, float b1, float b2, float eps, float c1, float c2,
+                             const float *lpart, float inv_count, float *loss, float *grad_out, hipStream_t s);
 hipError_t launch_mlp_standardise(const double *F, const MlpNorm &nm, int64_t P, float *X, hipStream_t s);
 hipError_t launch_mlp_targets(const SpeciesDev &sp, const double *pops, const CellRec *cell, const double *T,
                               int64_t P, float *Tg, hipStream_t s);

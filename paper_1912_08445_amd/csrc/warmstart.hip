@@ -27,9 +27,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kHid = 128;
-constexpr int kRowsWg = 64;   // rows per training workgroup (4 waves x 16)
-constexpr int kHS = 136;      // LDS row stride of bf16 activations (padding against bank conflicts)
-constexpr int kDS = 132;      // LDS row stride of FP32 output gradients
 
 // Round to the nearest bfloat16, ties to even (finite inputs).
 __device__ inline unsigned short bf16_bits(float x)
@@ -52,13 +49,31 @@ __device__ inline f32x4 mfma(const Frag &a, const Frag &b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), c, 0, 0, 0);
 }
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU and its derivative from one exponential.  erf(x) for x >= 0 by Abramowitz &
+// Stegun 7.1.26, erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^{-x^2} with
+// t = 1/(1 + p x) (absolute error below 1.5e-7, far under the bfloat16 rounding that
+// follows); at x = |z|/sqrt 2 its Gaussian e^{-z^2/2} is also the derivative's:
+//   gelu(z) = z (1 + erf(z/sqrt 2))/2,  gelu'(z) = (1 + erf(z/sqrt 2))/2 + z e^{-z^2/2}/sqrt(2 pi).
+// 1 + erf is formed as q or 2 - q with q = 1 - erf(|x|), without cancellation for z < 0.
+struct GeluPair {
+    float h, dh;
+};
 
-__device__ inline float gelu_grad(float z)
+__device__ inline GeluPair gelu_pair(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    const float e = __builtin_amdgcn_exp2f(-0.72134752044448170f * (z * z));   // e^{-z^2/2}
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+    float p = fmaf(1.061405429f, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    const float q = (p * t) * e;
+    const float one_p = z >= 0.0f ? 2.0f - q : q;
+    return {0.5f * z * one_p, fmaf(z * e, 0.39894228040143268f, 0.5f * one_p)};
 }
+
+__device__ inline float gelu(float z) { return gelu_pair(z).h; }
 
 // Reduction index of K slot j of lane group g in K step s.
 __device__ inline int kslot(int s, int g, int j) { return 32 * s + 16 * (j >> 2) + 4 * g + (j & 3); }
@@ -271,18 +286,28 @@ __device__ inline Frag input_frag(const float *__restrict__ X, int64_t row, bool
 }
 
 // Hidden layer L (1 or 2, 0-based index into the dims) from B operands hb[4] to new
-// pre-activations acc[8] (bias added).
+// pre-activations acc[8] (bias added).  The layer's 32 weight operands and its biases are
+// requested together before the first product, so that the wave waits for memory once
+// per layer rather than once per product.
 __device__ inline void hidden_layer(const Frag *__restrict__ fw, int L, const Frag (&hb)[4], const float *__restrict__ bias,
                                     int lane, f32x4 (&acc)[8])
 {
     const int g = lane >> 4;
+    Frag w[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) w[t] = load_frag(fw, kFwdBase[L] + t, lane);
+    f32x4 bv[8];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[mt][j] = bias[16 * mt + 4 * g + j];
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) c = mfma(load_frag(fw, kFwdBase[L] + mt * 4 + s, lane), hb[s], c);
+        for (int s = 0; s < 4; ++s) c = mfma(w[mt * 4 + s], hb[s], c);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) c[j] += bias[16 * mt + 4 * g + j];
+        for (int j = 0; j < 4; ++j) c[j] += bv[mt][j];
         acc[mt] = c;
     }
 }
@@ -329,10 +354,13 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const Frag *__restrict__ fw
 #pragma unroll
             for (int s = 0; s < 4; ++s) hb[t][s] = pack_pair(acc[t][2 * s], acc[t][2 * s + 1]);
     }
-    // layers 2 and 3
+    // layers 2 and 3 (each layer's 32 weight operands requested together)
 #pragma unroll
     for (int L = 1; L <= 2; ++L) {
         const float *bL = theta + d.b_off[L];
+        Frag wL[32];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) wL[t] = load_frag(fw, kFwdBase[L] + t, lane);
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             f32x4 c[NT];
@@ -340,7 +368,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const Frag *__restrict__ fw
             for (int t = 0; t < NT; ++t) c[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const Frag a = load_frag(fw, kFwdBase[L] + mt * 4 + s, lane);
+                const Frag a = wL[mt * 4 + s];
 #pragma unroll
                 for (int t = 0; t < NT; ++t) c[t] = mfma(a, hb[t][s], c[t]);
             }
@@ -389,106 +417,143 @@ hipError_t launch_mlp_forward(const void *frags, const float *theta, const MlpDi
     return hipGetLastError();
 }
 
-// One training pass over a batch: forward, loss, backward, and this workgroup's share
-// of the parameter gradient.  Workgroup w takes batch rows 64 w .. 64 w + 63; batch row
-// b reads data row (start + b) mod n.  gpart [n_wg][n_params]; lpart [n_wg] holds the
-// workgroup's sum of squared errors.  gscale = 2 / (batch n_out).
-__global__ __launch_bounds__(256) void k_mlp_train(const Frag *__restrict__ frags, const float *__restrict__ theta,
-                                                   MlpDims d, const float *__restrict__ X,
-                                                   const float *__restrict__ Tg, int64_t n, int64_t start,
-                                                   int batch, float gscale, float *__restrict__ gpart,
-                                                   float *__restrict__ lpart)
-{
-    __shared__ unsigned short H0[kRowsWg][16];
-    __shared__ unsigned short Hs[3][kRowsWg][kHS];
-    __shared__ float DZ[kRowsWg][kDS];
-    __shared__ float red[4];
+// ----------------------------------------------------------------- training
+//
+// One optimiser step is three launches:
+//   k_mlp_fwdbwd  one wave per 16 batch rows: forward, loss and backward through every
+//                 layer; each layer's input (bfloat16, as the products read it) and output
+//                 gradient (FP32) go to global memory, feature-major with the batch rows
+//                 contiguous (Ht [kHRows][ld], DZt [kDRows][ld], ld = batch rounded up to 32);
+//   k_mlp_wgrad   the weight gradients dW_L = DZ_L^T H_L as products over the batch rows:
+//                 one wave per (16 x 16 tile, chunk of rows), partial sums per chunk;
+//   k_mlp_update  the chunks summed in order, Adam, and the new weights written into the
+//                 bfloat16 operands of the forward and backward products.
+// Rounding is where the single-kernel form had it: activations and output gradients are
+// rounded to bfloat16 as product operands, the bias gradient sums the FP32 output gradients.
 
+constexpr int kHRows = 16 + 3 * kHid;                              // feature rows of Ht
+constexpr int kHOff[4] = {0, 16, 16 + kHid, 16 + 2 * kHid};        // input of layer L (8 inputs padded to 16)
+constexpr int kDRows = 3 * kHid + 16;                              // feature rows of DZt
+constexpr int kDOff[4] = {0, kHid, 2 * kHid, 3 * kHid};            // output gradient of layer L (n_out padded to 16)
+// weight-gradient tiles (16 outputs x 16 inputs): L1 8 x 1, L2 8 x 8, L3 8 x 8, L4 1 x 8
+constexpr int kTileBase[5] = {0, 8, 72, 136, 144};
+constexpr int kTiles = 144;
+constexpr int kMaxChunks = 8;
+
+// (rows padded to 32, row chunks) of a batch
+__host__ __device__ inline int mlp_ld(int batch) { return (batch + 31) / 32 * 32; }
+inline int mlp_chunks(int ld) { return ld / 32 < kMaxChunks ? ld / 32 : kMaxChunks; }
+
+__global__ __launch_bounds__(64) void k_mlp_fwdbwd(const Frag *__restrict__ frags, const float *__restrict__ theta,
+                                                    MlpDims d, const float *__restrict__ X,
+                                                    const float *__restrict__ Tg, int64_t n, int64_t start, int batch,
+                                                    float gscale, unsigned short *__restrict__ Ht,
+                                                    float *__restrict__ DZt, int ld, float *__restrict__ lpart)
+{
     const Frag *fw = frags;
     const Frag *bw = frags + (int64_t)kFwdFrags * 64;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     const int i = lane & 15, g = lane >> 4;
-    const int rl = 16 * w + i;  // this lane's row within the workgroup (as an output column)
-    const int64_t b = (int64_t)blockIdx.x * kRowsWg + rl;
+    const int64_t b = (int64_t)blockIdx.x * 16 + i;   // batch row: the tiles' column i
     const bool valid = b < batch;
     const int64_t row = valid ? (start + b) % n : 0;
-    float *gp = gpart + (int64_t)blockIdx.x * d.n_params;
 
-    // ---- forward, keeping pre-activations in registers and activations in LDS
-    f32x4 z[3][8];
+    // forward; the GELU derivative at each hidden pre-activation waits for the backward
+    // pass in the slot of DZt that the layer's output gradient later takes (each lane
+    // reads and writes only its own row)
+    f32x4 z[8];
     Frag hb[4];
     {
         const Frag xb = input_frag(X, row, valid, g);
-        if (g < 2) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) H0[rl][4 * g + j] = xb.v[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) H0[rl][8 + 4 * (g - 2) + j] = 0;
-        }
+        for (int j = 0; j < 4; ++j) Ht[(int64_t)(kHOff[0] + 4 * g + j) * ld + b] = xb.v[j];
         const float *b1 = theta + d.b_off[0];
+        Frag w1[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) w1[mt] = load_frag(fw, kFwdBase[0] + mt, lane);
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
-            c = mfma(load_frag(fw, kFwdBase[0] + mt, lane), xb, c);
+            c = mfma(w1[mt], xb, c);
 #pragma unroll
             for (int j = 0; j < 4; ++j) c[j] += b1[16 * mt + 4 * g + j];
-            z[0][mt] = c;
+            z[mt] = c;
         }
     }
 #pragma unroll
     for (int L = 0; L < 3; ++L) {
-        f32x4 h[8];
+        // activations rounded to bfloat16: stored for the weight gradients and packed in
+        // pairs of output tiles as the next layer's B operand
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt)
+        for (int s = 0; s < 4; ++s) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const unsigned short hv = bf16_bits(gelu(z[L][mt][j]));
-                Hs[L][rl][16 * mt + 4 * g + j] = hv;
-                h[mt][j] = bf16_value(hv);
+            for (int half = 0; half < 2; ++half) {
+                const int mt = 2 * s + half;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const GeluPair q = gelu_pair(z[mt][j]);
+                    const unsigned short hv = bf16_bits(q.h);
+                    Ht[(int64_t)(kHOff[L + 1] + 16 * mt + 4 * g + j) * ld + b] = hv;
+                    hb[s].v[4 * half + j] = hv;
+                    DZt[(int64_t)(kDOff[L] + 16 * mt + 4 * g + j) * ld + b] = q.dh;
+                }
             }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) hb[s] = pack_pair(h[2 * s], h[2 * s + 1]);
-        if (L < 2) hidden_layer(fw, L + 1, hb, theta + d.b_off[L + 1], lane, z[L + 1]);
+        }
+        if (L < 2) hidden_layer(fw, L + 1, hb, theta + d.b_off[L + 1], lane, z);
     }
-    // output layer and loss
+    // output layer and loss (rows past the batch contribute zero gradients)
     f32x4 dz[8];
     float sq = 0.0f;
     {
+        Frag w4[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) w4[s] = load_frag(fw, kFwdBase[3] + s, lane);
+        float tg[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = 4 * g + j;
+            tg[j] = (valid && o < d.out[3]) ? Tg[row * d.out[3] + o] : 0.0f;
+        }
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) c = mfma(load_frag(fw, kFwdBase[3] + s, lane), hb[s], c);
+        for (int s = 0; s < 4; ++s) c = mfma(w4[s], hb[s], c);
         const float *b4 = theta + d.b_off[3];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int o = 4 * g + j;
             float e = 0.0f;
-            if (valid && o < d.out[3]) e = (c[j] + b4[o]) - Tg[row * d.out[3] + o];
+            if (valid && o < d.out[3]) e = (c[j] + b4[o]) - tg[j];
             sq += e * e;
             dz[0][j] = gscale * e;
         }
 #pragma unroll
         for (int mt = 1; mt < 8; ++mt) dz[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    // loss partial: wave sum in a fixed tree, then the four waves in order
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
-    if (lane == 0) red[w] = sq;
+    if (lane == 0) lpart[blockIdx.x] = sq;
 
-    // ---- backward, layer 4 down to 1
+    // backward, layer 4 down to 1: store each output gradient, then form the next one
 #pragma unroll
     for (int L = 3; L >= 0; --L) {
-        const int MT = (d.out[L] + 15) / 16;
-        // output gradient of this layer into LDS [row][out]
+        const int MT = L == 3 ? 1 : 8;
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
             if (mt < MT)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) DZ[rl][16 * mt + 4 * g + j] = dz[mt][j];
-        // gradient w.r.t. this layer's input (registers), through the previous GELU
-        f32x4 dzn[8];
+                for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[L] + 16 * mt + 4 * g + j) * ld + b] = dz[mt][j];
         if (L > 0) {
             const int KT = (L == 3) ? 1 : 4;
+            // the layer's weight operands and the GELU derivatives requested together
+            Frag w[32];
+#pragma unroll
+            for (int t = 0; t < 32; ++t)
+                if (t < 8 * KT) w[t] = load_frag(bw, kBwdBase[L] + t, lane);
+            f32x4 dgv[8];
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dgv[mt][j] = DZt[(int64_t)(kDOff[L - 1] + 16 * mt + 4 * g + j) * ld + b];
             Frag db[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -498,97 +563,181 @@ __global__ __launch_bounds__(256) void k_mlp_train(const Frag *__restrict__ frag
                 f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    if (s < KT) c = mfma(load_frag(bw, kBwdBase[L] + mt * KT + s, lane), db[s], c);
+                    if (s < KT) c = mfma(w[mt * KT + s], db[s], c);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) dzn[mt][j] = c[j] * gelu_grad(z[L - 1][mt][j]);
+                for (int j = 0; j < 4; ++j) dz[mt][j] = c[j] * dgv[mt][j];
             }
         }
-        __syncthreads();
-        // weight gradient over the workgroup's 64 rows: tiles (output mt, input nt)
-        {
-            const int NTi = (d.in[L] + 15) / 16;
-            const int tiles = MT * NTi;
-            for (int tIdx = w; tIdx < tiles; tIdx += 4) {
-                const int mt = tIdx / NTi, nt = tIdx % NTi;
-                f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    Frag a, bb;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int r = kslot(s, g, j);
-                        a.v[j] = bf16_bits(DZ[r][16 * mt + i]);
-                        bb.v[j] = (L == 0) ? H0[r][i] : Hs[L - 1][r][16 * nt + i];
-                    }
-                    c = mfma(a, bb, c);
-                }
-                const int kcol = 16 * nt + i;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int o = 16 * mt + 4 * g + j;
-                    if (o < d.out[L] && kcol < d.in[L]) gp[d.w_off[L] + (int64_t)o * d.in[L] + kcol] = c[j];
-                }
-            }
-            // bias gradient: unrounded output gradients summed over rows in order
-            for (int o = threadIdx.x; o < d.out[L]; o += blockDim.x) {
-                float sacc = 0.0f;
-                for (int r = 0; r < kRowsWg; ++r) sacc += DZ[r][o];
-                gp[d.b_off[L] + o] = sacc;
-            }
-        }
-        __syncthreads();
-        if (L > 0)
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt) dz[mt] = dzn[mt];
     }
-    if (threadIdx.x == 0) lpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-int mlp_train_blocks(int batch) { return (batch + kRowsWg - 1) / kRowsWg; }
+// Weight gradients of one 16 x 16 tile over one chunk of batch rows (blockIdx.x: tile,
+// blockIdx.y: chunk).  The A operand is the output gradients (rounded to bfloat16), the
+// B operand the layer's inputs; a lane loads its eight rows as two runs of four.  Tiles
+// of the first input column also sum the FP32 output gradients for the bias.  gpart
+// [chunks][n_params].
+__global__ __launch_bounds__(64) void k_mlp_wgrad(MlpDims d, const unsigned short *__restrict__ Ht,
+                                                   const float *__restrict__ DZt, int ld, int chunk,
+                                                   float *__restrict__ gpart)
+{
+    const int tile = blockIdx.x, c = blockIdx.y;
+    const int L = tile < kTileBase[1] ? 0 : tile < kTileBase[2] ? 1 : tile < kTileBase[3] ? 2 : 3;
+    const int NT = L == 0 ? 1 : 8;
+    const int local = tile - kTileBase[L];
+    const int mt = local / NT, nt = local - mt * NT;
+    const int lane = threadIdx.x;
+    const int i = lane & 15, g = lane >> 4;
+    const float *arow = DZt + (int64_t)(kDOff[L] + 16 * mt + i) * ld;
+    const unsigned short *brow = Ht + (int64_t)(kHOff[L] + 16 * nt + i) * ld;
+    const int r_beg = c * chunk, r_end = min(ld, r_beg + chunk);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.0f;
+    // rows r0 + 16 q + 4 g + (0..3), q = 0, 1: the lane's eight K slots of one step
+    struct Raw {
+        float4 a0, a1;
+        uint2 b0, b1;
+    };
+    auto fetch = [&](int r0) {
+        Raw w;
+        w.a0 = *reinterpret_cast<const float4 *>(arow + r0 + 4 * g);
+        w.a1 = *reinterpret_cast<const float4 *>(arow + r0 + 16 + 4 * g);
+        w.b0 = *reinterpret_cast<const uint2 *>(brow + r0 + 4 * g);
+        w.b1 = *reinterpret_cast<const uint2 *>(brow + r0 + 16 + 4 * g);
+        return w;
+    };
+    auto use = [&](const Raw &w) {
+        Frag fa, fb;
+        fa.v[0] = bf16_bits(w.a0.x);
+        fa.v[1] = bf16_bits(w.a0.y);
+        fa.v[2] = bf16_bits(w.a0.z);
+        fa.v[3] = bf16_bits(w.a0.w);
+        fa.v[4] = bf16_bits(w.a1.x);
+        fa.v[5] = bf16_bits(w.a1.y);
+        fa.v[6] = bf16_bits(w.a1.z);
+        fa.v[7] = bf16_bits(w.a1.w);
+        fb.v[0] = (unsigned short)(w.b0.x & 0xFFFFu);
+        fb.v[1] = (unsigned short)(w.b0.x >> 16);
+        fb.v[2] = (unsigned short)(w.b0.y & 0xFFFFu);
+        fb.v[3] = (unsigned short)(w.b0.y >> 16);
+        fb.v[4] = (unsigned short)(w.b1.x & 0xFFFFu);
+        fb.v[5] = (unsigned short)(w.b1.x >> 16);
+        fb.v[6] = (unsigned short)(w.b1.y & 0xFFFFu);
+        fb.v[7] = (unsigned short)(w.b1.y >> 16);
+        bsum += ((w.a0.x + w.a0.y) + (w.a0.z + w.a0.w)) + ((w.a1.x + w.a1.y) + (w.a1.z + w.a1.w));
+        acc = mfma(fa, fb, acc);
+    };
+    int r0 = r_beg;
+    // four steps' operands requested before the first of their products
+    for (; r0 + 96 < r_end; r0 += 128) {
+        const Raw w0 = fetch(r0), w1 = fetch(r0 + 32), w2 = fetch(r0 + 64), w3 = fetch(r0 + 96);
+        use(w0);
+        use(w1);
+        use(w2);
+        use(w3);
+    }
+    for (; r0 < r_end; r0 += 32) use(fetch(r0));
+    float *gp = gpart + (int64_t)c * d.n_params;
+    const int col = 16 * nt + i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int o = 16 * mt + 4 * g + j;
+        if (o < d.out[L] && col < d.in[L]) gp[d.w_off[L] + (int64_t)o * d.in[L] + col] = acc[j];
+    }
+    if (nt == 0) {
+        // output 16 mt + i: the row sums of the four lane groups, in order
+        const float t0 = __shfl(bsum, i), t1 = __shfl(bsum, 16 + i), t2 = __shfl(bsum, 32 + i),
+                    t3 = __shfl(bsum, 48 + i);
+        const int o = 16 * mt + i;
+        if (g == 0 && o < d.out[L]) gp[d.b_off[L] + o] = ((t0 + t1) + t2) + t3;
+    }
+}
+
+int mlp_train_ld(int batch) { return mlp_ld(batch); }
+int mlp_train_chunks(int batch) { return mlp_chunks(mlp_ld(batch)); }
+size_t mlp_train_ht_count(int batch) { return (size_t)kHRows * mlp_ld(batch); }
+size_t mlp_train_dzt_count(int batch) { return (size_t)kDRows * mlp_ld(batch); }
 
 hipError_t launch_mlp_train(const void *frags, const float *theta, const MlpDims &d, const float *X, const float *T,
-                            int64_t n, int64_t start, int batch, float *gpart, float *lpart, hipStream_t s)
+                            int64_t n, int64_t start, int batch, unsigned short *Ht, float *DZt, float *gpart,
+                            float *lpart, hipStream_t s)
 {
-    const int blocks = mlp_train_blocks(batch);
+    const int ld = mlp_ld(batch);
     const float gscale = (float)(2.0 / ((double)batch * d.out[3]));
-    hipLaunchKernelGGL(k_mlp_train, dim3(blocks), dim3(256), 0, s, (const Frag *)frags, theta, d, X, T, n, start,
-                       batch, gscale, gpart, lpart);
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)(ld / 16)), dim3(64), 0, s, (const Frag *)frags, theta, d, X, T,
+                       n, start, batch, gscale, Ht, DZt, ld, lpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int S = mlp_chunks(ld);
+    const int chunk = (ld / 32 + S - 1) / S * 32;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(kTiles, S), dim3(64), 0, s, d, (const unsigned short *)Ht,
+                       (const float *)DZt, ld, chunk, gpart);
     return hipGetLastError();
 }
 
-// Sum the workgroup partials in a fixed order; optionally write the gradient and apply
-// one Adam step (c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t)).  The first thread also
-// writes the batch loss (mean squared error) to *loss.
-__global__ void k_mlp_reduce_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
-                                  const float *__restrict__ gpart, int n_wg, int64_t np, int update, float lr,
-                                  float b1, float b2, float eps, float c1, float c2,
-                                  const float *__restrict__ lpart, float inv_count, float *__restrict__ loss,
-                                  float *__restrict__ grad_out)
+// Sum the chunk partials in order; optionally write the gradient; with `update`, one
+// Adam step (c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t)) and the new weight's bfloat16
+// value written into its slot of the forward operands and, for layers 2-4, of the
+// backward (transposed) operands; the slots are those k_mlp_pack fills, found by
+// inverting its index map.  The first thread writes the batch loss (mean squared error).
+__global__ void k_mlp_update(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
+                             unsigned short *__restrict__ fslot, MlpDims d, const float *__restrict__ gpart, int S,
+                             int update, float lr, float b1, float b2, float eps, float c1, float c2,
+                             const float *__restrict__ lpart, int n_waves, float inv_count, float *__restrict__ loss,
+                             float *__restrict__ grad_out)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t np = d.n_params;
     if (p == 0 && loss) {
-        float s = 0.0f;
-        for (int w = 0; w < n_wg; ++w) s += lpart[w];
-        *loss = s * inv_count;
+        float sacc = 0.0f;
+        for (int w = 0; w < n_waves; ++w) sacc += lpart[w];
+        *loss = sacc * inv_count;
     }
     if (p >= np) return;
     float gsum = 0.0f;
-    for (int w = 0; w < n_wg; ++w) gsum += gpart[(int64_t)w * np + p];
+    for (int c = 0; c < S; ++c) gsum += gpart[(int64_t)c * np + p];
     if (grad_out) grad_out[p] = gsum;
     if (!update) return;
     const float mm = b1 * m[p] + (1.0f - b1) * gsum;
     const float vv = b2 * v[p] + (1.0f - b2) * gsum * gsum;
     m[p] = mm;
     v[p] = vv;
-    theta[p] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+    const float t = theta[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+    theta[p] = t;
+    int L = -1;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+        if (p >= d.w_off[l] && p < d.b_off[l]) L = l;
+    if (L < 0) return;   // a bias: not in the packed operands
+    const unsigned short tb = bf16_bits(t);
+    const int o = (int)((p - d.w_off[L]) / d.in[L]);
+    const int k = (int)((p - d.w_off[L]) - (int64_t)o * d.in[L]);
+    {
+        // forward operand: row o of tile mt, reduction index k = kslot(s, g, j)
+        const int KT = L == 0 ? 1 : 4;
+        const int s = k >> 5, r = k & 31;
+        const int j = 4 * (r >> 4) + (r & 3), g = (r & 15) >> 2;
+        const int fi = kFwdBase[L] + (o >> 4) * KT + s;
+        fslot[((int64_t)fi * 64 + 16 * g + (o & 15)) * 8 + j] = tb;
+    }
+    if (L >= 1) {
+        // backward operand: row k (the layer's input) of tile k / 16, reduction index o
+        const int KT = L == 3 ? 1 : 4;
+        const int s = o >> 5, r = o & 31;
+        const int j = 4 * (r >> 4) + (r & 3), g = (r & 15) >> 2;
+        const int fi = kFwdFrags + kBwdBase[L] + (k >> 4) * KT + s;
+        fslot[((int64_t)fi * 64 + 16 * g + (k & 15)) * 8 + j] = tb;
+    }
 }
 
-hipError_t launch_mlp_reduce_adam(float *theta, float *m, float *v, const float *gpart, int n_wg, int64_t np,
-                                  int update, float lr, float b1, float b2, float eps, float c1, float c2,
-                                  const float *lpart, float inv_count, float *loss, float *grad_out, hipStream_t s)
+hipError_t launch_mlp_update(float *theta, float *m, float *v, void *frags, const MlpDims &d, const float *gpart,
+                             int batch, int update, float lr, float b1, float b2, float eps, float c1, float c2,
+                             const float *lpart, float inv_count, float *loss, float *grad_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, theta, m, v, gpart,
-                       n_wg, np, update, lr, b1, b2, eps, c1, c2, lpart, inv_count, loss, grad_out);
+    const int ld = mlp_ld(batch);
+    const int64_t np = d.n_params;
+    hipLaunchKernelGGL(k_mlp_update, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, theta, m, v,
+                       (unsigned short *)frags, d, gpart, mlp_chunks(ld), update, lr, b1, b2, eps, c1, c2, lpart,
+                       ld / 16, inv_count, loss, grad_out);
     return hipGetLastError();
 }
 
