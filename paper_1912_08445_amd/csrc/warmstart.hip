@@ -420,7 +420,7 @@ hipError_t launch_mlp_forward(const void *frags, const float *theta, const MlpDi
 // ----------------------------------------------------------------- training
 //
 // One optimiser step is three launches:
-//   k_mlp_fwdbwd  one wave per 16 batch rows: forward, loss and backward through every
+//   k_mlp_fwdbwd  four waves per 16 batch rows: forward, loss and backward through every
 //                 layer; each layer's input (bfloat16, as the products read it) and output
 //                 gradient (FP32) go to global memory, feature-major with the batch rows
 //                 contiguous (Ht [kHRows][ld], DZt [kDRows][ld], ld = batch rounded up to 32);
@@ -444,128 +444,168 @@ constexpr int kMaxChunks = 8;
 __host__ __device__ inline int mlp_ld(int batch) { return (batch + 31) / 32 * 32; }
 inline int mlp_chunks(int ld) { return ld / 32 < kMaxChunks ? ld / 32 : kMaxChunks; }
 
-__global__ __launch_bounds__(64) void k_mlp_fwdbwd(const Frag *__restrict__ frags, const float *__restrict__ theta,
-                                                    MlpDims d, const float *__restrict__ X,
-                                                    const float *__restrict__ Tg, int64_t n, int64_t start, int batch,
-                                                    float gscale, unsigned short *__restrict__ Ht,
-                                                    float *__restrict__ DZt, int ld, float *__restrict__ lpart)
+// Forward and backward of 16 batch rows by a workgroup of four waves: wave w computes
+// output tiles 2w and 2w+1 of every 128-wide layer, whose packed pair is exactly K step w
+// of the next product's B operand; the waves exchange those operands through LDS (two
+// buffers used in turn, one barrier per exchange).  The output layer (one tile) is
+// computed by every wave, so that each holds the output gradient; wave 0 alone writes it
+// and the loss.  Every weight operand a wave needs (40 of them) is requested at the start.
+__global__ __launch_bounds__(256) void k_mlp_fwdbwd(const Frag *__restrict__ frags, const float *__restrict__ theta,
+                                                     MlpDims d, const float *__restrict__ X,
+                                                     const float *__restrict__ Tg, int64_t n, int64_t start,
+                                                     int batch, float gscale, unsigned short *__restrict__ Ht,
+                                                     float *__restrict__ DZt, int ld, float *__restrict__ lpart)
 {
+    __shared__ Frag xch[2][4][64];
     const Frag *fw = frags;
     const Frag *bw = frags + (int64_t)kFwdFrags * 64;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4;
     const int64_t b = (int64_t)blockIdx.x * 16 + i;   // batch row: the tiles' column i
     const bool valid = b < batch;
     const int64_t row = valid ? (start + b) % n : 0;
 
-    // forward; the GELU derivative at each hidden pre-activation waits for the backward
-    // pass in the slot of DZt that the layer's output gradient later takes (each lane
-    // reads and writes only its own row)
-    f32x4 z[8];
-    Frag hb[4];
-    {
-        const Frag xb = input_frag(X, row, valid, g);
+    // weight operands: forward layer 1 (tiles 2w, 2w+1), layers 2 and 3 (those tiles, K
+    // steps 0..3), the output layer (K steps 0..3); backward of layers 4, 3, 2 (the wave's
+    // tiles of W^T, one K step for layer 4, four otherwise)
+    Frag f1[2], f2[8], f3[8], f4[4], g4[2], g3[8], g2[8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) f1[t] = load_frag(fw, kFwdBase[0] + 2 * w + t, lane);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        f2[t] = load_frag(fw, kFwdBase[1] + 8 * w + t, lane);
+        f3[t] = load_frag(fw, kFwdBase[2] + 8 * w + t, lane);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) f4[t] = load_frag(fw, kFwdBase[3] + t, lane);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) g4[t] = load_frag(bw, kBwdBase[3] + 2 * w + t, lane);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        g3[t] = load_frag(bw, kBwdBase[2] + 8 * w + t, lane);
+        g2[t] = load_frag(bw, kBwdBase[1] + 8 * w + t, lane);
+    }
+    float tg[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int o = 4 * g + j;
+        tg[j] = (valid && o < d.out[3]) ? Tg[row * d.out[3] + o] : 0.0f;
+    }
+
+    const Frag xb = input_frag(X, row, valid, g);
+    if (w == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) Ht[(int64_t)(kHOff[0] + 4 * g + j) * ld + b] = xb.v[j];
+    }
+    int buf = 0;
+    // exchange: this wave's packed pair in, the four K steps out
+    auto exchange = [&](const Frag &mine, Frag (&all)[4]) {
+        xch[buf][w][lane] = mine;
+        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) all[s2] = xch[buf][s2][lane];
+        buf ^= 1;
+    };
+
+    // ---- forward
+    f32x4 z[2];
+    {
         const float *b1 = theta + d.b_off[0];
-        Frag w1[8];
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) w1[mt] = load_frag(fw, kFwdBase[0] + mt, lane);
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
+        for (int t = 0; t < 2; ++t) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
-            c = mfma(w1[mt], xb, c);
+            c = mfma(f1[t], xb, c);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) c[j] += b1[16 * mt + 4 * g + j];
-            z[mt] = c;
+            for (int j = 0; j < 4; ++j) c[j] += b1[16 * (2 * w + t) + 4 * g + j];
+            z[t] = c;
         }
     }
+    f32x4 dg[3][2];   // GELU derivatives of the wave's tiles, hidden layers 1..3
+    Frag hb[4];
 #pragma unroll
     for (int L = 0; L < 3; ++L) {
-        // activations rounded to bfloat16: stored for the weight gradients and packed in
-        // pairs of output tiles as the next layer's B operand
+        Frag mine;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int t = 0; t < 2; ++t) {
+            const int mt = 2 * w + t;
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const int mt = 2 * s + half;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const GeluPair q = gelu_pair(z[mt][j]);
-                    const unsigned short hv = bf16_bits(q.h);
-                    Ht[(int64_t)(kHOff[L + 1] + 16 * mt + 4 * g + j) * ld + b] = hv;
-                    hb[s].v[4 * half + j] = hv;
-                    DZt[(int64_t)(kDOff[L] + 16 * mt + 4 * g + j) * ld + b] = q.dh;
-                }
+            for (int j = 0; j < 4; ++j) {
+                const GeluPair q = gelu_pair(z[t][j]);
+                const unsigned short hv = bf16_bits(q.h);
+                Ht[(int64_t)(kHOff[L + 1] + 16 * mt + 4 * g + j) * ld + b] = hv;
+                mine.v[4 * t + j] = hv;
+                dg[L][t][j] = q.dh;
             }
         }
-        if (L < 2) hidden_layer(fw, L + 1, hb, theta + d.b_off[L + 1], lane, z);
-    }
-    // output layer and loss (rows past the batch contribute zero gradients)
-    f32x4 dz[8];
-    float sq = 0.0f;
-    {
-        Frag w4[4];
+        exchange(mine, hb);
+        if (L < 2) {
+            const Frag *fl = L == 0 ? f2 : f3;
+            const float *bL = theta + d.b_off[L + 1];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w4[s] = load_frag(fw, kFwdBase[3] + s, lane);
-        float tg[4];
+            for (int t = 0; t < 2; ++t) {
+                f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int o = 4 * g + j;
-            tg[j] = (valid && o < d.out[3]) ? Tg[row * d.out[3] + o] : 0.0f;
+                for (int s2 = 0; s2 < 4; ++s2) c = mfma(fl[4 * t + s2], hb[s2], c);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) c[j] += bL[16 * (2 * w + t) + 4 * g + j];
+                z[t] = c;
+            }
         }
+    }
+    // output layer (every wave) and loss (rows past the batch contribute zero gradients)
+    f32x4 dz4;
+    {
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) c = mfma(w4[s], hb[s], c);
+        for (int s2 = 0; s2 < 4; ++s2) c = mfma(f4[s2], hb[s2], c);
         const float *b4 = theta + d.b_off[3];
+        float sq = 0.0f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int o = 4 * g + j;
             float e = 0.0f;
             if (valid && o < d.out[3]) e = (c[j] + b4[o]) - tg[j];
             sq += e * e;
-            dz[0][j] = gscale * e;
+            dz4[j] = gscale * e;
         }
+        if (w == 0) {
 #pragma unroll
-        for (int mt = 1; mt < 8; ++mt) dz[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
+            if (lane == 0) lpart[blockIdx.x] = sq;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[3] + 4 * g + j) * ld + b] = dz4[j];
+        }
+    }
+    // ---- backward: layer 4's output gradient to layer 3's (one K step), then layers 3, 2
+    f32x4 dz[2];
+    {
+        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+        const Frag db = pack_pair(dz4, zero);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            c = mfma(g4[t], db, c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dz[t][j] = c[j] * dg[2][t][j];
+        }
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
-    if (lane == 0) lpart[blockIdx.x] = sq;
-
-    // backward, layer 4 down to 1: store each output gradient, then form the next one
+    for (int L = 2; L >= 0; --L) {
 #pragma unroll
-    for (int L = 3; L >= 0; --L) {
-        const int MT = L == 3 ? 1 : 8;
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt)
-            if (mt < MT)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[L] + 16 * mt + 4 * g + j) * ld + b] = dz[mt][j];
+            for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[L] + 16 * (2 * w + t) + 4 * g + j) * ld + b] = dz[t][j];
         if (L > 0) {
-            const int KT = (L == 3) ? 1 : 4;
-            // the layer's weight operands and the GELU derivatives requested together
-            Frag w[32];
-#pragma unroll
-            for (int t = 0; t < 32; ++t)
-                if (t < 8 * KT) w[t] = load_frag(bw, kBwdBase[L] + t, lane);
-            f32x4 dgv[8];
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) dgv[mt][j] = DZt[(int64_t)(kDOff[L - 1] + 16 * mt + 4 * g + j) * ld + b];
             Frag db[4];
+            exchange(pack_pair(dz[0], dz[1]), db);
+            const Frag *gl = L == 2 ? g3 : g2;
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-                if (s < KT) db[s] = pack_pair(dz[2 * s], dz[2 * s + 1]);
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
+            for (int t = 0; t < 2; ++t) {
                 f32x4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    if (s < KT) c = mfma(w[mt * KT + s], db[s], c);
+                for (int s2 = 0; s2 < 4; ++s2) c = mfma(gl[4 * t + s2], db[s2], c);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) dz[mt][j] = c[j] * dgv[mt][j];
+                for (int j = 0; j < 4; ++j) dz[t][j] = c[j] * dg[L - 1][t][j];
             }
         }
     }
@@ -663,7 +703,7 @@ hipError_t launch_mlp_train(const void *frags, const float *theta, const MlpDims
 {
     const int ld = mlp_ld(batch);
     const float gscale = (float)(2.0 / ((double)batch * d.out[3]));
-    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)(ld / 16)), dim3(64), 0, s, (const Frag *)frags, theta, d, X, T,
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)(ld / 16)), dim3(256), 0, s, (const Frag *)frags, theta, d, X, T,
                        n, start, batch, gscale, Ht, DZt, ld, lpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
