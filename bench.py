@@ -518,11 +518,20 @@ def mlp_timing(s, w, dev, steps=50):
         s.mlp_predict_dev(out)
     s.mlp_train_dev(X, T, steps=steps, batch=4096, lr=2e-4)
     torch.cuda.synchronize()
-    s.set_params(profile=0)
     f_ms, f_n = s.kernel_stats("mlp_forward")
     ft_ms, _ = s.kernel_stats("features")
     t_ms, t_n = s.kernel_stats("mlp_train")
     u_ms, _ = s.kernel_stats("mlp_update")
+    # the same kernels on the largest batch the library takes (65,536 rows): what they reach
+    # once a step has work for the whole chip (the 4096-row steps the training uses are
+    # bound by the latency of their dependent stages); lr = 0 leaves the weights unchanged
+    big = min(65536, X.shape[0])
+    s.reset_kernel_stats()
+    s.mlp_train_dev(X, T, steps=10, batch=big, lr=0.0)
+    torch.cuda.synchronize()
+    s.set_params(profile=0)
+    bt_ms, bt_n = s.kernel_stats("mlp_train")
+    bu_ms, _ = s.kernel_stats("mlp_update")
     fwd_ms, tr_ms, up_ms = f_ms / f_n, t_ms / t_n, u_ms / t_n
     fwd_tf = fwd_f * w.n_points / (fwd_ms * 1e-3) / 1e12
     # "train": the forward/backward and weight-gradient kernels of one step; "step": with
@@ -534,10 +543,14 @@ def mlp_timing(s, w, dev, steps=50):
          "train_batch": 4096, "train_kernel_ms": tr_ms, "update_ms": up_ms,
          "train_tflops": tr_tf, "train_mfma_frac": tr_tf / PEAK_BF16_MFMA_TFLOPS,
          "train_step_ms": tr_ms + up_ms, "train_step_mfma_frac": st_tf / PEAK_BF16_MFMA_TFLOPS,
+         "large_batch": {"rows": big, "train_kernel_ms": bt_ms / bt_n, "update_ms": bu_ms / bt_n,
+                         "train_tflops": train_f * big / (bt_ms / bt_n * 1e-3) / 1e12,
+                         "train_mfma_frac": train_f * big / (bt_ms / bt_n * 1e-3) / 1e12 / PEAK_BF16_MFMA_TFLOPS},
          "flops_per_row": {"forward": fwd_f, "train": train_f}, "peak_tflops": PEAK_BF16_MFMA_TFLOPS}
     log(f"mlp: forward {fwd_ms:.3f} ms for {w.n_points} rows ({fwd_tf:.1f} TFLOP/s), features "
         f"{ft_ms / f_n:.3f} ms; train step {tr_ms:.3f} + {up_ms:.3f} ms ({tr_tf:.1f} TFLOP/s, "
-        f"{st_tf:.1f} with the update)")
+        f"{st_tf:.1f} with the update); {big}-row step {bt_ms / bt_n:.3f} + {bu_ms / bt_n:.3f} ms "
+        f"({train_f * big / (bt_ms / bt_n * 1e-3) / 1e12:.1f} TFLOP/s)")
     return r
 
 
