@@ -285,33 +285,6 @@ __device__ inline Frag input_frag(const float *__restrict__ X, int64_t row, bool
     return f;
 }
 
-// Hidden layer L (1 or 2, 0-based index into the dims) from B operands hb[4] to new
-// pre-activations acc[8] (bias added).  The layer's 32 weight operands and its biases are
-// requested together before the first product, so that the wave waits for memory once
-// per layer rather than once per product.
-__device__ inline void hidden_layer(const Frag *__restrict__ fw, int L, const Frag (&hb)[4], const float *__restrict__ bias,
-                                    int lane, f32x4 (&acc)[8])
-{
-    const int g = lane >> 4;
-    Frag w[32];
-#pragma unroll
-    for (int t = 0; t < 32; ++t) w[t] = load_frag(fw, kFwdBase[L] + t, lane);
-    f32x4 bv[8];
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[mt][j] = bias[16 * mt + 4 * g + j];
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
-        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) c = mfma(w[mt * 4 + s], hb[s], c);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c[j] += bv[mt][j];
-        acc[mt] = c;
-    }
-}
-
 }  // namespace
 
 // Inference: each wave evaluates NT tiles of 16 rows.  X [n][8] standardised inputs,
@@ -438,18 +411,24 @@ constexpr int kDOff[4] = {0, kHid, 2 * kHid, 3 * kHid};            // output gra
 // weight-gradient tiles (16 outputs x 16 inputs): L1 8 x 1, L2 8 x 8, L3 8 x 8, L4 1 x 8
 constexpr int kTileBase[5] = {0, 8, 72, 136, 144};
 constexpr int kTiles = 144;
-constexpr int kMaxChunks = 8;
+constexpr int kChunkRows = 256;   // batch rows per weight-gradient chunk (more chunks up to kMaxChunks)
+constexpr int kMaxChunks = 128;
 
 // (rows padded to 32, row chunks) of a batch
 __host__ __device__ inline int mlp_ld(int batch) { return (batch + 31) / 32 * 32; }
-inline int mlp_chunks(int ld) { return ld / 32 < kMaxChunks ? ld / 32 : kMaxChunks; }
+inline int mlp_chunks(int ld)
+{
+    const int c = (ld + kChunkRows - 1) / kChunkRows;
+    return c < kMaxChunks ? c : kMaxChunks;
+}
 
 // Forward and backward of 16 batch rows by a workgroup of four waves: wave w computes
 // output tiles 2w and 2w+1 of every 128-wide layer, whose packed pair is exactly K step w
 // of the next product's B operand; the waves exchange those operands through LDS (two
 // buffers used in turn, one barrier per exchange).  The output layer (one tile) is
 // computed by every wave, so that each holds the output gradient; wave 0 alone writes it
-// and the loss.  Every weight operand a wave needs (40 of them) is requested at the start.
+// and the loss.  Every weight operand a wave needs (40 of them) is requested at the start
+// and kept in registers while the workgroup takes tiles of 16 rows in grid stride.
 __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const Frag *__restrict__ frags, const float *__restrict__ theta,
                                                      MlpDims d, const float *__restrict__ X,
                                                      const float *__restrict__ Tg, int64_t n, int64_t start,
@@ -461,9 +440,6 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const Frag *__restrict__ fra
     const Frag *bw = frags + (int64_t)kFwdFrags * 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4;
-    const int64_t b = (int64_t)blockIdx.x * 16 + i;   // batch row: the tiles' column i
-    const bool valid = b < batch;
-    const int64_t row = valid ? (start + b) % n : 0;
 
     // weight operands: forward layer 1 (tiles 2w, 2w+1), layers 2 and 3 (those tiles, K
     // steps 0..3), the output layer (K steps 0..3); backward of layers 4, 3, 2 (the wave's
@@ -485,18 +461,6 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const Frag *__restrict__ fra
         g3[t] = load_frag(bw, kBwdBase[2] + 8 * w + t, lane);
         g2[t] = load_frag(bw, kBwdBase[1] + 8 * w + t, lane);
     }
-    float tg[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int o = 4 * g + j;
-        tg[j] = (valid && o < d.out[3]) ? Tg[row * d.out[3] + o] : 0.0f;
-    }
-
-    const Frag xb = input_frag(X, row, valid, g);
-    if (w == 0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Ht[(int64_t)(kHOff[0] + 4 * g + j) * ld + b] = xb.v[j];
-    }
     int buf = 0;
     // exchange: this wave's packed pair in, the four K steps out
     auto exchange = [&](const Frag &mine, Frag (&all)[4]) {
@@ -507,105 +471,124 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const Frag *__restrict__ fra
         buf ^= 1;
     };
 
-    // ---- forward
-    f32x4 z[2];
-    {
-        const float *b1 = theta + d.b_off[0];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            f32x4 c = {0.f, 0.f, 0.f, 0.f};
-            c = mfma(f1[t], xb, c);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) c[j] += b1[16 * (2 * w + t) + 4 * g + j];
-            z[t] = c;
-        }
-    }
-    f32x4 dg[3][2];   // GELU derivatives of the wave's tiles, hidden layers 1..3
-    Frag hb[4];
-#pragma unroll
-    for (int L = 0; L < 3; ++L) {
-        Frag mine;
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int mt = 2 * w + t;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const GeluPair q = gelu_pair(z[t][j]);
-                const unsigned short hv = bf16_bits(q.h);
-                Ht[(int64_t)(kHOff[L + 1] + 16 * mt + 4 * g + j) * ld + b] = hv;
-                mine.v[4 * t + j] = hv;
-                dg[L][t][j] = q.dh;
-            }
-        }
-        exchange(mine, hb);
-        if (L < 2) {
-            const Frag *fl = L == 0 ? f2 : f3;
-            const float *bL = theta + d.b_off[L + 1];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s2 = 0; s2 < 4; ++s2) c = mfma(fl[4 * t + s2], hb[s2], c);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) c[j] += bL[16 * (2 * w + t) + 4 * g + j];
-                z[t] = c;
-            }
-        }
-    }
-    // output layer (every wave) and loss (rows past the batch contribute zero gradients)
-    f32x4 dz4;
-    {
-        f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) c = mfma(f4[s2], hb[s2], c);
-        const float *b4 = theta + d.b_off[3];
-        float sq = 0.0f;
+    // tiles of 16 rows, the workgroup's weights kept in registers from one to the next
+    const int64_t n_tiles = ld / 16;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t b = tile * 16 + i;   // batch row: the tiles' column i
+        const bool valid = b < batch;
+        const int64_t row = valid ? (start + b) % n : 0;
+        float tg[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int o = 4 * g + j;
-            float e = 0.0f;
-            if (valid && o < d.out[3]) e = (c[j] + b4[o]) - tg[j];
-            sq += e * e;
-            dz4[j] = gscale * e;
+            tg[j] = (valid && o < d.out[3]) ? Tg[row * d.out[3] + o] : 0.0f;
         }
+
+        const Frag xb = input_frag(X, row, valid, g);
         if (w == 0) {
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
-            if (lane == 0) lpart[blockIdx.x] = sq;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[3] + 4 * g + j) * ld + b] = dz4[j];
+            for (int j = 0; j < 4; ++j) Ht[(int64_t)(kHOff[0] + 4 * g + j) * ld + b] = xb.v[j];
         }
-    }
-    // ---- backward: layer 4's output gradient to layer 3's (one K step), then layers 3, 2
-    f32x4 dz[2];
-    {
-        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-        const Frag db = pack_pair(dz4, zero);
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            f32x4 c = {0.f, 0.f, 0.f, 0.f};
-            c = mfma(g4[t], db, c);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) dz[t][j] = c[j] * dg[2][t][j];
-        }
-    }
-#pragma unroll
-    for (int L = 2; L >= 0; --L) {
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[L] + 16 * (2 * w + t) + 4 * g + j) * ld + b] = dz[t][j];
-        if (L > 0) {
-            Frag db[4];
-            exchange(pack_pair(dz[0], dz[1]), db);
-            const Frag *gl = L == 2 ? g3 : g2;
+        // ---- forward
+        f32x4 z[2];
+        {
+            const float *b1 = theta + d.b_off[0];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 f32x4 c = {0.f, 0.f, 0.f, 0.f};
+                c = mfma(f1[t], xb, c);
 #pragma unroll
-                for (int s2 = 0; s2 < 4; ++s2) c = mfma(gl[4 * t + s2], db[s2], c);
+                for (int j = 0; j < 4; ++j) c[j] += b1[16 * (2 * w + t) + 4 * g + j];
+                z[t] = c;
+            }
+        }
+        f32x4 dg[3][2];   // GELU derivatives of the wave's tiles, hidden layers 1..3
+        Frag hb[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) dz[t][j] = c[j] * dg[L - 1][t][j];
+        for (int L = 0; L < 3; ++L) {
+            Frag mine;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int mt = 2 * w + t;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const GeluPair q = gelu_pair(z[t][j]);
+                    const unsigned short hv = bf16_bits(q.h);
+                    Ht[(int64_t)(kHOff[L + 1] + 16 * mt + 4 * g + j) * ld + b] = hv;
+                    mine.v[4 * t + j] = hv;
+                    dg[L][t][j] = q.dh;
+                }
+            }
+            exchange(mine, hb);
+            if (L < 2) {
+                const Frag *fl = L == 0 ? f2 : f3;
+                const float *bL = theta + d.b_off[L + 1];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2) c = mfma(fl[4 * t + s2], hb[s2], c);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) c[j] += bL[16 * (2 * w + t) + 4 * g + j];
+                    z[t] = c;
+                }
+            }
+        }
+        // output layer (every wave) and loss (rows past the batch contribute zero gradients)
+        f32x4 dz4;
+        {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) c = mfma(f4[s2], hb[s2], c);
+            const float *b4 = theta + d.b_off[3];
+            float sq = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = 4 * g + j;
+                float e = 0.0f;
+                if (valid && o < d.out[3]) e = (c[j] + b4[o]) - tg[j];
+                sq += e * e;
+                dz4[j] = gscale * e;
+            }
+            if (w == 0) {
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
+                if (lane == 0) lpart[tile] = sq;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[3] + 4 * g + j) * ld + b] = dz4[j];
+            }
+        }
+        // ---- backward: layer 4's output gradient to layer 3's (one K step), then layers 3, 2
+        f32x4 dz[2];
+        {
+            const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+            const Frag db = pack_pair(dz4, zero);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                f32x4 c = {0.f, 0.f, 0.f, 0.f};
+                c = mfma(g4[t], db, c);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dz[t][j] = c[j] * dg[2][t][j];
+            }
+        }
+#pragma unroll
+        for (int L = 2; L >= 0; --L) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) DZt[(int64_t)(kDOff[L] + 16 * (2 * w + t) + 4 * g + j) * ld + b] = dz[t][j];
+            if (L > 0) {
+                Frag db[4];
+                exchange(pack_pair(dz[0], dz[1]), db);
+                const Frag *gl = L == 2 ? g3 : g2;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2) c = mfma(gl[4 * t + s2], db[s2], c);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) dz[t][j] = c[j] * dg[L - 1][t][j];
+                }
             }
         }
     }
@@ -703,7 +686,9 @@ hipError_t launch_mlp_train(const void *frags, const float *theta, const MlpDims
 {
     const int ld = mlp_ld(batch);
     const float gscale = (float)(2.0 / ((double)batch * d.out[3]));
-    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)(ld / 16)), dim3(256), 0, s, (const Frag *)frags, theta, d, X, T,
+    // up to 1024 workgroups (four per CU), each taking every 1024th tile of 16 rows
+    const int grid = ld / 16 < 1024 ? ld / 16 : 1024;
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)grid), dim3(256), 0, s, (const Frag *)frags, theta, d, X, T,
                        n, start, batch, gscale, Ht, DZt, ld, lpart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -727,10 +712,18 @@ __global__ void k_mlp_update(float *__restrict__ theta, float *__restrict__ m, f
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t np = d.n_params;
-    if (p == 0 && loss) {
+    if (blockIdx.x == 0 && loss) {
+        // the loss partials: thread t sums entries t, t + 256, ... in order, then a fixed tree
+        __shared__ float red[256];
         float sacc = 0.0f;
-        for (int w = 0; w < n_waves; ++w) sacc += lpart[w];
-        *loss = sacc * inv_count;
+        for (int w = threadIdx.x; w < n_waves; w += blockDim.x) sacc += lpart[w];
+        red[threadIdx.x] = sacc;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *loss = red[0] * inv_count;
     }
     if (p >= np) return;
     float gsum = 0.0f;
