@@ -582,6 +582,8 @@ def main():
     ap.add_argument("--train-sample", type=int, default=None,
                     help="rows taken from each training model (default: every point of the disc family's "
                          "training discs for disc10, else 20000)")
+    ap.add_argument("--mlp-only", action="store_true",
+                    help="only the warm-start network's kernels (seeded weights, synthetic rows) on the workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (4 launches), "
                          "the calibration kernel for HBM byte counters")
@@ -644,6 +646,18 @@ def main():
 
     dev = torch.device("cuda:0")
     P, nlev, nl = w.n_points, w.species.n_lev, w.species.n_lines
+    if args.mlp_only:
+        import numpy as np
+        # the network's kernels alone: seeded Glorot weights, unit standardisation, 131,072
+        # seeded synthetic rows (inputs and targets standard normal); prints the mlp object
+        s.mlp_init(nlev, seed=1)
+        s.mlp_set_norm(np.zeros(8), np.ones(8))
+        g = torch.Generator(device="cpu").manual_seed(7)
+        X = torch.randn((131072, 8), generator=g, dtype=torch.float32).to(dev)
+        T = torch.randn((131072, nlev), generator=g, dtype=torch.float32).to(dev)
+        s._bench_rows = [(X, T)]
+        print(json.dumps({"workload": w.name, "mlp": mlp_timing(s, w, dev)}), flush=True)
+        return
     pops = torch.empty((P, nlev), dtype=torch.float64, device=dev)
     new = torch.empty_like(pops)
     J, Je, L = [torch.empty((P, nl), dtype=torch.float64, device=dev) for _ in range(3)]
