@@ -41,7 +41,8 @@ struct Bulk<true> {
 // x_q at this node as x = a x_q - b.  The segment to the next node toward O has m
 // sub-intervals of length 2 sqrt(2) dzq; per sub-interval x changes by da x_q - db.  maxdx
 // bounds |dx| over all frequencies, K is the restart interval of the profile recurrence
-// (0: evaluate every profile directly).  kap, S: line-centre opacity and source function
+// (0: evaluate every profile directly) in the long-segment mode and, in the short mode,
+// which has no recurrence, the number of segments without sub-steps from this node on.  kap, S: line-centre opacity and source function
 // of the wave's lines.
 template <typename T, int NLW>
 struct NodeRec {
@@ -176,13 +177,22 @@ __device__ __forceinline__ void elim_p(double Pp, double S_row, HalfState &st)
     st.Hm = Pp;
 }
 
+// short_node skips the profile's exponential where the whole wave is beyond its range
+// if SHORT_VOTE is set.  It is not: the vote is a wave-wide branch on a vector result at
+// every node, whose wait costs more than the exponentials it saves on a disc.  For the
+// same reason the segment loop checks for rescaling after every second node only (every
+// fourth measured slower: its extra test costs more than the check), and tests for the
+// end of a run on a scalar count taken at the run's start rather than on the next staged
+// record (disc10 FP64 sweep 5.50 -> 4.90 s for the three together).
+constexpr bool SHORT_VOTE = false;
+
 // One segment without sub-steps, to staged node r1 (the segment's dzq given): the
 // profile g1 of this lane at r1, r1's kappa and S of the lane's lines (k1, S1), and every
 // line's step with P = (kappa_0 g0 + kappa_1 g1) dzq and the row source S0 (in FP32 formed
 // as the general path forms it, so that both segment modes give the same bits).  A loop over
 // segments that calls this twice per iteration with the (g, k, S) sets swapped copies no
 // registers between segments.
-template <bool F32, int LPL>
+template <bool F32, int LPL, bool CHECK = true>
 __device__ __forceinline__ void short_node(const NodeRec<typename Bulk<F32>::T, 2 * LPL> &r1,
                                            typename Bulk<F32>::T dzq, typename Bulk<F32>::T xq,
                                            const double *tab, int grp, typename Bulk<F32>::T g0,
@@ -192,7 +202,10 @@ __device__ __forceinline__ void short_node(const NodeRec<typename Bulk<F32>::T, 
 {
     using T = typename Bulk<F32>::T;
     const T xn = r1.a * xq - r1.b;
-    g1 = profile_far(xn, tab);
+    if constexpr (SHORT_VOTE)
+        g1 = profile_far(xn, tab);
+    else
+        g1 = profile(xn, tab);
 #pragma unroll
     for (int l = 0; l < LPL; ++l) {
         const int c = grp * LPL + l;
@@ -205,7 +218,19 @@ __device__ __forceinline__ void short_node(const NodeRec<typename Bulk<F32>::T, 
             Pp = fma(k0[l], g0, k1[l] * g1) * dzq;
         elim_p((double)Pp, (double)S0[l], ls.st[l]);
     }
-    rescale_if_big<LPL, false>(ls);
+    if (CHECK) rescale_if_big<LPL, false>(ls);
+}
+
+// The profile at a sub-step node: with the far-wing vote in the long-segment mode, without
+// it in the short mode (whose segments are rarely all in the far wing; the vote's branch
+// costs more there than the exponentials it saves).
+template <bool COLLAPSE, typename T>
+__device__ __forceinline__ T profile_sub(T x, const double *tab)
+{
+    if constexpr (COLLAPSE)
+        return profile_far(x, tab);
+    else
+        return profile(x, tab);
 }
 
 // Runs of segments without sub-steps take the loop of short_node (not in the long-segment
@@ -280,6 +305,7 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
         }
         const double Zn = __shfl_down(Zs, 1), sn = __shfl_down(sv, 1), vwn = __shfl_down(vw, 1);
         const double an1 = __shfl_down(an, 1), bn1 = __shfl_down(bn, 1);
+        int m_seg = 1;   // sub-intervals of this lane's segment (1 where it has none)
         if (load) {
             NodeRec<T, NLW> r;
             r.a = (T)an;
@@ -306,6 +332,7 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                     m = mr < (double)kMaxSub ? (int)mr : kMaxSub;
                 }
                 const double im = 1.0 / (double)m;
+                m_seg = m;
                 r.m = m;
                 r.inv_m = (T)im;
                 r.dzq = (T)(kInv2Sqrt2 * (Zs - Zn) * im);
@@ -318,6 +345,14 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                 r.K = maxdx > 4.0 ? 0 : (maxdx > 0.25 ? (int)(16.0 / maxdx) : 64);
             }
             rec[lane] = r;
+        }
+        if (!COLLAPSE) {
+            // short mode has no recurrence: K holds the number of segments without sub-steps
+            // from this node on within the round (the trailing zeros of the wave's mask of
+            // segments with sub-steps or past the round's last)
+            const int nseg_r = min(ns - 1, L - b0);
+            const unsigned long long brk = __ballot(!(lane < nseg_r && m_seg == 1));
+            if (load) rec[lane].K = (int)__builtin_ctzll(brk >> lane);
         }
         __syncthreads();
         // ---- sweep the staged segments
@@ -343,11 +378,17 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                     kA[l] = ls.k_cur[l];
                     SA[l] = ls.S_e[l];
                 }
+                // the run's length is known at its start (>= 1): the test between segments is on a
+                // scalar count, not on the next record
+                int run = rec[i].K;
+                // two segments per iteration (the sets alternate A -> B -> A ...); the state is
+                // checked for rescaling after the second and where the run ends
                 for (;;) {
-                    short_node<F32, LPL>(rec[i + 1], rec[i].dzq, xq, tab, grp, gA, gB, kA, kB, SA, SB, ls);
+                    short_node<F32, LPL, false>(rec[i + 1], rec[i].dzq, xq, tab, grp, gA, gB, kA, kB, SA, SB, ls);
                     ++nexec;
                     ++i;
-                    if (i >= nseg || rec[i].m != 1) {
+                    if (--run == 0) {
+                        rescale_if_big<LPL, false>(ls);
                         gA = gB;
 #pragma unroll
                         for (int l = 0; l < LPL; ++l) {
@@ -356,10 +397,11 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                         }
                         break;
                     }
-                    short_node<F32, LPL>(rec[i + 1], rec[i].dzq, xq, tab, grp, gB, gA, kB, kA, SB, SA, ls);
+                    short_node<F32, LPL, false>(rec[i + 1], rec[i].dzq, xq, tab, grp, gB, gA, kB, kA, SB, SA, ls);
                     ++nexec;
                     ++i;
-                    if (i >= nseg || rec[i].m != 1) break;
+                    rescale_if_big<LPL, false>(ls);
+                    if (--run == 0) break;
                 }
                 g_cur = gA;
                 x_cur = rec[i].a * xq - rec[i].b;   // the same bits as the last xn
@@ -467,13 +509,13 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                     int j = 1;
                     for (; j + 1 < m; j += 2) {
                         const T t1 = (T)j, t2 = (T)(j + 1);
-                        const T g1 = profile_far(fma(t1, dx, x_cur), tab) * dzq;
+                        const T g1 = profile_sub<COLLAPSE>(fma(t1, dx, x_cur), tab) * dzq;
 #pragma unroll
                         for (int l = 0; l < LPL; ++l) {
                             aB[l] = fma(t1, dk[l], ls.k_cur[l]) * g1;
                             elim_p((double)(a_prev[l] + aB[l]), (double)fma(t1 - (T)1, dS[l], S0[l]), ls.st[l]);
                         }
-                        const T g2 = profile_far(fma(t2, dx, x_cur), tab) * dzq;
+                        const T g2 = profile_sub<COLLAPSE>(fma(t2, dx, x_cur), tab) * dzq;
 #pragma unroll
                         for (int l = 0; l < LPL; ++l) {
                             a_prev[l] = fma(t2, dk[l], ls.k_cur[l]) * g2;
@@ -483,7 +525,7 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                     }
                     if (j < m) {
                         const T t1 = (T)j;
-                        const T g1 = profile_far(fma(t1, dx, x_cur), tab) * dzq;
+                        const T g1 = profile_sub<COLLAPSE>(fma(t1, dx, x_cur), tab) * dzq;
 #pragma unroll
                         for (int l = 0; l < LPL; ++l) {
                             aB[l] = fma(t1, dk[l], ls.k_cur[l]) * g1;
@@ -494,7 +536,7 @@ __device__ __forceinline__ void half_sweep(const SolveArgs &a, NodeRec<typename 
                     // the source of the last sub-node, whose row the end node's step eliminates
 #pragma unroll
                     for (int l = 0; l < LPL; ++l) ls.S_e[l] = fma((T)(m - 1), dS[l], S0[l]);
-                    gn = profile_far(xn, tab);
+                    gn = profile_sub<COLLAPSE>(xn, tab);
                     travel = 0.0;
                 } else if ((TRACK || !LEAN_SUBSTEPS<F32, COLLAPSE>) && (F32 || !COLLAPSE || K == 0 || m <= 2)) {
                     T S0[LPL], dk[LPL], dS[LPL];
