@@ -163,10 +163,12 @@ nlte_status ensure_work(nlte_ctx *c)
 void set_launch_shape(nlte_ctx *c, SolveArgs &a, bool fp32)
 {
     const int lpl = a.lines_per_wave / a.ngrp;
-    // by rule: 3 waves per SIMD up to two lines per lane, else 2 (measured on the disc: the
-    // whole register file for one wave removes the spills of five FP64 lines per lane but
-    // leaves too little to hide latency)
-    a.waves = (c->cfg.waves >= 1 && c->cfg.waves <= 3) ? c->cfg.waves : (lpl <= 2 ? 3 : 2);
+    // by rule: 3 waves per SIMD in FP32 and up to two lines per lane in FP64, else 2
+    // (measured on the disc: the whole register file for one wave removes the spills of
+    // five FP64 lines per lane but leaves too little to hide latency; five FP64 lines at
+    // three waves spill inside the node loops; five FP32 lines fit three waves with a few
+    // spills outside them, and the third wave takes the disc's FP32 sweep from 4.0 to 3.5 s)
+    a.waves = (c->cfg.waves >= 1 && c->cfg.waves <= 3) ? c->cfg.waves : ((lpl <= 2 || fp32) ? 3 : 2);
     // long-segment mode (profile recurrence, far-wing collapse) where sub-step segments are
     // long: more than two elimination steps per cached cell on average
     a.collapse = c->cfg.long_seg >= 0 ? c->cfg.long_seg : (c->total_steps > 2 * c->total_cells ? 1 : 0);

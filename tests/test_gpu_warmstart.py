@@ -80,7 +80,9 @@ def test_mfma_forward_matches_oracle(n_rows, n_out):
         assert np.median(np.abs(Y - R64)) > 10 * np.median(d)
 
 
-@pytest.mark.parametrize("n_rows,n_out", [(64, 10), (300, 5), (1000, 10)])
+# (4099 rows: a ragged last tile and chunk; 20000 rows: more tiles of 16 rows than the
+# forward/backward kernel's 1024 workgroups, each taking several, and 79 row chunks)
+@pytest.mark.parametrize("n_rows,n_out", [(64, 10), (300, 5), (1000, 10), (4099, 16), (20000, 7)])
 def test_gradient_matches_oracle(n_rows, n_out):
     s, theta = _net_solver(n_out, seed=100 + n_rows)
     rng = np.random.default_rng(n_rows)
