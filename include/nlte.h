@@ -69,9 +69,11 @@ typedef struct {
                            its profile evaluations.  0 */
     int waves_per_simd; /* formal-solve register budget: 1, 2 or 3 waves per SIMD (1: the whole
                            register file, 512 with the accumulation registers; 3: 168);
-                           0 = by rule (3 up to two lines per lane, else 2).  0 */
+                           0 = by rule (3 in the FP32 form and up to two lines per lane in
+                           FP64, else 2).  0 */
     int persistent;   /* 1: persistent formal solve taking points from a work queue in
-                         decreasing order of their cached step counts.  0 */
+                         decreasing order of their cached step counts; 0: one workgroup per
+                         tile of points in index order (XCD-contiguous).  1 */
     int ng_every;     /* Ng acceleration (Sec. 3.4): after every ng_every regular ALI
                          iterations each model still iterating takes the combination of its
                          last ng_every - 1 iterates, summing to one, that minimises the same
