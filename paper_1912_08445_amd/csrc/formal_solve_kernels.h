@@ -21,8 +21,9 @@ namespace nlte {
 constexpr double kSqrt2 = 1.41421356237309504880;
 constexpr double kInv2Sqrt2 = 0.35355339059327376220;  // 1 / (2 sqrt 2)
 // The elimination state only grows (see elim_step); it is rescaled by a power of two once
-// any line's D passes 2^300, checked after every node and at least every fourth sub-step,
-// which leaves room for steps with D_+ up to about 2^70 before the FP64 range ends.
+// any line's D passes 2^300, checked after every node (every second node in the short
+// mode's segment loop) and at least every fourth sub-step, which leaves room for steps
+// with D_+ up to about 2^70 before the FP64 range ends.
 // Power-of-two rescaling is exact, so when it happens does not change any result.
 constexpr double kRenormAbove = 2.0370359763344861e90;   // 2^300
 
