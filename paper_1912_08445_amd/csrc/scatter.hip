@@ -36,7 +36,11 @@
 // profile follows the multiplicative recurrence of the line formal solve (exact restarts
 // after at most 16 widths of travel) and, on an evenly spaced quadrature, the position
 // of +-y advances by a constant; the state is renormalised at every cell node and every
-// fourth sub-step.  Besides J, L* (times chi_line/chi_t) and Jeff it returns Jw at the
+// fourth sub-step.  With isotropic scattering two kinds of sub-step segment take shorter
+// forms: where every lane's lookups clamp, Jw is linear along the segment and the node values
+// come from the running Jbar - S and dJ; in the far wing (no line opacity) every node value
+// is linear in the sub-node index, so from the third sub-node on the differences across the
+// eliminated node are constants.  Besides J, L* (times chi_line/chi_t) and Jeff it returns Jw at the
 // quadrature offsets from u and v at the origin: I(n, x) = u(x) + v(x) and
 // I(-n, x) = u(-x) - v(-x) for the pair representative n, weighted by w(+-n) of the origin.
 #include <type_traits>
@@ -189,13 +193,13 @@ struct SNode {
 
 // Segment from a staged node to the next: m sub-intervals of optical-depth weight
 // hz = (Z - Z_next)/(2 sqrt 2 m), per sub-interval increments of the Doppler coefficients
-// and of kappa, S and chi_s; maxdx bounds |dy| over the quadrature, K is the restart
-// interval of the profile recurrence (0: direct evaluation).
+// and of kappa, S and chi_s; maxdx bounds |dy| over the quadrature (imdx = 1/maxdx, 0 for
+// none), K is the restart interval of the profile recurrence (0: direct evaluation).
 // With an odd opacity: per sub-interval the increment dcm of cm, the path length ds, and
 // the frame factor e^{-dM} of the first sub-interval (f0) and its ratio between successive
 // ones (rho), dM = ds (cm_j + cm_{j+1})/2 being linear in the sub-interval index.
 struct SSeg {
-    double hz, da, db, im, maxdx, ds;
+    double hz, da, db, im, maxdx, imdx, ds;
     double dk[2], dS[2], dcs[2], dcm[2], f0[2], rho[2];
     int m, K;
 };
@@ -226,6 +230,22 @@ __device__ __forceinline__ NodeVal node_val(double cl, double cs, double cm, dou
         v.Sp = fma(0.5 * rm, jm - jp, v.Sp);
         v.sq = fma(0.5 * kISq2 * rm, jp + jm, v.sq);
     }
+    return v;
+}
+
+// The same where Jw is linear along a segment (its lookups clamp), from the running
+// D = Jbar - S and Q = (Jw(-y) - Jw(y)) / (2 sqrt 2), themselves linear in the sub-node index:
+// S+ = S + r D, sigma~ / sqrt 2 = r Q (isotropic scattering).
+__device__ __forceinline__ NodeVal node_val_lin(double chit, double cs, double S, double D, double Q)
+{
+    NodeVal v;
+    v.chit = chit;
+    double ic = __builtin_amdgcn_rcp(chit);
+    ic = fma(ic, fma(-chit, ic, 1.0), ic);
+    ic = cs > 0.0 ? ic : 0.0;
+    const double r = cs * ic;
+    v.Sp = chit > 0.0 ? fma(r, D, S) : 0.0;
+    v.sq = r * Q;
     return v;
 }
 
@@ -307,11 +327,13 @@ __device__ __forceinline__ void step(HalfState &h, const NodeVal &v, double hz)
 // frame factor of the next sub-interval).
 struct SubRun {
     double g, r, kq, cs, cm, S, pos, tt, f;
+    double D, Q;   // clamped lookups, isotropic: node_val_lin's D and Q
 };
 
 // Jw end values of a segment whose lookups clamp: +y lookups a + t da, -y lookups a_m + t da_m.
 struct JEnds {
     double ap, dap, am, dam;
+    double dD, dQ;   // per sub-interval changes of node_val_lin's D and Q
 };
 
 template <bool UNI, bool ANISO, bool CLAMP, bool RENORM>
@@ -324,6 +346,12 @@ __device__ __forceinline__ void sub_step(HalfState &h, SubRun &w, double c, doub
     w.kq += dk;
     w.cs += dcs;
     w.S += dS;
+    if constexpr (CLAMP && !ANISO) {
+        w.D += je.dD;
+        w.Q += je.dQ;
+        step<RENORM>(h, node_val_lin(fma(w.kq, w.g, w.cs), w.cs, w.S, w.D, w.Q), hz);
+        return;
+    }
     w.tt += im;
     if (ANISO) w.cm += dcm;
     double jp, jm;
@@ -424,6 +452,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                 }
             }
             e.maxdx = (fabs(q.a - p.a) * xq_max + fabs(q.b - p.b)) * e.im;
+            e.imdx = e.maxdx > 0.0 ? 1.0 / e.maxdx : 0.0;
             e.K = e.maxdx > 4.0 ? 0 : (e.maxdx > 0.25 ? (int)(16.0 / e.maxdx) : 64);
             sgm[t] = e;
         }
@@ -465,7 +494,7 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                 const double dy = sgm[i].da * x - sgm[i].db;
                 const double dk = sgm[i].dk[gs], dS = sgm[i].dS[gs], dcs = sgm[i].dcs[gs], im = sgm[i].im;
                 const double dcm = ANISO ? sgm[i].dcm[gs] : 0.0, rho = ANISO ? sgm[i].rho[gs] : 1.0;
-                const double mdx = sgm[i].maxdx;
+                const double mdx = sgm[i].maxdx, imdx = sgm[i].imdx;
                 const int K = sgm[i].K;
                 // Every lane's offsets beyond the quadrature on one side over the whole
                 // segment (x is linear in the sub-step index): both lookups clamp to the end
@@ -516,7 +545,9 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                     // (|y| > 27) cannot hide a profile above e^{-121}
                     const double u2 = 2.0 * dy * dy;
                     const double c = mdx <= 0.5 ? exp_neg_small(u2) : exp_le700(-u2);
-                    const JEnds je{ap, dap, am, dam};
+                    // (D and Q of node_val_lin at the segment's start and their changes)
+                    const double D0 = fma(0.5, ap + am, -S_cur), Q0 = (0.5 * kISq2) * (am - ap);
+                    const JEnds je{ap, dap, am, dam, fma(0.5 * im, dap + dam, -dS), (0.5 * kISq2 * im) * (dam - dap)};
                     SubRun w;
                     w.g = g_cur;
                     w.r = exp_tab16(fmin(-(2.0 * y_cur + dy) * dy, 700.0), tab);
@@ -527,9 +558,11 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                     w.pos = qpos<UNI>(qg, y_cur);
                     w.tt = 0.0;
                     w.f = f;
+                    w.D = D0;
+                    w.Q = Q0;
                     const double dpos = UNI ? dy * qg.inv_h : dy;
                     int budget = K;
-                    if (mdx > 0.0) budget = (int)fmin((16.0 - travel) / mdx, (double)K);
+                    if (mdx > 0.0) budget = (int)fmin((16.0 - travel) * imdx, (double)K);
                     if (budget < 1) {
                         w.g = profile(y_cur, tab);
                         travel = 0.0;
@@ -571,6 +604,8 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                         w.cs = fma(fj, dcs, cs_cur);
                         w.S = fma(fj, dS, S_cur);
                         w.tt = fj * im;
+                        w.D = fma(fj, je.dD, D0);
+                        w.Q = fma(fj, je.dQ, Q0);
                         if (ANISO) {
                             w.cm = fma(fj, dcm, cm_cur);
                             w.f = frame_exp(sgm[i].ds * fma(fj + 0.5, dcm, cm_cur));
@@ -608,14 +643,66 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                         if (ANISO) f *= rho;
                         step_p<decltype(renorm_tag)::value>(h, v, fma(fj, dP, P0));
                     };
-                    int j = 1;
-                    for (; j + 3 < m; j += 4) {
-                        far_step(j, std::false_type{});
-                        far_step(j + 1, std::false_type{});
-                        far_step(j + 2, std::false_type{});
-                        far_step(j + 3, std::true_type{});
+                    if constexpr (ANISO) {
+                        int j = 1;
+                        for (; j + 3 < m; j += 4) {
+                            far_step(j, std::false_type{});
+                            far_step(j + 1, std::false_type{});
+                            far_step(j + 2, std::false_type{});
+                            far_step(j + 3, std::true_type{});
+                        }
+                        for (; j < m; ++j) far_step(j, std::false_type{});
+                    } else {
+                        // sub-nodes 1 and 2 by the general step: their central differences reach
+                        // back to the cell node, whose values need not lie on the line
+                        far_step(1, std::false_type{});
+                        if (m > 2) far_step(2, std::false_type{});
+                        if (m > 3) {
+                            // from sub-node 3 on both neighbours of the eliminated sub-node lie on
+                            // the line: the sigma~ and S+ differences across it are the constants
+                            // -2 dsq and -2 dSp, and P_{j-1} + P_j grows by 2 dP per sub-node
+                            double n = h.n, d = h.d, y = h.y, yv = h.yv, Sh = h.Sp, qh = h.sq;
+                            const double cy = -2.0 * dsq, cv = -dSp, dQ = 2.0 * dP, Q0 = fma(2.0, P0, -dP);
+                            double fj = 3.0;
+                            auto lean = [&](auto renorm_tag) {
+                                const double hd = fma(fj, dQ, Q0) * d;
+                                n += hd;
+                                y = fma(Sh, hd, fma(cy, d, y));
+                                yv = fma(qh, hd, fma(cv, d, yv));
+                                d = fma(fma(fj, dP, P0), n, d);
+                                Sh = fma(fj, dSp, Sp0);
+                                qh = fma(fj, dsq, sq0);
+                                fj += 1.0;
+                                if (decltype(renorm_tag)::value) {
+                                    const int ex = __builtin_amdgcn_frexp_exp(d);
+                                    n = ldexp(n, -ex);
+                                    d = ldexp(d, -ex);
+                                    y = ldexp(y, -ex);
+                                    yv = ldexp(yv, -ex);
+                                }
+                            };
+                            int j = 3;
+                            for (; j + 3 < m; j += 4) {
+                                lean(std::false_type{});
+                                lean(std::false_type{});
+                                lean(std::false_type{});
+                                lean(std::true_type{});
+                            }
+                            for (; j < m; ++j) lean(std::false_type{});
+                            // the state after sub-node m - 1, as the general step leaves it
+                            const double fl = (double)(m - 1);
+                            h.n = n;
+                            h.d = d;
+                            h.y = y;
+                            h.yv = yv;
+                            h.Pm = fma(fl, dP, P0);
+                            h.chit = fma(fl, dcs, cs_cur);
+                            h.Sp = Sh;
+                            h.sq = qh;
+                            h.Sp_pp = fma(fl - 1.0, dSp, Sp0);
+                            h.sq_pp = fma(fl - 1.0, dsq, sq0);
+                        }
                     }
-                    for (; j < m; ++j) far_step(j, std::false_type{});
                     g_n = 0.0;   // e^{-y_n^2} underflows too
                     travel = 0.0;
                 } else if (clampJ) {
@@ -648,8 +735,10 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
 
 }  // namespace
 
+// The isotropic form on an evenly spaced quadrature is held to two waves per SIMD (it then
+// needs no spill; at three it spills and runs slower); the others fit one.
 template <bool UNI, bool ANISO>
-__global__ __launch_bounds__(kScatMaxQ) void k_formal_solve_scat(ScatArgs a)
+__global__ __launch_bounds__(kScatMaxQ, (UNI && !ANISO) ? 2 : 1) void k_formal_solve_scat(ScatArgs a)
 {
     extern __shared__ double smem[];
     // lanes: with n_q <= 32 two lines per wave (lanes 32 g + frequency), else one line

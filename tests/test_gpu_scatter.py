@@ -197,6 +197,10 @@ def test_dipole_formal_solve_static_sphere_matches_oracle():
 
 
 def test_zero_dipole_is_the_isotropic_solve():
+    """A zero dipole gives the isotropic solve.  The two kernels round differently (the
+    isotropic one steps far-wing and clamped-lookup segments with their node values linear
+    in the sub-node index, the other through the general step), so they agree to 1e-12 of
+    each output's largest value, not bit for bit."""
     w = configs.outflow5(n_points=200, seed=5, nside=1)
     o = oracle_for(w)
     pops, chi_sca, Jnu = _fields(o, w, 19)
@@ -206,7 +210,7 @@ def test_zero_dipole_is_the_isotropic_solve():
     s.set_scattering_dipole(np.zeros((w.n_points, w.species.n_lines, 3)))
     b = s.formal_solve_scat(pops, Jnu)
     for x, y in zip(a, b):
-        assert np.array_equal(x, y)
+        assert np.max(np.abs(x - y)) <= 1e-12 * np.max(np.abs(x))
     # a new scattering opacity drops the dipole
     s.set_scattering_dipole(_dipole(w, chi_sca, 20))
     assert not np.array_equal(s.formal_solve_scat(pops, Jnu)[3], a[3])
