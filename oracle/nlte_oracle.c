@@ -1114,7 +1114,8 @@ static double jnu_at(const or_ctx *c, const double *Jnu, int64_t q, int l, doubl
  * chi^- = chi_dip . n there, the two directions receive (chi_sca + chi^-) Jw(y) and
  * (chi_sca - chi^-) Jw(-y), and Psi^+-, the half sum and half difference of these, give
  * with chi_tot = chi_line + chi_sca:  Splus = (chi_line S + Psi^+)/chi_tot,
- * sigma = Psi^-/chi_tot (both 0 where chi_tot = 0).  Velocity sub-steps interpolate
+ * sigma = Psi^-/chi_tot (where chi_tot = 0, Splus = S, the limit as the line opacity
+ * vanishes without scattering, and sigma = 0).  Velocity sub-steps interpolate
  * chi_sca, chi_dip . n and the Jw of the segment's end cells linearly in t, at the
  * sub-step's own offset.  Per selected point and line:
  *   J     (2/N_rays) sum_pairs sum_n w_n u_o,
@@ -1189,7 +1190,13 @@ int or_formal_solve_scat(const or_ctx *c, const double *pops, const double *chi_
                         double psi_p = (cs + cm[i]) * jp, psi_m = (cs - cm[i]) * jm;
                         double tot = cl + cs;
                         ct[i] = tot;
-                        Sp[i] = tot > 0.0 ? (cl * S[i * nl + l] + 0.5 * (psi_p + psi_m)) / tot : 0.0;
+                        /* (chi_line S + Psi^+)/chi_tot as (chi_line/chi_tot) S + Psi^+/chi_tot: the
+                         * same value, but chi_line S does not underflow where the line opacity is
+                         * denormal (without scattering the share is then exactly 1); with no
+                         * opacity at all the line's S, the limit as its opacity goes to zero, as
+                         * in the line-only solve */
+                        double share_i = tot > 0.0 ? cl / tot : 1.0;
+                        Sp[i] = share_i * S[i * nl + l] + (tot > 0.0 ? 0.5 * (psi_p + psi_m) / tot : 0.0);
                         sg[i] = tot > 0.0 ? 0.5 * (psi_p - psi_m) / tot : 0.0;
                         if (i == io) {
                             clO = cl;

@@ -211,7 +211,8 @@ struct NodeVal {
 
 // S+ = S + r (Jbar - S) + rm dJ and sigma~ = r dJ + rm Jbar with r = chi_s/chi_t, the
 // scattering share, and rm = cm/chi_t (safe for denormal far-wing opacities; cm = 0
-// wherever chi_s = 0).
+// wherever chi_s = 0).  Without scattering r = 0, so S+ is the line's S also where the line
+// opacity has underflowed to zero: the value does not jump where the profile underflows.
 template <bool ANISO>
 __device__ __forceinline__ NodeVal node_val(double cl, double cs, double cm, double S, double jp, double jm)
 {
@@ -223,7 +224,7 @@ __device__ __forceinline__ NodeVal node_val(double cl, double cs, double cm, dou
     ic = fma(ic, fma(-v.chit, ic, 1.0), ic);
     ic = cs > 0.0 ? ic : 0.0;   // chit >= cs > 0
     const double r = cs * ic;
-    v.Sp = v.chit > 0.0 ? fma(0.5 * r, jp + jm, fma(-r, S, S)) : 0.0;
+    v.Sp = fma(0.5 * r, jp + jm, fma(-r, S, S));
     v.sq = (0.5 * kISq2 * r) * (jm - jp);
     if (ANISO) {
         const double rm = cm * ic;
@@ -244,7 +245,7 @@ __device__ __forceinline__ NodeVal node_val_lin(double chit, double cs, double S
     ic = fma(ic, fma(-chit, ic, 1.0), ic);
     ic = cs > 0.0 ? ic : 0.0;
     const double r = cs * ic;
-    v.Sp = chit > 0.0 ? fma(r, D, S) : 0.0;
+    v.Sp = fma(r, D, S);
     v.sq = r * Q;
     return v;
 }
@@ -620,9 +621,10 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                     // no line opacity anywhere in the segment: each sub-node is the scattering
                     // term alone, S+ = Jbar and sigma~ = dJ (sqrt 2 sq), linear in the sub-node
                     // index like Jw and chi_s (r = 1 wherever chi_s > 0: at every sub-node when
-                    // either end has scattering, linear interpolation keeping it positive)
+                    // either end has scattering, linear interpolation keeping it positive);
+                    // without scattering at either end, S+ = S (no opacity, r = 0) and sigma~ = 0
                     const double on = (cs_cur > 0.0 || nd[i + 1].cs[gs] > 0.0) ? 1.0 : 0.0;
-                    const double Sp0 = (0.5 * on) * (ap + am), dSp = (0.5 * on * im) * (dap + dam);
+                    const double Sp0 = on > 0.0 ? 0.5 * (ap + am) : S_cur, dSp = on > 0.0 ? (0.5 * im) * (dap + dam) : dS;
                     const double sq0 = (0.5 * kISq2 * on) * (am - ap), dsq = (0.5 * kISq2 * on * im) * (dam - dap);
                     // the sub-interval ending at sub-node j has P = (chi_{j-1} + chi_j) hz, linear in j
                     const double dP = 2.0 * dcs * hz, P0 = (2.0 * cs_cur - dcs) * hz;

@@ -52,6 +52,52 @@ def test_scat_formal_solve_matches_oracle(nq):
     _check(s.formal_solve_scat(pops, Jnu), ref)
 
 
+def _segment_paths(o, w):
+    """Counts of the sub-step segments that the isotropic kernel steps by its linear forms:
+    far-wing segments (every offset beyond |y|^2 = 750 on one side at both ends) with at
+    least four sub-steps, and segments whose lookups all clamp (every offset beyond the
+    quadrature on one side at both ends) but that are not far-wing, with at least three."""
+    x = np.asarray(w.quad_x)
+    lo, hi = x.min(), x.max()
+    vw = o.line_width_speed()
+    vel, rays = w.model.vel, np.asarray(w.rays)
+    far4 = clamp3 = 0
+    for O in range(w.n_points):
+        for r in range(len(rays)):
+            cells, _ = o.walk(O, r)
+            if len(cells) == 0:
+                continue
+            nodes = np.concatenate(([O], cells))
+            s_ = (vel[nodes] - vel[O]) @ rays[r]
+            y = (vw[O] / vw[nodes])[:, None] * x[None, :] - (s_ / vw[nodes])[:, None]
+            ds = np.abs(np.diff(s_))
+            thr = 0.25 * np.minimum(vw[nodes][:-1], vw[nodes][1:])
+            m = np.where(ds > thr, np.ceil(ds / thr), 1)
+            a, b = y[:-1], y[1:]
+            clamp = np.all(((a >= hi) & (b >= hi)) | ((a <= lo) & (b <= lo)), axis=1)
+            far = clamp & np.all((np.sign(a) == np.sign(b)) & (a * a > 750.0) & (b * b > 750.0), axis=1)
+            far4 += int(np.sum(far & (m >= 4)))
+            clamp3 += int(np.sum(clamp & ~far & (m >= 3)))
+    return far4, clamp3
+
+
+def test_scat_linear_segment_forms_match_oracle():
+    """The isotropic kernel's linear forms (far-wing and clamped-lookup segments) on an
+    outflow that has both, with no scattering opacity in about 30% of the cells (the forms'
+    zero-opacity cases: no scattering term at a node, or at one end of a segment only),
+    against the oracle."""
+    w = configs.outflow5(n_points=300, seed=12, nside=1)
+    o = oracle_for(w)
+    far4, clamp3 = _segment_paths(o, w)
+    assert far4 > 100 and clamp3 > 100, (far4, clamp3)
+    pops, chi_sca, Jnu = _fields(o, w, 31)
+    chi_sca *= np.random.default_rng(32).uniform(size=w.n_points)[:, None] > 0.3
+    ref = o.formal_solve_scat(pops, chi_sca, Jnu)
+    s = solver_for(w)
+    s.set_scattering(chi_sca)
+    _check(s.formal_solve_scat(pops, Jnu), ref)
+
+
 def test_scat_formal_solve_static_sphere_matches_oracle():
     w = configs.sphere2(n_points=400, seed=7)
     o = oracle_for(w)

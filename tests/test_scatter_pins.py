@@ -42,6 +42,41 @@ def test_zero_scattering_opacity_gives_the_line_formal_solve(oracle_lib):
     assert rel(J, J0).max() < 1e-12 and rel(E, E0).max() < 1e-12 and rel(L, L0).max() < 1e-12
 
 
+def test_zero_scattering_opacity_per_frequency_field(oracle_lib):
+    """Without scattering every node's source is the line's S, also where the line opacity
+    is denormal or zero (far wings): J_nu out of the scattering solve against the same
+    field assembled pair by pair and frequency by frequency from the pair nodes, with
+    S+ = S and sigma = 0 at every node (the line solve's rows; the generalised ray solve
+    without sigma is pinned to the line solve above), and the per-frequency output formed
+    from u + v and u - v of the two directions."""
+    w = configs.outflow5(n_points=120, seed=2, nside=1)
+    o = oracle_lib.from_workload(w)
+    pops = o.lte() * np.random.default_rng(6).uniform(0.7, 1.3, (w.n_points, w.species.n_lev))
+    Jnu = o.scattering_start() * np.random.default_rng(7).uniform(0.5, 2.0, (o.P, o.n_lines, o.n_q))
+    sel = np.arange(3, 120, 13)
+    _, _, _, Jo = o.formal_solve_scat(pops, np.zeros((o.P, o.n_lines)), Jnu, sel=sel)
+    x = np.asarray(w.quad_x)
+    nu = o.line_frequencies()
+    denormal = 0
+    for k, O in enumerate(sel):
+        Jp = np.zeros((o.n_lines, o.n_q))
+        Jm = np.zeros((o.n_lines, o.n_q))
+        for p in range(o.n_pairs):
+            nd = o.pair_nodes(pops, O, p)
+            for l in range(o.n_lines):
+                Ib = oracle_lib.planck(nu[l], 2.725)
+                for n in range(o.n_q):
+                    y = nd["a"] * x[n] - nd["b"]
+                    chi = nd["kappa"][:, l] * np.exp(-y * y)
+                    denormal += int(np.sum((chi > 0) & (chi < 2.2250738585072014e-308)))
+                    u, _, _, v = oracle_lib.solve_ray_gen(nd["z"], chi, nd["S"][:, l], np.zeros(len(y)), Ib, Ib, nd["o"])
+                    Jp[l, n] += u + v
+                    Jm[l, n] += u - v
+        ref = (Jp + Jm[:, ::-1]) / o.n_rays
+        assert rel(Jo[k], ref).max() < 1e-12
+    assert denormal > 0
+
+
 # ---------------------------------------------------------------- invariants
 
 
@@ -64,6 +99,26 @@ def test_thermal_equilibrium_with_scattering(oracle_lib, moving):
     assert np.abs(Jnu / B - 1).max() < 1e-12 and np.abs(J / B - 1).max() < 1e-12
     new, flags = o.stateq(pops, J, E, L)
     assert np.all(flags == 0) and rel(new, pops).max() < 1e-12
+
+
+def test_thermal_equilibrium_with_scattering_in_part_of_the_points(oracle_lib):
+    """T_gas = T_CMB on the outflow, whose far wings reach denormal and zero line opacities,
+    with no scattering opacity in about 30% of the points: u = B still solves every pair at
+    every frequency, so J_nu = J = B.  This needs S+ = S at the nodes without scattering
+    whatever their line opacity: an S+ formed as chi_line S / chi_tot is 0 where
+    chi_line S underflows, and so is one that is 0 at nodes without opacity."""
+    w = configs.outflow5(n_points=150, seed=8, nside=1)
+    w.model.temperature[:] = 2.725
+    o = oracle_lib.from_workload(w)
+    pops = o.lte()
+    rng = np.random.default_rng(9)
+    nd = o.pair_nodes(pops, 0, 0)
+    chi_sca = nd["kappa"][nd["o"]][None, :] * rng.uniform(0.1, 10.0, (o.P, o.n_lines))
+    chi_sca *= rng.uniform(size=(o.P, 1)) > 0.3
+    nu = o.line_frequencies()
+    B = np.array([planck(f, 2.725) for f in nu])
+    J, E, L, Jnu = o.formal_solve_scat(pops, chi_sca, o.scattering_start())
+    assert np.abs(Jnu / B[None, :, None] - 1).max() < 1e-12 and np.abs(J / B[None, :] - 1).max() < 1e-12
 
 
 # ---------------------------------------------------------------- per-direction intensities
