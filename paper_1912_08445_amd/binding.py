@@ -232,10 +232,10 @@ class Solver:
         up, lo, A = _c(sp.line_up, np.int32), _c(sp.line_lo, np.int32), _c(sp.line_A, np.float64)
         cu, cl = _c(sp.coll_up, np.int32), _c(sp.coll_lo, np.int32)
         T, K = _c(sp.coll_T, np.float64), _c(sp.coll_K, np.float64)
-        self.n_lev, self.n_lines = sp.n_lev, sp.n_lines
         self._chk(self.L.nlte_set_species(self.h, sp.n_lev, _p(E), _p(g), float(sp.mass), sp.n_lines,
                                           _p(up), _p(lo), _p(A), int(cu.shape[0]), _p(cu), _p(cl),
                                           int(T.shape[0]), _p(T), _p(K)))
+        self.n_lev, self.n_lines = sp.n_lev, sp.n_lines
 
     def set_models(self, model, offsets=None):
         P = model.n_points
@@ -245,20 +245,21 @@ class Solver:
                 _c(model.abundance, np.float64)]
         nbr = _c(model.nbr, np.int32)
         bnd = None if model.boundary is None else _c(model.boundary, np.uint8)
+        self._chk(self.L.nlte_set_models(self.h, off.shape[0] - 1, _p(off), *[_p(a) for a in arrs],
+                                         int(nbr.shape[1]), _p(nbr), _p(bnd)))
+        # (recorded only once the library has taken the models: a rejected set leaves both)
         self.P = P
         self.n_models = off.shape[0] - 1
-        self._chk(self.L.nlte_set_models(self.h, self.n_models, _p(off), *[_p(a) for a in arrs],
-                                         int(nbr.shape[1]), _p(nbr), _p(bnd)))
 
     def set_rays(self, dirs):
         d = _c(dirs, np.float64)
-        self.n_rays = d.shape[0]
         self._chk(self.L.nlte_set_rays(self.h, d.shape[0], _p(d)))
+        self.n_rays = d.shape[0]
 
     def set_quadrature(self, x, w):
         x, w = _c(x, np.float64), _c(w, np.float64)
-        self.n_q = x.shape[0]
         self._chk(self.L.nlte_set_quadrature(self.h, x.shape[0], _p(x), _p(w)))
+        self.n_q = x.shape[0]
 
     def set_params(self, **kw):
         for k, v in kw.items():

@@ -287,7 +287,13 @@ def test_error_codes():
     with pytest.raises(binding.NlteError) as e:
         s.set_models(bad)
     assert e.value.code == binding.NLTE_E_INVALID_ARG
+    # an empty model in a batch, and decreasing model offsets
+    for offs in ([0, 100, 100, 200], [0, 150, 100, 200]):
+        with pytest.raises(binding.NlteError) as e:
+            s.set_models(w.model, offsets=offs)
+        assert e.value.code == binding.NLTE_E_INVALID_ARG
     s.set_models(w.model)
+    assert s.P == 200 and s.n_models == 1
     with pytest.raises(binding.NlteError) as e:
         s.set_rays(np.array([[1.0, 0, 0], [0, 1.0, 0]]))
     assert e.value.code == binding.NLTE_E_INVALID_ARG
