@@ -662,7 +662,8 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
                         if (m > 3) {
                             // from sub-node 3 on both neighbours of the eliminated sub-node lie on
                             // the line: the sigma~ and S+ differences across it are the constants
-                            // -2 dsq and -2 dSp, and P_{j-1} + P_j grows by 2 dP per sub-node
+                            // -2 dsq and -2 dSp (the v-equation takes half the latter, cv), and
+                            // P_{j-1} + P_j grows by 2 dP per sub-node
                             double n = h.n, d = h.d, y = h.y, yv = h.yv, Sh = h.Sp, qh = h.sq;
                             const double cy = -2.0 * dsq, cv = -dSp, dQ = 2.0 * dP, Q0 = fma(2.0, P0, -dP);
                             double fj = 3.0;
