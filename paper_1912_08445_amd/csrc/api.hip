@@ -172,9 +172,15 @@ void set_launch_shape(nlte_ctx *c, SolveArgs &a, bool fp32)
     // long-segment mode (profile recurrence, far-wing collapse) where sub-step segments are
     // long: more than two elimination steps per cached cell on average
     a.collapse = c->cfg.long_seg >= 0 ? c->cfg.long_seg : (c->total_steps > 2 * c->total_cells ? 1 : 0);
-    // the most staged nodes whose LDS keeps the register budget's occupancy (160 KiB per CU)
+    // the most staged nodes whose LDS keeps the register budget's occupancy (160 KiB per CU):
+    // dynamic and static bytes in the units the hardware allocates (counted without them, the
+    // disc's FP32 form took 48 nodes and lost one wave per CU to the rounding: 3.40 s per
+    // sweep against 3.26 s at 40)
     const size_t budget = (size_t)160 * 1024 / (size_t)(4 * a.waves);
-    auto lds = [&](int n) { return fp32 ? formal_solve_lds_f32(lpl, n) : formal_solve_lds_f64(lpl, n); };
+    auto lds = [&](int n) {
+        const size_t b = (fp32 ? formal_solve_lds_f32(lpl, n) : formal_solve_lds_f64(lpl, n)) + kFsStaticLds;
+        return (b + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+    };
     int ns = kWave;
     while (ns > 16 && lds(ns) > budget) ns -= 8;
     if (c->cfg.ns >= 2 && c->cfg.ns <= kWave) ns = c->cfg.ns;

@@ -394,6 +394,10 @@ hipError_t launch_formal_solve_f32(const SolveArgs &a, const SolveConfig &cfg, h
 // dynamic LDS bytes of one formal-solve workgroup with lpl lines per lane and ns staged nodes
 size_t formal_solve_lds_f64(int lpl, int ns);
 size_t formal_solve_lds_f32(int lpl, int ns);
+// the formal-solve kernel's static LDS (its exponential table and work-queue slot, 136 bytes)
+// rounded up, and the unit in which the hardware allocates a workgroup's LDS
+constexpr size_t kFsStaticLds = 256;
+constexpr size_t kLdsGranule = 512;
 hipError_t launch_formal_solve_band(const SolveArgs &a, hipStream_t s);
 hipError_t launch_count_steps(const SolveArgs &a, int64_t *steps, unsigned long long *point_cost,
                               hipStream_t s);
