@@ -738,10 +738,12 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
 
 }  // namespace
 
-// The isotropic form on an evenly spaced quadrature is held to two waves per SIMD (it then
-// needs no spill; at three it spills and runs slower); the others fit one.
+// The forms on an evenly spaced quadrature are held to two waves per SIMD: the isotropic one
+// then needs no spill (at three it spills and runs slower), the one with a dipole spills 45
+// VGPRs and still runs a third faster than at one wave (outflow5 sweep 336 -> 225 ms); the
+// forms for other quadratures fit one.
 template <bool UNI, bool ANISO>
-__global__ __launch_bounds__(kScatMaxQ, (UNI && !ANISO) ? 2 : 1) void k_formal_solve_scat(ScatArgs a)
+__global__ __launch_bounds__(kScatMaxQ, UNI ? 2 : 1) void k_formal_solve_scat(ScatArgs a)
 {
     extern __shared__ double smem[];
     // lanes: with n_q <= 32 two lines per wave (lanes 32 g + frequency), else one line
