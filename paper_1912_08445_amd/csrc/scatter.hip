@@ -738,12 +738,12 @@ __device__ void half(const ScatArgs &a, const QGeo &qg, const double *tab, SNode
 
 }  // namespace
 
-// The forms on an evenly spaced quadrature are held to two waves per SIMD: the isotropic one
-// then needs no spill (at three it spills and runs slower), the one with a dipole spills 45
-// VGPRs and still runs a third faster than at one wave (outflow5 sweep 336 -> 225 ms); the
-// forms for other quadratures fit one.
+// Every form is held to two waves per SIMD: the isotropic one on an evenly spaced quadrature
+// then needs no spill (at three it spills and runs slower); the others spill (45 to 83 VGPRs)
+// and still run a third or more faster than at one wave (outflow5 sweeps: with a dipole
+// 336 -> 225 ms; on 24 Gauss-Hermite offsets 491 -> 275 ms, with a dipole 567 -> 346 ms).
 template <bool UNI, bool ANISO>
-__global__ __launch_bounds__(kScatMaxQ, UNI ? 2 : 1) void k_formal_solve_scat(ScatArgs a)
+__global__ __launch_bounds__(kScatMaxQ, 2) void k_formal_solve_scat(ScatArgs a)
 {
     extern __shared__ double smem[];
     // lanes: with n_q <= 32 two lines per wave (lanes 32 g + frequency), else one line
